@@ -1,0 +1,295 @@
+"""Benchmark: state-vector hot path on one MI355X.
+
+Headline workload (one "step"): the gate-based QFT (H, controlled phases,
+final swaps; 420 logical gates) applied to a resident 28-qubit complex64
+state with i.i.d. complex Gaussian amplitudes (seed 2).  Metric: amplitude
+updates per second = logical gates x 2^n per step / time.
+
+Extras in the same JSON line (each bounded in time):
+  qft        20/24/28 qubits at complex64 and complex128, fused and one
+             launch per gate, GB/s per pass
+  grad10     10-qubit complex128 VQE gradient (161 circuits): batched vs one
+             circuit at a time
+  grad20     20-qubit complex64 gradient, 8 layers (641 circuits), 200-term
+             random 2-local Hamiltonian: batched vs one circuit at a time
+  deep30     30-qubit complex64 depth-40 U3 + CZ circuit: fused vs unfused
+  serving    Poisson stream of mixed requests through the serving queue
+             (bounded sample), p50/p99 latency vs a serial loop
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def qft_gates(n):
+    return n + n * (n - 1) // 2 + n // 2
+
+
+def time_qft(ctx, sv, n, dtype, steps, warmup, flags=0, psi=None, profile=False):
+    st = ctx.alloc(n, dtype)
+    if psi is not None:
+        st.set_amplitudes(psi)
+    for _ in range(warmup):
+        st.qft(flags)
+    ctx.synchronize()
+    if profile:
+        ctx.profile_reset()
+        ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.qft(flags)
+    ctx.synchronize()
+    dt = time.perf_counter() - t0
+    prof = {}
+    if profile:
+        for name in ("tile", "perm"):
+            prof[name] = ctx.profile_get(name)
+        ctx.profile(False)
+        ctx.profile_reset()
+    return st, dt, prof
+
+
+def bench_qft_headline(ctx, sv, inputs, args):
+    n = 28
+    log(f"[bench] headline: QFT n={n} complex64, generating input")
+    psi = inputs.gaussian_state(n, 2).astype(np.complex64)
+    st, dt, prof = time_qft(ctx, sv, n, sv.C64, args.steps, args.warmup, psi=psi, profile=True)
+    del psi
+    G = qft_gates(n)
+    au = G * float(1 << n) * args.steps
+    S = 8.0 * (1 << n)
+    tile_ms, tile_n, tile_bytes = prof["tile"]
+    perm_ms, perm_n, _ = prof["perm"]
+    avg_tile_s = tile_ms / 1e3 / max(tile_n, 1)
+    achieved = (2.0 * S) / avg_tile_s / 1e9
+    st.free()
+    return {
+        "value": au / dt, "ms_per_step": dt / args.steps * 1e3, "n": n, "gates": G,
+        "passes_per_step": (tile_n + perm_n) / args.steps,
+        "tile_avg_ms": tile_ms / max(tile_n, 1), "perm_avg_ms": perm_ms / max(perm_n, 1),
+        "tile_launches": tile_n, "achieved_gbs": achieved, "S": S,
+        "pass_gbs": 2.0 * S * (tile_n + perm_n) / (dt) / 1e9,
+    }
+
+
+def bench_qft_table(ctx, sv, inputs, oracle_mod):
+    out = {}
+    for n in (20, 24, 28):
+        for dtype, name in ((sv.C64, "c64"), (sv.C128, "c128")):
+            psi = inputs.gaussian_state(n, 2) if n <= 24 else None
+            st = ctx.alloc(n, dtype)
+            if psi is not None:
+                st.set_amplitudes(psi)
+                st.qft()
+                got = st.get_amplitudes().astype(np.complex128)
+                ref = math.sqrt(1 << n) * np.fft.ifft(psi)
+                rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            else:
+                rel = None
+            st.free()
+            reps = 3 if n <= 24 else 2
+            st, dt, prof = time_qft(ctx, sv, n, dtype, reps, 1, profile=True)
+            st.free()
+            amp = 8 if dtype == sv.C64 else 16
+            S = float(amp << n)
+            G = qft_gates(n)
+            tile_ms, tile_n, _ = prof["tile"]
+            perm_ms, perm_n, _ = prof["perm"]
+            passes = (tile_n + perm_n) / reps
+            rec = {"au_per_s": G * float(1 << n) * reps / dt, "ms": dt / reps * 1e3,
+                   "passes": passes,
+                   "gbs_per_pass": 2 * S * (tile_n + perm_n) / ((tile_ms + perm_ms) / 1e3) / 1e9
+                   if tile_n + perm_n else None,
+                   "rel_l2_vs_inverse_dft": rel}
+            if n <= 24:
+                # one launch per gate: GB/s per gate sweep
+                st, dt1, _ = time_qft(ctx, sv, n, dtype, 1, 0, flags=sv.FLAG_UNFUSED)
+                st.free()
+                rec["unfused_ms"] = dt1 * 1e3
+                rec["unfused_au_per_s"] = G * float(1 << n) / dt1
+            out[f"n{n}_{name}"] = rec
+            log(f"[bench] qft n={n} {name}: {rec['ms']:.3f} ms, {rec['au_per_s']:.3e} AU/s")
+    return out
+
+
+def bench_grad(ctx, sv, inputs, n, layers, dtype, ham, reps, seq_reps=1, seq_flags=None):
+    c = inputs.hea_circuit(n, layers)
+    params = inputs.uniform_params(c.n_params, 1 if n == 10 else 3)
+    circuits = 2 * c.n_params + 1
+    ctx.param_shift_grad(c, params, ham, dtype)  # warm-up
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        e, g = ctx.param_shift_grad(c, params, ham, dtype)
+    dt = (time.perf_counter() - t0) / reps
+    rec = {"n": n, "params": c.n_params, "circuits": circuits, "gates_per_circuit": c.n_gates,
+           "batched_ms": dt * 1e3, "batched_grads_per_s": 1.0 / dt,
+           "au_per_s": circuits * c.n_gates * float(1 << n) / dt}
+    for name, fl in (seq_flags or {}).items():
+        t0 = time.perf_counter()
+        for _ in range(seq_reps):
+            e2, g2 = ctx.param_shift_grad(c, params, ham, dtype, fl)
+        dts = (time.perf_counter() - t0) / seq_reps
+        rec[f"{name}_ms"] = dts * 1e3
+        rec[f"{name}_grads_per_s"] = 1.0 / dts
+        rec[f"{name}_max_abs_diff_vs_batched"] = float(np.max(np.abs(g2 - g)))
+    rec["energy"] = e
+    return rec, (c, params, e, g)
+
+
+def bench_deep30(ctx, sv, inputs, n=30, depth=40):
+    c = inputs.deep_random_circuit(n, depth, 4)
+    rec = {"n": n, "depth": depth, "gates": c.n_gates}
+    st = ctx.alloc(n, sv.C64)
+    for name, fl in (("fused", 0), ("unfused", sv.FLAG_UNFUSED)):
+        st.reset()
+        ctx.synchronize()
+        ctx.profile_reset()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        st.apply(c, None, fl)
+        ctx.synchronize()
+        dt = time.perf_counter() - t0
+        names = ["tile", "perm"] if fl == 0 else ["sweep_u1", "sweep_phase", "sweep_xperm", "sweep_diag",
+                                                  "sweep_u2", "sweep_swap", "sweep_ladder"]
+        ms = nl = by = 0.0
+        for k in names:
+            a, b, cb = ctx.profile_get(k)
+            ms += a
+            nl += b
+            by += cb
+        ctx.profile(False)
+        rec[name] = {"ms": dt * 1e3, "au_per_s": c.n_gates * float(1 << n) / dt, "launches": int(nl),
+                     "kernel_ms": ms, "algorithmic_gbs": by / (ms / 1e3) / 1e9 if ms else None,
+                     "norm2_minus_1": st.norm2() - 1.0}
+        log(f"[bench] deep30 {name}: {dt*1e3:.1f} ms")
+    st.free()
+    return rec
+
+
+def bench_serving(ctx, sv, inputs, count, seed=5):
+    # serial baseline rate first (same request list, one at a time, plain path)
+    reqs = inputs.serving_requests(count, seed, rate_per_s=0.0, n_range=(8, 20), depth_range=(2, 6))
+    t0 = time.perf_counter()
+    for r in reqs[: max(4, count // 8)]:
+        if r.grad:
+            ctx.param_shift_grad(r.circuit, r.params, r.hamiltonian, sv.C64, sv.FLAG_SEQUENTIAL)
+        else:
+            ctx.param_shift_grad(r.circuit, r.params[:0] if False else r.params, r.hamiltonian, sv.C64,
+                                 sv.FLAG_SEQUENTIAL)
+    serial_dt = (time.perf_counter() - t0) / max(4, count // 8)
+    mu = 1.0 / serial_dt
+    out = {"requests": count, "serial_req_per_s": mu, "n_range": [8, 20], "depth_range": [2, 6]}
+    for load in (0.8, 2.0):
+        lam = load * mu
+        reqs = inputs.serving_requests(count, seed, rate_per_s=lam, n_range=(8, 20), depth_range=(2, 6))
+        q = ctx.queue(64 << 30)
+        tickets = []
+        t_start = time.perf_counter()
+        for r in reqs:
+            now = time.perf_counter() - t_start
+            if r.arrival_s > now:
+                time.sleep(r.arrival_s - now)
+            p = r.params if r.grad else r.params
+            tickets.append(q.submit(r.circuit, p, r.hamiltonian, r.grad, sv.C64))
+        lat = []
+        for t in tickets:
+            _, _, l = q.wait(t)
+            lat.append(l)
+        total = time.perf_counter() - t_start
+        st = q.stats()
+        q.close()
+        lat = np.array(lat)
+        out[f"load_{load}"] = {"arrival_rate": lam, "req_per_s": count / total,
+                               "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                               "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                               "launches": st["launches"], "circuits": st["circuits_run"]}
+        log(f"[bench] serving load {load}: p50 {out[f'load_{load}']['p50_ms']:.1f} ms")
+    return out
+
+
+def cpu_baseline(oracle_mod, inputs):
+    n = 24
+    psi = inputs.gaussian_state(n, 2)
+    t0 = time.perf_counter()
+    oracle_mod.qft(psi)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": qft_gates(n) * float(1 << n) / dt, "unit": "amplitude-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"FP64 oracle gate-by-gate QFT on one {n}-qubit Gaussian state "
+                      f"({qft_gates(n)} gates, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--quick", action="store_true", help="headline only")
+    ap.add_argument("--serving", type=int, default=48, help="serving sample size (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(this build runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+    import oracle
+    from paper_2512_23183_amd import inputs
+    from paper_2512_23183_amd import sv
+
+    ctx = sv.Context(0)
+    head = bench_qft_headline(ctx, sv, inputs, args)
+    extras = {}
+    if not args.quick:
+        extras["qft"] = bench_qft_table(ctx, sv, inputs, oracle)
+        rec10, _ = bench_grad(ctx, sv, inputs, 10, 4, sv.C128, inputs.xyz_chain(10), 20, 3,
+                              {"sequential": sv.FLAG_SEQUENTIAL,
+                               "sequential_unfused": sv.FLAG_SEQUENTIAL | sv.FLAG_UNFUSED})
+        extras["grad10_c128"] = rec10
+        log(f"[bench] grad10: {rec10['batched_ms']:.2f} ms")
+        rec20, _ = bench_grad(ctx, sv, inputs, 20, 8, sv.C64, inputs.random_2local(20, 200, 3), 1, 1,
+                              {"sequential": sv.FLAG_SEQUENTIAL})
+        extras["grad20_c64"] = rec20
+        log(f"[bench] grad20: {rec20['batched_ms']:.2f} ms")
+        extras["deep30_c64"] = bench_deep30(ctx, sv, inputs)
+        if args.serving > 0:
+            extras["serving"] = bench_serving(ctx, sv, inputs, args.serving)
+    cpu = cpu_baseline(oracle, inputs) if rank == 0 else None
+    ctx.close()
+    frac = head["achieved_gbs"] / HBM_PEAK_GBS
+    line = {
+        "metric": "amplitude-updates/s", "value": head["value"], "unit": "amplitude-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "qft_gate_based_n28_complex64", "n_qubits": 28, "logical_gates": head["gates"],
+                   "input": "iid complex Gaussian, normalised (seed 2)",
+                   "passes_per_step": head["passes_per_step"]},
+        "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": frac, "traffic": None, "kernel": "k_tile (fused LDS tile pass)",
+                     "bytes_per_launch": 2 * head["S"], "avg_launch_ms": head["tile_avg_ms"]},
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    if rank == 0:
+        print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,312 @@
+/*
+ * sv.h -- C ABI of libsv.so, an MI355X (gfx950) state-vector simulator for
+ * the gate / expectation / parameter-shift hot path of LogosQ
+ * (arxiv 2512.23183).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an sv_status (0 = SV_OK, negative = error).  No
+ *    C++ exception, abort or HIP error escapes the ABI.  On error a
+ *    human-readable message is available from sv_last_error() (thread-local;
+ *    valid until the next sv_* call on the same thread).
+ *  - All arguments are validated on the host BEFORE any device work is
+ *    enqueued; an invalid argument returns SV_EINVAL and leaves device state
+ *    untouched.  The paper's unchecked insertion path (Sec. "Circuit Data
+ *    Structure", add_operation_unchecked) is deliberately not mirrored.
+ *  - Input arrays (gates, matrices, parameters, Pauli strings, host
+ *    amplitudes) are borrowed for the duration of the call only; the library
+ *    copies what it keeps.  Outputs are written to caller-owned buffers.
+ *  - States are owned by the library (sv_alloc .. sv_free), except states
+ *    made by sv_wrap, whose device memory stays owned by the caller.
+ *  - Qubit q corresponds to amplitude-index bit n-1-q ("MSB-first"; Alg.
+ *    "Direct State Vector CNOT" and the worked examples of App. A and B).
+ *    Amplitudes are interleaved (re, im) pairs: float for SV_C64, double for
+ *    SV_C128.
+ *  - A non-finite energy or gradient is reported as SV_ENUMERIC, never
+ *    returned silently (App. D: explicit error reporting instead of silent
+ *    NaN or empty gradients).
+ *  - Device work runs on the context's stream (sv_set_stream); calls that
+ *    return host results synchronise that stream before returning.
+ */
+#ifndef SV_ABI_H_INCLUDED
+#define SV_ABI_H_INCLUDED
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SV_OK = 0,
+    SV_EINVAL = -1,     /* invalid argument (nothing was enqueued)          */
+    SV_ENOMEM = -2,     /* device or host allocation failed                 */
+    SV_EDEVICE = -3,    /* a HIP call failed                                */
+    SV_EBUSY = -4,      /* request exceeds the queue's memory budget        */
+    SV_ENUMERIC = -5,   /* result not finite                                */
+    SV_ECANCELED = -6,  /* request was cancelled                            */
+    SV_ENODEV = -7,     /* no usable gfx950 device                          */
+    SV_ETIMEDOUT = -8   /* sv_queue_wait timed out (request still pending)  */
+} sv_status;
+
+/* Amplitude precision: complex64 = pair of float, complex128 = pair of double. */
+typedef enum { SV_C64 = 0, SV_C128 = 1 } sv_dtype;
+
+/*
+ * Gate kinds.  Angles are the gate's effective angles (see sv_gate).
+ *  H, X, Y, Z           fixed one-qubit gates (H as printed in App. C)
+ *  RX, RY, RZ (t)       exp(-i t P / 2) (generator form given with
+ *                       Eq. "parameter_shift"); RZ = diag(e^{-it/2}, e^{it/2})
+ *  U3 (t, p, l)         OpenQASM 2 U3 (not defined in the paper; the paper
+ *                       names OpenQASM as its circuit format)
+ *  CNOT (c, t)          Alg. "Direct State Vector CNOT"
+ *  CZ (a, b)            diag(1, 1, 1, -1)
+ *  CP (a, b; p)         diag(1, 1, 1, e^{ip}); the controlled phase of Alg.
+ *                       "Gate-Based QFT"
+ *  SWAP (a, b)          exchange of two qubits (Alg. "Gate-Based QFT")
+ *  CRX/CRY/CRZ (c, t; t) |0><0|_c x I + |1><1|_c x R_P(t)_t (App. D circuit)
+ *  CCX (c1, c2, t)      Toffoli, Alg. "Direct State Vector Toffoli" (App. B)
+ *  RXX/RYY/RZZ (a,b; t) exp(-i t/2 P x P), the Trotter two-qubit rotations
+ *                       of Sec. "XYZ Heisenberg Model"
+ *  MAT1 (q)             user 2x2 matrix (apply_single_qubit_matrix of
+ *                       Sec. "Circuit Data Structure")
+ *  MAT2 (a, b)          user 4x4 matrix (apply_two_qubit_matrix); the 4x4 row
+ *                       / column index is 2*bit(a) + bit(b)
+ */
+typedef enum {
+    SV_H = 0, SV_X = 1, SV_Y = 2, SV_Z = 3,
+    SV_RX = 4, SV_RY = 5, SV_RZ = 6, SV_U3 = 7,
+    SV_CNOT = 8, SV_CZ = 9, SV_CP = 10, SV_SWAP = 11,
+    SV_CRX = 12, SV_CRY = 13, SV_CRZ = 14, SV_CCX = 15,
+    SV_RXX = 16, SV_RYY = 17, SV_RZZ = 18,
+    SV_MAT1 = 19, SV_MAT2 = 20,
+    SV_NUM_GATE_KINDS = 21
+} sv_gate_kind;
+
+/*
+ * One gate occurrence (Sec. "Circuit Data Structure", Operation), 56 bytes.
+ *   kind        sv_gate_kind
+ *   q[3]        qubit operands, controls first; unused slots ignored
+ *   param_idx[3] for each angle slot: index into the parameter vector, or -1
+ *   mat_idx     MAT1 / MAT2: row of sv_circuit.mats; otherwise ignored
+ *   angle[3]    fixed angle (or offset) per slot
+ * Effective angle k = angle[k] + (param_idx[k] >= 0 ? params[param_idx[k]] : 0)
+ * -- the circuit-rebuilding model of Sec. "Circuit Rebuilding Architecture":
+ * every evaluation instantiates its gates from the parameter vector.
+ */
+typedef struct sv_gate {
+    int32_t kind;
+    int32_t q[3];
+    int32_t param_idx[3];
+    int32_t mat_idx;
+    double angle[3];
+} sv_gate;
+
+/*
+ * A gate list (Sec. "Circuit Data Structure", Circuit; Sec. "Compile-Time
+ * Type Safety", ParameterizedCircuit).
+ *   n_qubits   1..SV_MAX_QUBITS
+ *   n_params   length the parameter vector must have (the length assert of
+ *              build_circuit becomes an SV_EINVAL)
+ *   gates      n_gates records
+ *   mats       n_mats rows of 32 doubles: a row-major complex matrix as
+ *              (re, im) pairs; a 2x2 uses the first 8 doubles, a 4x4 all 32
+ */
+typedef struct sv_circuit {
+    int32_t n_qubits;
+    int32_t n_params;
+    const sv_gate *gates;
+    size_t n_gates;
+    const double *mats;
+    size_t n_mats;
+} sv_circuit;
+
+/*
+ * H = sum_t coeffs[t] P_t with P_t a Pauli string (VQE "Problem
+ * Formulation"; Eq. "xyz_hamiltonian" and Eq. "energy_expectation").
+ * paulis holds n_terms rows of n_qubits characters from "IXYZ"; character q
+ * of row t is the factor on qubit q.  No terminating NULs are needed.
+ */
+typedef struct sv_pauli_sum {
+    int32_t n_qubits;
+    size_t n_terms;
+    const double *coeffs;
+    const char *paulis;
+} sv_pauli_sum;
+
+#define SV_MAX_QUBITS 34       /* 2^34 complex128 = 256 GiB < 288 GB HBM  */
+#define SV_MAX_GATES (1u << 24)
+#define SV_MAX_TERMS (1u << 20)
+
+typedef struct sv_ctx sv_ctx;
+typedef struct sv_state sv_state;
+typedef struct sv_queue sv_queue;
+
+/* Execution options for sv_apply_circuit_ex / sv_param_shift_grad_ex. */
+enum {
+    SV_FLAG_UNFUSED = 1u << 0,    /* one kernel launch per gate (plain path) */
+    SV_FLAG_SEQUENTIAL = 1u << 1, /* gradient: one circuit at a time        */
+    SV_FLAG_PERGATE_BATCH = 1u << 2 /* gradient: one launch per pass over all
+                                       circuits instead of the persistent
+                                       work-queue kernel                     */
+};
+
+/*
+ * Context: one device, one stream, the planner's tuning cache and buffer
+ * pools.  device = HIP ordinal.  cfg may be NULL (defaults).  Returns
+ * SV_ENODEV if the device is missing or not gfx950.
+ */
+typedef struct sv_config {
+    int32_t tile_bits_c64;   /* LDS tile width for complex64, 0 = default */
+    int32_t tile_bits_c128;  /* LDS tile width for complex128, 0 = default */
+    int32_t reserved[6];
+} sv_config;
+
+int sv_init(sv_ctx **out, int device, const sv_config *cfg);
+int sv_shutdown(sv_ctx *ctx);
+
+/* Use the caller's HIP stream (e.g. PyTorch's current stream); NULL = the
+ * context's own stream. */
+int sv_set_stream(sv_ctx *ctx, void *hip_stream);
+/* Block until all work on the context's stream has finished. */
+int sv_synchronize(sv_ctx *ctx);
+
+/*
+ * State allocation: a contiguous 2^n amplitude vector in HBM initialised to
+ * |0...0> (Sec. "Dense State Vector Representation", zero_state: allocated
+ * once, no allocation during execution).
+ */
+int sv_alloc(sv_ctx *ctx, int n_qubits, int dtype, sv_state **out);
+/* Adopt caller-owned device memory of 2^n amplitudes (e.g. a torch tensor);
+ * the contents are left as they are. */
+int sv_wrap(sv_ctx *ctx, void *dev_ptr, int n_qubits, int dtype,
+            sv_state **out);
+int sv_free(sv_state *st);
+int sv_reset(sv_state *st);                     /* back to |0...0> */
+int sv_state_info(const sv_state *st, int *n_qubits, int *dtype,
+                  void **dev_ptr);
+/* Host <-> device copies of all 2^n amplitudes in the state's dtype. */
+int sv_set_amplitudes(sv_state *st, const void *host, size_t n_amps);
+int sv_get_amplitudes(sv_state *st, void *host, size_t n_amps);
+
+/*
+ * Apply a gate list to the state: psi <- U_L ... U_1 psi (Sec. "Circuit
+ * Data Structure", execute; gates by Sec. "Direct State Vector Gates").
+ * The default path plans fused passes (LDS tiles, in-register runs,
+ * diagonal gates folded in); SV_FLAG_UNFUSED applies one gate per launch.
+ * params must hold circuit->n_params finite values.
+ */
+int sv_apply_circuit(sv_state *st, const sv_circuit *circuit,
+                     const double *params, size_t n_params);
+int sv_apply_circuit_ex(sv_state *st, const sv_circuit *circuit,
+                        const double *params, size_t n_params, uint32_t flags);
+
+/*
+ * Quantum Fourier transform as the gate list of Alg. "Gate-Based QFT"
+ * (H, controlled phases CP(pi/2^(j-i)), final swaps) run through the same
+ * executor; equals sqrt(N) times the inverse DFT of the amplitudes
+ * (Sec. "Quantum Fourier Transform Optimizations").
+ */
+int sv_qft(sv_state *st);
+int sv_qft_ex(sv_state *st, uint32_t flags);
+
+/* sum_k |psi_k|^2 in FP64, and scaling of psi to unit norm. */
+int sv_norm2(sv_state *st, double *out);
+int sv_normalize(sv_state *st);
+
+/*
+ * Energy E = sum_t c_t <psi|P_t|psi> / <psi|psi>, every product and sum in
+ * FP64 (two-stage deterministic reduction; the division is the FP64
+ * renormalisation).  term_values (nullable, n_terms doubles) receives each
+ * <P_t> / <psi|psi>.  ham->n_qubits must equal the state's.
+ */
+int sv_expectation(sv_state *st, const sv_pauli_sum *ham, double *energy,
+                   double *term_values);
+
+/*
+ * Parameter-shift gradient (Eq. "parameter_shift", s = pi/2; ParameterShift
+ * of Sec. "Circuit Rebuilding Architecture"): every evaluation starts from a
+ * fresh |0...0>.  Computes f(theta) into *energy and df/dtheta_i into
+ * grad[0..n_params-1].  Rules per gate occurrence of parameter i (summed
+ * over occurrences): two-term (s = pi/2) for RX/RY/RZ/U3/CP/RXX/RYY/RZZ;
+ * four-term (shifts pi/2, 3pi/2) for CRX/CRY/CRZ.  All 1 + sum(shifts)
+ * circuits run batched (one persistent launch) unless flags say otherwise;
+ * the differences are taken in FP64 on the device.
+ */
+int sv_param_shift_grad(sv_ctx *ctx, int dtype, const sv_circuit *circuit,
+                        const double *params, size_t n_params,
+                        const sv_pauli_sum *ham, double *energy,
+                        double *grad);
+int sv_param_shift_grad_ex(sv_ctx *ctx, int dtype, const sv_circuit *circuit,
+                           const double *params, size_t n_params,
+                           const sv_pauli_sum *ham, uint32_t flags,
+                           double *energy, double *grad);
+
+/*
+ * Energies of many independent circuits of possibly different qubit counts
+ * in one batched launch, each from |0...0>: energies[i] =
+ * <psi_i|H_i|psi_i> for circuits[i], params[i], hams[i].
+ */
+int sv_batch_energies(sv_ctx *ctx, int dtype, size_t n_circuits,
+                      const sv_circuit *circuits, const double *const *params,
+                      const sv_pauli_sum *hams, double *energies);
+
+/*
+ * Serving queue: continuous batching of energy / gradient requests of mixed
+ * qubit counts.  A scheduler thread admits requests while their state
+ * slots fit in hbm_budget_bytes, runs every admitted circuit in shared
+ * batched launches, and admits new work as slots free up.
+ */
+typedef struct sv_request {
+    int32_t want_grad;        /* 0 = energy only, 1 = energy + gradient */
+    int32_t dtype;            /* sv_dtype */
+    sv_circuit circuit;
+    const double *params;
+    size_t n_params;
+    sv_pauli_sum ham;
+} sv_request;
+
+typedef struct sv_queue_stats {
+    uint64_t submitted, completed, failed, cancelled;
+    uint64_t launches;         /* batched launches issued by the scheduler */
+    uint64_t circuits_run;
+    uint64_t peak_bytes;       /* largest resident footprint seen */
+} sv_queue_stats;
+
+int sv_queue_create(sv_ctx *ctx, size_t hbm_budget_bytes, sv_queue **out);
+/* Copies the request; SV_EBUSY if one request alone exceeds the budget. */
+int sv_queue_submit(sv_queue *q, const sv_request *req, uint64_t *ticket);
+/* Wait up to timeout_ms (< 0 = forever).  grad may be NULL for energy-only
+ * requests; grad_len must be >= the request's n_params otherwise.  The
+ * ticket is released once a final status (OK or error) is returned. */
+int sv_queue_wait(sv_queue *q, uint64_t ticket, int timeout_ms,
+                  double *energy, double *grad, size_t grad_len);
+/* As sv_queue_wait; latency_s (nullable) receives the time from submission
+ * to completion measured by the scheduler (steady clock). */
+int sv_queue_wait_timed(sv_queue *q, uint64_t ticket, int timeout_ms,
+                        double *energy, double *grad, size_t grad_len,
+                        double *latency_s);
+int sv_queue_cancel(sv_queue *q, uint64_t ticket);
+int sv_queue_get_stats(sv_queue *q, sv_queue_stats *out);
+int sv_queue_destroy(sv_queue *q);
+
+/* Host-only validation used by every entry point (no device needed). */
+int sv_check_circuit(const sv_circuit *circuit, const double *params,
+                     size_t n_params);
+int sv_check_pauli_sum(const sv_pauli_sum *ham, int n_qubits);
+
+/* Optional per-kernel timing with HIP events recorded on the launching
+ * stream around every launch (off by default).  name = kernel family. */
+int sv_profile_enable(sv_ctx *ctx, int on);
+int sv_profile_get(sv_ctx *ctx, const char *name, double *total_ms,
+                   uint64_t *launches, double *bytes);
+int sv_profile_reset(sv_ctx *ctx);
+
+const char *sv_last_error(void);
+const char *sv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SV_ABI_H_INCLUDED */

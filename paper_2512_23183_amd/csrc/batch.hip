@@ -1,0 +1,319 @@
+// Batched execution of many independent circuits (parameter-shift copies,
+// serving requests of mixed qubit counts), each from |0...0>.
+//
+//  * Circuits whose whole state fits one workgroup's LDS run in one
+//    persistent launch: each workgroup repeatedly takes the next circuit
+//    from a device counter (largest first), applies every op in LDS and
+//    reduces the FP64 energy in place.  No HBM traffic for the state.
+//  * Larger circuits run one at a time through the fused pass executor and
+//    the two-stage FP64 expectation, energies staying on the device.
+//  * The gradient is combined on the device in FP64 from the energies
+//    (fixed summation order).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "device_common.h"
+
+namespace sv {
+
+struct alignas(16) DevCirc {
+    int32_t n, op_begin, op_end, ovr_index;  // ovr_index: absolute op index or -1
+    int32_t ovr_slot, grp_begin, grp_end, T;
+    int32_t coeff_begin, out_slot, pad0, pad1;
+};
+
+constexpr int SMALL_TPB = 256;
+
+int small_batch_max_qubits(int dtype) { return dtype == SV_C64 ? 13 : 12; }
+
+__global__ void k_fill_u32(unsigned *p, unsigned v, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+// LDS: state[2^max_n], red[TPB/64], vals[max_T + 1].
+template <typename R>
+__global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
+    const DevCirc *__restrict__ circ, int ncirc, unsigned *__restrict__ counter,
+    const DevOp<R> *__restrict__ ops, const DevOp<R> *__restrict__ ovr_ops,
+    const DevTerm *__restrict__ terms, const int *__restrict__ gbeg, const int *__restrict__ gend,
+    const uint64_t *__restrict__ gx, const double *__restrict__ coeffs, double *__restrict__ energies,
+    int max_n) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int cur;
+    V2<R> *st = reinterpret_cast<V2<R> *>(smem);
+    double *red = reinterpret_cast<double *>(smem + (sizeof(V2<R>) << max_n));
+    double *vals = red + SMALL_TPB / 64;
+    auto gidx = [](uint32_t j) -> uint64_t { return j; };
+    for (;;) {
+        if (threadIdx.x == 0) cur = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int c = cur;
+        __syncthreads();
+        if (c >= ncirc) break;
+        const DevCirc &C = circ[c];
+        const int n = C.n;
+        const uint32_t N = 1u << n;
+        for (uint32_t j = threadIdx.x; j < N; j += SMALL_TPB) {
+            V2<R> v;
+            v.x = j == 0 ? (R)1 : (R)0;
+            v.y = 0;
+            st[j] = v;
+        }
+        lds_apply_list<R, SMALL_TPB>(st, n, ops, C.op_begin, C.op_end, 0, gidx, C.ovr_index,
+                                     ovr_ops + (C.ovr_slot > 0 ? C.ovr_slot : 0));
+        for (int g = C.grp_begin; g < C.grp_end; ++g) {
+            const uint64_t x = gx[g];
+            const int hb = x ? 63 - __clzll(x) : -1;
+            const uint32_t items = x ? N / 2 : N;
+            for (int t = gbeg[g]; t < gend[g]; ++t) {
+                const uint64_t z = terms[t].z;
+                const int ny = terms[t].ny;
+                double acc = 0.0;
+                for (uint32_t it = threadIdx.x; it < items; it += SMALL_TPB) {
+                    if (x == 0) {
+                        const V2<R> a = st[it];
+                        const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+                        acc += (__popcll(it & z) & 1) ? -p : p;
+                    } else {
+                        const uint32_t k = ((it >> hb) << (hb + 1)) | (it & ((1u << hb) - 1));
+                        const uint32_t k2 = k ^ (uint32_t)x;
+                        const V2<R> a = st[k], b = st[k2];
+                        const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+                        acc += pair_contrib(bx * ax + by * ay, bx * ay - by * ax, k, k2, z, ny);
+                    }
+                }
+                const double s = block_sum<SMALL_TPB>(acc, red);
+                if (threadIdx.x == 0) vals[terms[t].idx] = s;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double e = 0.0;
+            for (int t = 0; t < C.T; ++t) e += coeffs[C.coeff_begin + t] * vals[t];
+            energies[C.out_slot] = e / vals[C.T];
+        }
+        __syncthreads();
+    }
+}
+
+// grad[i] = sum_j w[j] * E[circ[j]] for j in [beg[i], beg[i+1]) in order.
+__global__ void k_combine(const double *__restrict__ E, const int *__restrict__ beg,
+                          const int *__restrict__ circ, const double *__restrict__ w, int np,
+                          double *__restrict__ grad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    double s = 0.0;
+    for (int j = beg[i]; j < beg[i + 1]; ++j) s += w[j] * E[circ[j]];
+    grad[i] = s;
+}
+
+namespace {
+
+struct Blob {
+    std::vector<unsigned char> host;
+    size_t add(const void *src, size_t bytes) {
+        const size_t off = (host.size() + 255) & ~(size_t)255;
+        host.resize(off + std::max<size_t>(bytes, 16), 0);
+        if (bytes && src) std::memcpy(host.data() + off, src, bytes);
+        return off;
+    }
+};
+
+constexpr size_t SMALL_VALS_MAX = 32 * 1024;  // LDS bytes for term values
+
+template <typename R>
+void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, double *d_E) {
+    if (idx.empty()) return;
+    // op sets used by these circuits, uploaded once
+    std::vector<int> set_begin(spec.op_sets.size(), -1), set_end(spec.op_sets.size(), -1);
+    std::vector<DevOp<R>> dops;
+    std::vector<int> all_local(64);
+    std::iota(all_local.begin(), all_local.end(), 0);
+    std::vector<int> ham_gb(spec.hams.size(), -1), ham_ge(spec.hams.size(), -1),
+        ham_cb(spec.hams.size(), -1), ham_T(spec.hams.size(), 0);
+    std::vector<DevTerm> terms;
+    std::vector<int> gbeg, gend;
+    std::vector<uint64_t> gx;
+    std::vector<double> coeffs;
+    std::vector<DevCirc> circ;
+    std::vector<DevOp<R>> ovr;
+    int max_n = 1, max_T = 0;
+    for (int c : idx) {
+        const BatchCircuit &bc = spec.circuits[c];
+        if (set_begin[bc.op_set] < 0) {
+            set_begin[bc.op_set] = (int)dops.size();
+            std::vector<int> loc(all_local.begin(), all_local.begin() + bc.n);
+            for (const Op &op : spec.op_sets[bc.op_set]) {
+                DevOp<R> d = to_dev<R>(op);
+                localise(d, loc);
+                dops.push_back(d);
+            }
+            set_end[bc.op_set] = (int)dops.size();
+        }
+        if (ham_gb[bc.ham] < 0) {
+            DevTerms dt = build_dev_terms(spec.hams[bc.ham]);
+            const int tb = (int)terms.size();
+            ham_gb[bc.ham] = (int)gx.size();
+            for (size_t g = 0; g < dt.gx.size(); ++g) {
+                gx.push_back(dt.gx[g]);
+                gbeg.push_back(tb + dt.gbeg[g]);
+                gend.push_back(tb + dt.gend[g]);
+            }
+            ham_ge[bc.ham] = (int)gx.size();
+            terms.insert(terms.end(), dt.terms.begin(), dt.terms.end());
+            ham_cb[bc.ham] = (int)coeffs.size();
+            coeffs.insert(coeffs.end(), dt.coeffs.begin(), dt.coeffs.end());
+            ham_T[bc.ham] = dt.T;
+        }
+        DevCirc d;
+        std::memset(&d, 0, sizeof d);
+        d.n = bc.n;
+        d.op_begin = set_begin[bc.op_set];
+        d.op_end = set_end[bc.op_set];
+        d.ovr_index = -1;
+        d.ovr_slot = 0;
+        if (bc.ovr_index >= 0) {
+            d.ovr_index = d.op_begin + bc.ovr_index;
+            d.ovr_slot = (int)ovr.size();
+            std::vector<int> loc(all_local.begin(), all_local.begin() + bc.n);
+            DevOp<R> o = to_dev<R>(bc.ovr_op);
+            localise(o, loc);
+            ovr.push_back(o);
+        }
+        d.grp_begin = ham_gb[bc.ham];
+        d.grp_end = ham_ge[bc.ham];
+        d.T = ham_T[bc.ham];
+        d.coeff_begin = ham_cb[bc.ham];
+        d.out_slot = bc.out_slot >= 0 ? bc.out_slot : c;
+        circ.push_back(d);
+        max_n = std::max(max_n, bc.n);
+        max_T = std::max(max_T, d.T);
+    }
+    if (ovr.empty()) ovr.resize(1);
+    // largest circuits first: better balance of the dynamic schedule
+    std::stable_sort(circ.begin(), circ.end(), [](const DevCirc &a, const DevCirc &b) {
+        return (a.op_end - a.op_begin) * (1ll << a.n) > (b.op_end - b.op_begin) * (1ll << b.n);
+    });
+    Blob blob;
+    const size_t o_c = blob.add(circ.data(), circ.size() * sizeof(DevCirc));
+    const size_t o_ops = blob.add(dops.data(), dops.size() * sizeof(DevOp<R>));
+    const size_t o_ovr = blob.add(ovr.data(), ovr.size() * sizeof(DevOp<R>));
+    const size_t o_t = blob.add(terms.data(), terms.size() * sizeof(DevTerm));
+    const size_t o_gb = blob.add(gbeg.data(), gbeg.size() * 4);
+    const size_t o_ge = blob.add(gend.data(), gend.size() * 4);
+    const size_t o_gx = blob.add(gx.data(), gx.size() * 8);
+    const size_t o_cf = blob.add(coeffs.data(), coeffs.size() * 8);
+    const size_t o_cnt = blob.add(nullptr, 16);
+    char *base = (char *)scratch(ctx, "batch_small", blob.host.size());
+    upload(ctx, base, blob.host.data(), blob.host.size());
+    unsigned *d_cnt = (unsigned *)(base + o_cnt);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, ctx->stream, d_cnt, 0u, 1);
+    const size_t lds = (sizeof(V2<R>) << max_n) + 8 * (SMALL_TPB / 64) + 8 * (max_T + 1);
+    set_lds_limit((const void *)k_small_batch<R>, lds);
+    const int nc = (int)circ.size();
+    const int per_cu = lds <= 40 * 1024 ? 4 : lds <= 80 * 1024 ? 2 : 1;
+    const int grid = std::max(1, std::min(nc, ctx->cu_count * per_cu));
+    double bytes = 0;
+    for (const DevCirc &d : circ) bytes += (double)(sizeof(V2<R>) << d.n);
+    LaunchScope ls(ctx, "small_batch", bytes);
+    hipLaunchKernelGGL(k_small_batch<R>, dim3(grid), dim3(SMALL_TPB), lds, ctx->stream,
+                       (const DevCirc *)(base + o_c), nc, d_cnt, (const DevOp<R> *)(base + o_ops),
+                       (const DevOp<R> *)(base + o_ovr), (const DevTerm *)(base + o_t),
+                       (const int *)(base + o_gb), (const int *)(base + o_ge),
+                       (const uint64_t *)(base + o_gx), (const double *)(base + o_cf), d_E, max_n);
+    SV_HIP(hipGetLastError());
+}
+
+// Large circuits: one at a time through the pass executor.
+void run_large_sequential(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, uint32_t flags,
+                          double *d_E) {
+    if (idx.empty()) return;
+    int max_n = 0;
+    for (int c : idx) max_n = std::max(max_n, spec.circuits[c].n);
+    const size_t amp = spec.dtype == SV_C64 ? 8 : 16;
+    void *buf = scratch(ctx, "batch_state", amp << max_n);
+    std::vector<DevTerms> dts(spec.hams.size());
+    std::vector<bool> have(spec.hams.size(), false);
+    for (int c : idx) {
+        const BatchCircuit &bc = spec.circuits[c];
+        State st;
+        st.ctx = ctx;
+        st.n = bc.n;
+        st.dtype = spec.dtype;
+        st.ptr = buf;
+        st.owned = false;
+        set_zero_state(ctx, buf, bc.n, spec.dtype);
+        std::vector<Op> ops = spec.op_sets[bc.op_set];
+        if (bc.ovr_index >= 0) ops[bc.ovr_index] = bc.ovr_op;
+        if (flags & SV_FLAG_UNFUSED) {
+            run_unfused(ctx, &st, ops);
+        } else {
+            PlanOptions po;
+            po.tile_bits = spec.dtype == SV_C64 ? ctx->tile_bits_c64 : ctx->tile_bits_c128;
+            run_plan(ctx, &st, make_plan(bc.n, ops, po));
+        }
+        if (!have[bc.ham]) {
+            dts[bc.ham] = build_dev_terms(spec.hams[bc.ham]);
+            have[bc.ham] = true;
+        }
+        expectation_dev(ctx, buf, bc.n, spec.dtype, dts[bc.ham], d_E + (bc.out_slot >= 0 ? bc.out_slot : c),
+                        nullptr);
+    }
+}
+
+}  // namespace
+
+void run_batch_dev(Ctx *ctx, const BatchSpec &spec, uint32_t flags, double *d_E) {
+    const int nc = (int)spec.circuits.size();
+    std::vector<int> small, large;
+    const int smax = small_batch_max_qubits(spec.dtype);
+    const bool sequential = (flags & (SV_FLAG_SEQUENTIAL | SV_FLAG_UNFUSED)) != 0;
+    for (int c = 0; c < nc; ++c) {
+        const BatchCircuit &bc = spec.circuits[c];
+        const size_t vals = 8 * (spec.hams[bc.ham].terms.size() + 1);
+        if (!sequential && bc.n <= smax && vals <= SMALL_VALS_MAX) small.push_back(c);
+        else large.push_back(c);
+    }
+    if (spec.dtype == SV_C64) launch_small<float>(ctx, spec, small, d_E);
+    else launch_small<double>(ctx, spec, small, d_E);
+    run_large_sequential(ctx, spec, large, flags, d_E);
+}
+
+void combine_dev(Ctx *ctx, const double *d_E, const std::vector<int> &beg, const std::vector<int> &circ,
+                 const std::vector<double> &w, double *d_grad) {
+    const int np = beg.empty() ? 0 : (int)beg.size() - 1;
+    if (np <= 0) return;
+    Blob blob;
+    const size_t o_b = blob.add(beg.data(), beg.size() * 4);
+    const size_t o_c = blob.add(circ.data(), circ.size() * 4);
+    const size_t o_w = blob.add(w.data(), w.size() * 8);
+    char *base = (char *)scratch(ctx, "comb", blob.host.size());
+    upload(ctx, base, blob.host.data(), blob.host.size());
+    hipLaunchKernelGGL(k_combine, dim3((np + 255) / 256), dim3(256), 0, ctx->stream, d_E,
+                       (const int *)(base + o_b), (const int *)(base + o_c), (const double *)(base + o_w), np,
+                       d_grad);
+    SV_HIP(hipGetLastError());
+}
+
+void run_batch(Ctx *ctx, const BatchSpec &spec, uint32_t flags, std::vector<double> &E,
+               std::vector<double> &grad) {
+    const int nc = (int)spec.circuits.size();
+    const int np = spec.comb_begin.empty() ? 0 : (int)spec.comb_begin.size() - 1;
+    double *d_E = (double *)scratch(ctx, "batch_E", (size_t)(std::max(nc, 1) + np) * 8);
+    run_batch_dev(ctx, spec, flags, d_E);
+    grad.assign(np, 0.0);
+    if (np > 0) {
+        combine_dev(ctx, d_E, spec.comb_begin, spec.comb_circ, spec.comb_w, d_E + nc);
+        SV_HIP(hipMemcpyAsync(grad.data(), d_E + nc, (size_t)np * 8, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    E.assign(nc, 0.0);
+    if (nc) SV_HIP(hipMemcpyAsync(E.data(), d_E, (size_t)nc * 8, hipMemcpyDeviceToHost, ctx->stream));
+    SV_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->profile) profile_collect(ctx);
+}
+
+}  // namespace sv

@@ -1,0 +1,676 @@
+// HIP kernels for gfx950 (wave64) and their host launchers.
+//
+//  * sweep kernels: one gate over the whole state, one launch per gate (the
+//    plain path).  The loop runs over the reduced index space of the
+//    amplitudes the gate actually touches (bit-mask loops of the paper's
+//    direct state-vector gates): consecutive work-items map to consecutive
+//    addresses on every bit above the target, so loads and stores of both
+//    halves of a pair are coalesced.
+//  * tile pass: one workgroup loads 2^m amplitudes (every index bit outside
+//    the tile fixed) into LDS with coalesced runs over the low bits, applies
+//    a list of ops in LDS and writes the tile back: one HBM round trip for
+//    many gates.  Diagonal ops are evaluated from the global index and so may
+//    touch any bit.
+//  * permutation pass: in-place exchange of bit pairs (restores the layout
+//    after the planner absorbed SWAP gates into a relabelling).
+//  * expectation: stage 1 writes FP64 per-block partial sums per Pauli term
+//    (amplitudes upcast to FP64 before any product); stage 2 reduces them in
+//    a fixed order, so results are bitwise reproducible.
+//  * small-state batch: one workgroup runs a whole circuit of <= 2^13
+//    amplitudes in LDS and reduces its energy (parameter-shift batches).
+#include "device_common.h"
+
+namespace sv {
+
+// ---------------------------------------------------------------------------
+// Sweep kernels (one gate per launch)
+// ---------------------------------------------------------------------------
+
+constexpr int SWEEP_TPB = 256;
+
+template <typename R>
+__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_u1(V2<R> *__restrict__ psi, uint64_t items,
+                                                        Ins in, int a, DevOp<R> op) {
+    const V2<R> m0 = mat_at(op, 0), m1 = mat_at(op, 1), m2 = mat_at(op, 2), m3 = mat_at(op, 3);
+    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
+    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
+        const uint64_t k0 = expand(r, in), k1 = k0 | (1ull << a);
+        const V2<R> x = psi[k0], y = psi[k1];
+        psi[k0] = cmac2(m0, x, m1, y);
+        psi[k1] = cmac2(m2, x, m3, y);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_xperm(V2<R> *__restrict__ psi, uint64_t items,
+                                                           Ins in, int a) {
+    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
+    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
+        const uint64_t k0 = expand(r, in), k1 = k0 | (1ull << a);
+        const V2<R> x = psi[k0], y = psi[k1];
+        psi[k0] = y;
+        psi[k1] = x;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_u2(V2<R> *__restrict__ psi, uint64_t items,
+                                                        Ins in, int a, int b, DevOp<R> op) {
+    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
+    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
+        const uint64_t k = expand(r, in);
+        const uint64_t idx[4] = {k, k | (1ull << b), k | (1ull << a), k | (1ull << a) | (1ull << b)};
+        V2<R> v[4], w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = psi[idx[i]];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            V2<R> acc = cmul(mat_at(op, 4 * i), v[0]);
+#pragma unroll
+            for (int j = 1; j < 4; ++j) {
+                V2<R> t = cmul(mat_at(op, 4 * i + j), v[j]);
+                acc.x += t.x;
+                acc.y += t.y;
+            }
+            w[i] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) psi[idx[i]] = w[i];
+    }
+}
+
+// Phase on the amplitudes selected by `in` (every fixed bit set): factor f.
+template <typename R>
+__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_phase(V2<R> *__restrict__ psi, uint64_t items,
+                                                           Ins in, V2<R> f) {
+    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
+    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
+        const uint64_t k = expand(r, in);
+        psi[k] = cmul(psi[k], f);
+    }
+}
+
+// General diagonal: amplitudes with all control bits set get m[idx(bits a, b)].
+template <typename R>
+__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_diag(V2<R> *__restrict__ psi, uint64_t items,
+                                                          Ins in, int a, int b, DevOp<R> op) {
+    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
+    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
+        const uint64_t k = expand(r, in);
+        int idx = (int)((k >> a) & 1);
+        if (b >= 0) idx = 2 * idx + (int)((k >> b) & 1);
+        psi[k] = cmul(psi[k], mat_at(op, idx));
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_ladder(V2<R> *__restrict__ psi, uint64_t items,
+                                                            Ins in, uint64_t lmask, double turns) {
+    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
+    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
+        const uint64_t k = expand(r, in);
+        psi[k] = cmul(psi[k], ladder_phase<R>(turns, k & lmask));
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_swap(V2<R> *__restrict__ psi, uint64_t items,
+                                                          Ins in, uint64_t flip) {
+    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
+    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
+        const uint64_t k = expand(r, in), k2 = k ^ flip;
+        const V2<R> x = psi[k], y = psi[k2];
+        psi[k] = y;
+        psi[k2] = x;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(SWEEP_TPB) void k_zero(V2<R> *__restrict__ psi, uint64_t dim) {
+    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
+    for (uint64_t k = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; k < dim; k += stride) {
+        V2<R> v;
+        v.x = (k == 0) ? (R)1 : (R)0;
+        v.y = 0;
+        psi[k] = v;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(SWEEP_TPB) void k_scale(V2<R> *__restrict__ psi, uint64_t dim, double s) {
+    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
+    for (uint64_t k = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; k < dim; k += stride) {
+        V2<R> v = psi[k];
+        v.x = (R)((double)v.x * s);
+        v.y = (R)((double)v.y * s);
+        psi[k] = v;
+    }
+}
+
+constexpr int TILE_TPB = 256;
+
+// One workgroup per tile.  LDS: tile[2^m] then hi_off[2^(m-l)].
+template <typename R>
+__global__ __launch_bounds__(TILE_TPB) void k_tile(V2<R> *__restrict__ psi,
+                                                   const DevPass *__restrict__ passes, int pidx,
+                                                   const DevOp<R> *__restrict__ ops) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const DevPass &P = passes[pidx];
+    const int m = P.m, l = P.l;
+    V2<R> *tile = reinterpret_cast<V2<R> *>(smem);
+    uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem + (sizeof(V2<R>) << m));
+    const uint32_t T = 1u << m;
+    const uint32_t nhi = 1u << (m - l);
+    const uint32_t lowm = (1u << l) - 1;
+    for (uint32_t h = threadIdx.x; h < nhi; h += TILE_TPB) {
+        uint64_t o = 0;
+        for (int i = 0; i < m - l; ++i)
+            if ((h >> i) & 1) o |= 1ull << P.local_bits[l + i];
+        hi_off[h] = o;
+    }
+    uint64_t base = 0;
+    {
+        const uint64_t t = blockIdx.x;
+        for (int i = 0; i < P.nfree; ++i)
+            if ((t >> i) & 1) base |= 1ull << P.free_bits[i];
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < T; j += TILE_TPB) tile[j] = psi[base | hi_off[j >> l] | (j & lowm)];
+    auto gidx = [&](uint32_t j) -> uint64_t { return base | hi_off[j >> l] | (j & lowm); };
+    lds_apply_list<R, TILE_TPB>(tile, m, ops, P.op_begin, P.op_end, base, gidx);
+    for (uint32_t j = threadIdx.x; j < T; j += TILE_TPB) psi[base | hi_off[j >> l] | (j & lowm)] = tile[j];
+}
+
+// In-place involution on index bits: pairs (swap_a[i], swap_b[i]).  The
+// local bit set is closed under the involution, so tile v maps onto tile
+// w = P(v); the workgroup owning min(v, w) exchanges both.
+template <typename R>
+__global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ psi,
+                                                   const DevPass *__restrict__ passes, int pidx) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const DevPass &P = passes[pidx];
+    const int m = P.m, l = P.l;
+    const uint32_t T = 1u << m;
+    V2<R> *A = reinterpret_cast<V2<R> *>(smem);
+    V2<R> *B = A + T;
+    uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem + 2 * (sizeof(V2<R>) << m));
+    const uint32_t nhi = 1u << (m - l);
+    const uint32_t lowm = (1u << l) - 1;
+    for (uint32_t h = threadIdx.x; h < nhi; h += TILE_TPB) {
+        uint64_t o = 0;
+        for (int i = 0; i < m - l; ++i)
+            if ((h >> i) & 1) o |= 1ull << P.local_bits[l + i];
+        hi_off[h] = o;
+    }
+    uint64_t bv = 0;
+    {
+        const uint64_t t = blockIdx.x;
+        for (int i = 0; i < P.nfree; ++i)
+            if ((t >> i) & 1) bv |= 1ull << P.free_bits[i];
+    }
+    // partner base and the local permutation (pairs inside the tile)
+    uint64_t bw = bv;
+    uint32_t lsa[24], lsb[24];
+    int nl = 0;
+    for (int i = 0; i < P.nswap; ++i) {
+        const int a = P.swap_a[i], b = P.swap_b[i];
+        int la = -1, lb = -1;
+        for (int j = 0; j < m; ++j) {
+            if (P.local_bits[j] == a) la = j;
+            if (P.local_bits[j] == b) lb = j;
+        }
+        if (la >= 0 && lb >= 0) {
+            lsa[nl] = la;
+            lsb[nl] = lb;
+            ++nl;
+        } else {
+            const uint64_t ba = (bv >> a) & 1, bb = (bv >> b) & 1;
+            if (ba != bb) bw ^= (1ull << a) | (1ull << b);
+        }
+    }
+    if (bw < bv) return;  // the partner workgroup does both tiles
+    __syncthreads();
+    const bool two = bw != bv;
+    for (uint32_t j = threadIdx.x; j < T; j += TILE_TPB) {
+        const uint64_t off = hi_off[j >> l] | (j & lowm);
+        A[j] = psi[bv | off];
+        if (two) B[j] = psi[bw | off];
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < T; j += TILE_TPB) {
+        uint32_t s = j;
+        for (int i = 0; i < nl; ++i) {
+            const uint32_t x = ((s >> lsa[i]) ^ (s >> lsb[i])) & 1;
+            s ^= (x << lsa[i]) | (x << lsb[i]);
+        }
+        const uint64_t off = hi_off[j >> l] | (j & lowm);
+        if (two) {
+            psi[bw | off] = A[s];
+            psi[bv | off] = B[s];
+        } else {
+            psi[bv | off] = A[s];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 expectation values
+// ---------------------------------------------------------------------------
+
+constexpr int EXP_TPB = 256;
+constexpr int EXP_CHUNK = 8;  // terms accumulated per sweep over the items
+
+// grid (nb, ngroups).  Terms of group g are tg[gbeg[g] .. gend[g]).
+// partial[term.idx * nb + blockIdx.x] receives the block's FP64 sum.
+template <typename R>
+__global__ __launch_bounds__(EXP_TPB) void k_expect1(const V2<R> *__restrict__ psi, int n,
+                                                     const DevTerm *__restrict__ tg,
+                                                     const int *__restrict__ gbeg,
+                                                     const int *__restrict__ gend,
+                                                     const uint64_t *__restrict__ gx, int nb,
+                                                     double *__restrict__ partial) {
+    __shared__ double red[EXP_TPB / 64];
+    const int g = blockIdx.y;
+    const uint64_t x = gx[g];
+    const int hb = x ? 63 - __clzll(x) : -1;
+    const uint64_t items = x ? (1ull << (n - 1)) : (1ull << n);
+    const uint64_t stride = (uint64_t)nb * EXP_TPB;
+    const uint64_t start = (uint64_t)blockIdx.x * EXP_TPB + threadIdx.x;
+    for (int t0 = gbeg[g]; t0 < gend[g]; t0 += EXP_CHUNK) {
+        const int cnt = min(EXP_CHUNK, gend[g] - t0);
+        double acc[EXP_CHUNK];
+#pragma unroll
+        for (int i = 0; i < EXP_CHUNK; ++i) acc[i] = 0.0;
+        for (uint64_t it = start; it < items; it += stride) {
+            if (x == 0) {
+                const V2<R> a = psi[it];
+                const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+#pragma unroll
+                for (int i = 0; i < EXP_CHUNK; ++i)
+                    if (i < cnt) acc[i] += (__popcll(it & tg[t0 + i].z) & 1) ? -p : p;
+            } else {
+                const uint64_t k = ((it >> hb) << (hb + 1)) | (it & ((1ull << hb) - 1));
+                const uint64_t k2 = k ^ x;
+                const V2<R> a = psi[k], b = psi[k2];
+                const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+                const double pre = bx * ax + by * ay, pim = bx * ay - by * ax;  // conj(b) a
+#pragma unroll
+                for (int i = 0; i < EXP_CHUNK; ++i)
+                    if (i < cnt) acc[i] += pair_contrib(pre, pim, k, k2, tg[t0 + i].z, tg[t0 + i].ny);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < EXP_CHUNK; ++i) {
+            if (i < cnt) {
+                const double s = block_sum<EXP_TPB>(acc[i], red);
+                if (threadIdx.x == 0) partial[(size_t)tg[t0 + i].idx * nb + blockIdx.x] = s;
+            }
+        }
+    }
+}
+
+// Stage 2: value[t] = sum_b partial[t*nb + b] (ascending b); then
+// E = (sum_t c_t value[t]) / value[T] in term order.  vals_out[t] =
+// value[t] / norm for t < T, vals_out[T] = norm; *energy_out = E.
+__global__ void k_expect2(double *__restrict__ partial, int nb, int T, const double *__restrict__ coeffs,
+                          double *__restrict__ vals_out, double *__restrict__ energy_out) {
+    // each thread owns rows t: sums them in ascending b and parks the value
+    // in partial[t * nb] (the row's first slot)
+    for (int t = threadIdx.x; t <= T; t += blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += partial[(size_t)t * nb + b];
+        partial[(size_t)t * nb] = s;
+    }
+    __threadfence_block();
+    __syncthreads();
+    const double norm = partial[(size_t)T * nb];
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        for (int t = 0; t < T; ++t) e += coeffs[t] * partial[(size_t)t * nb];
+        *energy_out = e / norm;
+        if (vals_out) vals_out[T] = norm;
+    }
+    if (vals_out)
+        for (int t = threadIdx.x; t < T; t += blockDim.x) vals_out[t] = partial[(size_t)t * nb] / norm;
+}
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+
+void *scratch(Ctx *ctx, const std::string &name, size_t bytes) {
+    DeviceBuffer &b = ctx->scratch[name];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            SV_HIP(hipStreamSynchronize(ctx->stream));
+            SV_HIP(hipFree(b.ptr));
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        size_t want = std::max<size_t>(bytes, 4096);
+        if (hipMalloc(&b.ptr, want) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(SV_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+        }
+        b.bytes = want;
+    }
+    return b.ptr;
+}
+
+void upload(Ctx *ctx, void *dst, const void *src, size_t bytes) {
+    if (bytes) SV_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+}
+
+LaunchScope::LaunchScope(Ctx *c, const char *nm, double b) : ctx(c), name(nm), bytes(b) {
+    if (!ctx->profile) return;
+    if (ctx->free_events.size() >= 2) {
+        e0 = ctx->free_events.back();
+        ctx->free_events.pop_back();
+        e1 = ctx->free_events.back();
+        ctx->free_events.pop_back();
+    } else {
+        SV_HIP(hipEventCreate(&e0));
+        SV_HIP(hipEventCreate(&e1));
+    }
+    SV_HIP(hipEventRecord(e0, ctx->stream));
+}
+LaunchScope::~LaunchScope() {
+    if (!e0) return;
+    if (hipEventRecord(e1, ctx->stream) != hipSuccess) return;
+    ctx->pending.push_back({name, {e0, e1}});
+    ctx->pending_bytes.push_back(bytes);
+}
+
+void profile_collect(Ctx *ctx) {
+    for (size_t i = 0; i < ctx->pending.size(); ++i) {
+        auto &p = ctx->pending[i];
+        float ms = 0.f;
+        SV_HIP(hipEventSynchronize(p.second.second));
+        SV_HIP(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+        ProfileEntry &e = ctx->prof[p.first];
+        e.ms += ms;
+        e.launches += 1;
+        e.bytes += ctx->pending_bytes[i];
+        ctx->free_events.push_back(p.second.first);
+        ctx->free_events.push_back(p.second.second);
+    }
+    ctx->pending.clear();
+    ctx->pending_bytes.clear();
+}
+
+unsigned grid_for(uint64_t items, int tpb, int cu) {
+    uint64_t g = (items + tpb - 1) / tpb;
+    const uint64_t cap = (uint64_t)cu * 64;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+void set_lds_limit(const void *fn, size_t bytes) {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> g(mu);
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+static DevPass to_dev_pass(const Pass &ps, int op_begin, int op_end) {
+    DevPass d;
+    std::memset(&d, 0, sizeof d);
+    d.kind = ps.kind;
+    d.m = ps.m;
+    d.l = ps.l;
+    d.nfree = (int)ps.free_bits.size();
+    d.op_begin = op_begin;
+    d.op_end = op_end;
+    d.nswap = (int)ps.swaps.size();
+    for (size_t i = 0; i < ps.local_bits.size(); ++i) d.local_bits[i] = (int8_t)ps.local_bits[i];
+    for (size_t i = 0; i < ps.free_bits.size(); ++i) d.free_bits[i] = (int8_t)ps.free_bits[i];
+    for (size_t i = 0; i < ps.swaps.size(); ++i) {
+        d.swap_a[i] = (int8_t)ps.swaps[i].first;
+        d.swap_b[i] = (int8_t)ps.swaps[i].second;
+    }
+    return d;
+}
+
+template <typename R>
+static void sweep_one(Ctx *ctx, V2<R> *psi, int n, const Op &op) {
+    const int cu = ctx->cu_count;
+    const double amp = (double)sizeof(V2<R>);
+    DevOp<R> d = to_dev<R>(op);
+    std::vector<int> cb = bits_of(op.cmask);
+    switch (op.kind) {
+    case OP_U1:
+    case OP_XPERM: {
+        std::vector<int> pos = cb;
+        pos.push_back(op.a);
+        const Ins in = make_ins(pos, op.cmask);
+        const uint64_t items = 1ull << (n - pos.size());
+        LaunchScope ls(ctx, op.kind == OP_U1 ? "sweep_u1" : "sweep_xperm", 4.0 * amp * items);
+        if (op.kind == OP_U1)
+            hipLaunchKernelGGL(k_sweep_u1<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
+                               ctx->stream, psi, items, in, op.a, d);
+        else
+            hipLaunchKernelGGL(k_sweep_xperm<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
+                               ctx->stream, psi, items, in, op.a);
+        break;
+    }
+    case OP_U2: {
+        std::vector<int> pos = cb;
+        pos.push_back(op.a);
+        pos.push_back(op.b);
+        const Ins in = make_ins(pos, op.cmask);
+        const uint64_t items = 1ull << (n - pos.size());
+        LaunchScope ls(ctx, "sweep_u2", 8.0 * amp * items);
+        hipLaunchKernelGGL(k_sweep_u2<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
+                           ctx->stream, psi, items, in, op.a, op.b, d);
+        break;
+    }
+    case OP_SWAP: {
+        std::vector<int> pos = cb;
+        pos.push_back(op.a);
+        pos.push_back(op.b);
+        const Ins in = make_ins(pos, op.cmask | (1ull << op.a));
+        const uint64_t items = 1ull << (n - pos.size());
+        LaunchScope ls(ctx, "sweep_swap", 4.0 * amp * items);
+        hipLaunchKernelGGL(k_sweep_swap<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
+                           ctx->stream, psi, items, in, (1ull << op.a) | (1ull << op.b));
+        break;
+    }
+    case OP_DIAG: {
+        // phase-only on one pattern when the other entries are 1
+        const bool one_b = op.b < 0;
+        const int last = one_b ? 1 : 3;
+        bool only_last = true;
+        for (int k = 0; k < last; ++k) only_last &= op.m[k] == cd(1.0);
+        if (only_last) {
+            std::vector<int> pos = cb;
+            uint64_t ones = op.cmask | (1ull << op.a);
+            if (!(op.cmask & (1ull << op.a))) pos.push_back(op.a);
+            if (!one_b) {
+                if (!(ones & (1ull << op.b))) pos.push_back(op.b);
+                ones |= 1ull << op.b;
+            }
+            const Ins in = make_ins(pos, ones);
+            const uint64_t items = 1ull << (n - pos.size());
+            V2<R> f;
+            f.x = (R)op.m[last].real();
+            f.y = (R)op.m[last].imag();
+            LaunchScope ls(ctx, "sweep_phase", 2.0 * amp * items);
+            hipLaunchKernelGGL(k_sweep_phase<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
+                               ctx->stream, psi, items, in, f);
+        } else {
+            const Ins in = make_ins(cb, op.cmask);
+            const uint64_t items = 1ull << (n - cb.size());
+            LaunchScope ls(ctx, "sweep_diag", 2.0 * amp * items);
+            hipLaunchKernelGGL(k_sweep_diag<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
+                               ctx->stream, psi, items, in, op.a, op.b, d);
+        }
+        break;
+    }
+    case OP_LADDER: {
+        const Ins in = make_ins({op.a}, 1ull << op.a);
+        const uint64_t items = 1ull << (n - 1);
+        LaunchScope ls(ctx, "sweep_ladder", 2.0 * amp * items);
+        hipLaunchKernelGGL(k_sweep_ladder<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
+                           ctx->stream, psi, items, in, op.lmask, op.turns);
+        break;
+    }
+    default:
+        fail(SV_EDEVICE, "internal: bad op kind");
+    }
+    SV_HIP(hipGetLastError());
+}
+
+template <typename R>
+static void run_plan_t(Ctx *ctx, State *st, const Plan &plan) {
+    V2<R> *psi = reinterpret_cast<V2<R> *>(st->ptr);
+    const int n = st->n;
+    std::vector<DevOp<R>> dops;
+    std::vector<DevPass> dpass;
+    for (const Pass &ps : plan.passes) {
+        if (ps.kind == PASS_SWEEP) {
+            dpass.push_back(DevPass{});
+            continue;
+        }
+        const int b = (int)dops.size();
+        for (const Op &op : ps.ops) {
+            DevOp<R> d = to_dev<R>(op);
+            localise(d, ps.local_bits);
+            dops.push_back(d);
+        }
+        dpass.push_back(to_dev_pass(ps, b, (int)dops.size()));
+    }
+    DevOp<R> *d_ops = nullptr;
+    DevPass *d_pass = nullptr;
+    if (!dops.empty()) {
+        d_ops = (DevOp<R> *)scratch(ctx, "plan_ops", dops.size() * sizeof(DevOp<R>));
+        upload(ctx, d_ops, dops.data(), dops.size() * sizeof(DevOp<R>));
+    }
+    d_pass = (DevPass *)scratch(ctx, "plan_passes", dpass.size() * sizeof(DevPass) + 16);
+    upload(ctx, d_pass, dpass.data(), dpass.size() * sizeof(DevPass));
+    const double S = (double)st->bytes();
+    for (size_t i = 0; i < plan.passes.size(); ++i) {
+        const Pass &ps = plan.passes[i];
+        if (ps.kind == PASS_SWEEP) {
+            sweep_one<R>(ctx, psi, n, ps.ops[0]);
+            continue;
+        }
+        const uint64_t tiles = 1ull << ps.free_bits.size();
+        const uint32_t nhi = 1u << (ps.m - ps.l);
+        if (ps.kind == PASS_TILE) {
+            const size_t lds = (sizeof(V2<R>) << ps.m) + 8 * nhi;
+            set_lds_limit((const void *)k_tile<R>, lds);
+            LaunchScope ls(ctx, "tile", 2.0 * S);
+            hipLaunchKernelGGL(k_tile<R>, dim3((unsigned)tiles), dim3(TILE_TPB), lds, ctx->stream, psi,
+                               d_pass, (int)i, d_ops);
+        } else {
+            const size_t lds = 2 * (sizeof(V2<R>) << ps.m) + 8 * nhi;
+            set_lds_limit((const void *)k_perm<R>, lds);
+            LaunchScope ls(ctx, "perm", 2.0 * S);
+            hipLaunchKernelGGL(k_perm<R>, dim3((unsigned)tiles), dim3(TILE_TPB), lds, ctx->stream, psi,
+                               d_pass, (int)i);
+        }
+        SV_HIP(hipGetLastError());
+    }
+}
+
+void run_plan(Ctx *ctx, State *st, const Plan &plan) {
+    if (st->dtype == SV_C64) run_plan_t<float>(ctx, st, plan);
+    else run_plan_t<double>(ctx, st, plan);
+}
+
+void run_unfused(Ctx *ctx, State *st, const std::vector<Op> &ops) {
+    for (const Op &op : ops) {
+        if (st->dtype == SV_C64) sweep_one<float>(ctx, (V2<float> *)st->ptr, st->n, op);
+        else sweep_one<double>(ctx, (V2<double> *)st->ptr, st->n, op);
+    }
+}
+
+void set_zero_state(Ctx *ctx, void *psi, int n, int dtype) {
+    const uint64_t dim = 1ull << n;
+    const unsigned g = grid_for(dim, SWEEP_TPB, ctx->cu_count);
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL(k_zero<float>, dim3(g), dim3(SWEEP_TPB), 0, ctx->stream, (V2<float> *)psi, dim);
+    else
+        hipLaunchKernelGGL(k_zero<double>, dim3(g), dim3(SWEEP_TPB), 0, ctx->stream, (V2<double> *)psi, dim);
+    SV_HIP(hipGetLastError());
+}
+
+void device_scale(Ctx *ctx, void *psi, int n, int dtype, double s) {
+    const uint64_t dim = 1ull << n;
+    const unsigned g = grid_for(dim, SWEEP_TPB, ctx->cu_count);
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL(k_scale<float>, dim3(g), dim3(SWEEP_TPB), 0, ctx->stream, (V2<float> *)psi, dim, s);
+    else
+        hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(SWEEP_TPB), 0, ctx->stream, (V2<double> *)psi, dim, s);
+    SV_HIP(hipGetLastError());
+}
+
+// Two-stage FP64 expectation of a lowered Pauli sum.  The energy is written
+// to the device scalar d_energy; d_vals (nullable) receives the T + 1 values.
+template <typename R>
+static void expectation_dev_t(Ctx *ctx, const V2<R> *psi, int n, const DevTerms &dt, double *d_energy,
+                              double *d_vals) {
+    const int T = dt.T, G = (int)dt.gx.size();
+    if (G > 65535) fail(SV_EINVAL, "more than 65535 distinct X/Y supports in one Pauli sum");
+    const uint64_t items = 1ull << (n > 0 ? n - 1 : 0);
+    const int nb = (int)std::min<uint64_t>(1024, std::max<uint64_t>(1, items / (EXP_TPB * 16)));
+    const size_t tb = dt.terms.size() * sizeof(DevTerm);
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_gb = al(tb), o_ge = o_gb + al(G * 4), o_gx = o_ge + al(G * 4), o_c = o_gx + al(G * 8);
+    const size_t total = o_c + al(dt.coeffs.size() * 8);
+    std::vector<unsigned char> host(total, 0);
+    std::memcpy(host.data(), dt.terms.data(), tb);
+    std::memcpy(host.data() + o_gb, dt.gbeg.data(), G * 4);
+    std::memcpy(host.data() + o_ge, dt.gend.data(), G * 4);
+    std::memcpy(host.data() + o_gx, dt.gx.data(), G * 8);
+    std::memcpy(host.data() + o_c, dt.coeffs.data(), dt.coeffs.size() * 8);
+    char *buf = (char *)scratch(ctx, "exp_meta", total);
+    upload(ctx, buf, host.data(), total);
+    double *d_partial = (double *)scratch(ctx, "exp_partial", (size_t)(T + 1) * nb * 8);
+    {
+        LaunchScope ls(ctx, "expect1", (double)sizeof(V2<R>) * (double)(1ull << n) * G);
+        hipLaunchKernelGGL(k_expect1<R>, dim3(nb, G), dim3(EXP_TPB), 0, ctx->stream, psi, n,
+                           (const DevTerm *)buf, (const int *)(buf + o_gb), (const int *)(buf + o_ge),
+                           (const uint64_t *)(buf + o_gx), nb, d_partial);
+        SV_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_expect2, dim3(1), dim3(256), 0, ctx->stream, d_partial, nb, T,
+                       (const double *)(buf + o_c), d_vals, d_energy);
+    SV_HIP(hipGetLastError());
+}
+
+void expectation_dev(Ctx *ctx, const void *psi, int n, int dtype, const DevTerms &dt, double *d_energy,
+                     double *d_vals) {
+    if (dtype == SV_C64) expectation_dev_t<float>(ctx, (const V2<float> *)psi, n, dt, d_energy, d_vals);
+    else expectation_dev_t<double>(ctx, (const V2<double> *)psi, n, dt, d_energy, d_vals);
+}
+
+template <typename R>
+static void expectation_t(Ctx *ctx, const V2<R> *psi, int n, const TermGroups &tg, double *energy,
+                          double *term_values, double *norm2) {
+    DevTerms dt = build_dev_terms(tg);
+    const int T = dt.T;
+    double *d_out = (double *)scratch(ctx, "exp_out", (size_t)(T + 2) * 8);
+    expectation_dev_t<R>(ctx, psi, n, dt, d_out, d_out + 1);
+    std::vector<double> out(T + 2);
+    SV_HIP(hipMemcpyAsync(out.data(), d_out, (T + 2) * 8, hipMemcpyDeviceToHost, ctx->stream));
+    SV_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->profile) profile_collect(ctx);
+    if (energy) *energy = out[0];
+    if (term_values)
+        for (int t = 0; t < T; ++t) term_values[t] = out[1 + t];
+    if (norm2) *norm2 = out[1 + T];
+}
+
+void device_expectation(Ctx *ctx, const void *psi, int n, int dtype, const TermGroups &tg,
+                        double *energy, double *term_values, double *norm2) {
+    if (dtype == SV_C64) expectation_t<float>(ctx, (const V2<float> *)psi, n, tg, energy, term_values, norm2);
+    else expectation_t<double>(ctx, (const V2<double> *)psi, n, tg, energy, term_values, norm2);
+}
+
+void device_norm2(Ctx *ctx, const void *psi, int n, int dtype, double *out) {
+    TermGroups empty;
+    device_expectation(ctx, psi, n, dtype, empty, nullptr, nullptr, out);
+}
+
+}  // namespace sv

@@ -1,0 +1,311 @@
+// Planner: groups lowered ops into passes over the state.
+//
+// A TILE pass holds every amplitude whose index agrees outside a set S of m
+// bit positions ("local bits") in one workgroup's LDS.  S always contains
+// the lowest bits so that global loads and stores are coalesced runs.  An op
+// joins the pass if the bits it mixes (the target of a 2x2, both bits of a
+// 4x4) are in S; diagonal ops (phases, controlled phases, ladders) join any
+// pass because their factor is a function of the global index.  Ops that do
+// not fit are deferred, and later ops that commute with every deferred op
+// may still join (commutation test on bit sets), so layered circuits pack
+// several layers' worth of gates per pass.
+//
+// SWAP gates are absorbed into a relabelling of bit positions; the standard
+// layout is restored at the end by at most two in-place involution passes
+// (every permutation is a product of two involutions).
+#include <algorithm>
+#include <cassert>
+#include <numeric>
+
+#include "sv_internal.h"
+
+namespace sv {
+
+namespace {
+
+inline uint64_t bit(int b) { return 1ull << b; }
+
+struct OpSets {
+    uint64_t target = 0;   // bits mixed by the op (must be local)
+    uint64_t control = 0;  // control bits
+    uint64_t touch = 0;    // every bit the op depends on
+    bool diag = false;
+};
+
+OpSets sets_of(const Op &op) {
+    OpSets s;
+    switch (op.kind) {
+    case OP_U1: case OP_XPERM:
+        s.target = bit(op.a);
+        s.control = op.cmask;
+        break;
+    case OP_U2: case OP_SWAP:
+        s.target = bit(op.a) | bit(op.b);
+        s.control = op.cmask;
+        break;
+    case OP_DIAG:
+        s.diag = true;
+        s.touch = bit(op.a) | (op.b >= 0 ? bit(op.b) : 0) | op.cmask;
+        break;
+    case OP_LADDER:
+        s.diag = true;
+        s.touch = bit(op.a) | op.lmask;
+        break;
+    }
+    if (!s.diag) s.touch = s.target | s.control;
+    return s;
+}
+
+// Relabel bit positions of an op through phys[] (logical bit -> physical).
+Op remap(const Op &op, const std::vector<int> &phys) {
+    Op r = op;
+    auto mapmask = [&](uint64_t m) {
+        uint64_t o = 0;
+        for (int b = 0; b < (int)phys.size(); ++b)
+            if (m & bit(b)) o |= bit(phys[b]);
+        return o;
+    };
+    if (r.a >= 0) r.a = phys[r.a];
+    if (r.b >= 0) r.b = phys[r.b];
+    r.cmask = mapmask(op.cmask);
+    r.lmask = mapmask(op.lmask);  // ladders are only formed after relabelling
+    return r;
+}
+
+// Decompose the permutation "data bit at physical position phys[i] must move
+// to position i" into <= 2 involutions, each a list of disjoint bit pairs.
+// Applying the first involution and then the second realises the move.
+std::vector<std::vector<std::pair<int, int>>> involutions(const std::vector<int> &phys) {
+    const int n = (int)phys.size();
+    // dest[p] = where the bit now at position p must go
+    std::vector<int> dest(n);
+    for (int i = 0; i < n; ++i) dest[phys[i]] = i;
+    std::vector<std::vector<std::pair<int, int>>> out;
+    std::vector<std::pair<int, int>> s1, s2;
+    std::vector<bool> seen(n, false);
+    for (int p0 = 0; p0 < n; ++p0) {
+        if (seen[p0] || dest[p0] == p0) { seen[p0] = true; continue; }
+        std::vector<int> cyc;
+        for (int p = p0; !seen[p]; p = dest[p]) { seen[p] = true; cyc.push_back(p); }
+        const int k = (int)cyc.size();
+        // cycle c0 -> c1 -> ... -> c_{k-1} -> c0 (position c_i goes to c_{i+1})
+        // r1: c_i <-> c_{-i}, r2: c_i <-> c_{1-i};  r2 o r1 maps c_i -> c_{i+1}
+        for (int i = 0; i < k; ++i) {
+            int j = (k - i) % k;
+            if (i < j) s1.push_back({cyc[i], cyc[j]});
+            int j2 = ((1 - i) % k + k) % k;
+            if (i < j2) s2.push_back({cyc[i], cyc[j2]});
+        }
+    }
+    if (!s1.empty()) out.push_back(s1);
+    if (!s2.empty()) out.push_back(s2);
+    // verify on positions
+    std::vector<int> pos(n);
+    std::iota(pos.begin(), pos.end(), 0);  // pos[p] = current position of bit originally at p
+    for (auto &inv : out)
+        for (int p = 0; p < n; ++p)
+            for (auto &pr : inv) {
+                if (pos[p] == pr.first) { pos[p] = pr.second; break; }
+                if (pos[p] == pr.second) { pos[p] = pr.first; break; }
+            }
+    for (int p = 0; p < n; ++p)
+        if (pos[p] != dest[p]) fail(SV_EDEVICE, "internal: permutation decomposition failed");
+    return out;
+}
+
+Pass make_perm_pass(int n, const std::vector<std::pair<int, int>> &pairs, int m_target, int l) {
+    Pass ps;
+    ps.kind = PASS_PERM;
+    ps.swaps = pairs;
+    std::vector<int> partner(n, -1);
+    for (auto &pr : pairs) { partner[pr.first] = pr.second; partner[pr.second] = pr.first; }
+    std::vector<bool> in(n, false);
+    int cnt = 0;
+    auto add = [&](int b) {
+        if (!in[b]) { in[b] = true; ++cnt; }
+    };
+    for (int b = 0; b < l; ++b) {
+        add(b);
+        if (partner[b] >= 0) add(partner[b]);
+    }
+    // pad with the lowest bits that are unswapped, or whole pairs
+    for (int b = 0; b < n && cnt < m_target; ++b) {
+        if (in[b]) continue;
+        if (partner[b] < 0) add(b);
+        else if (cnt + 2 <= m_target) { add(b); add(partner[b]); }
+    }
+    for (int b = 0; b < n; ++b) (in[b] ? ps.local_bits : ps.free_bits).push_back(b);
+    ps.m = (int)ps.local_bits.size();
+    int run = 0;
+    while (run < ps.m && ps.local_bits[run] == run) ++run;
+    ps.l = run;
+    return ps;
+}
+
+void finish_tile_pass(int n, Pass &ps, uint64_t S) {
+    ps.kind = PASS_TILE;
+    ps.local_bits.clear();
+    ps.free_bits.clear();
+    for (int b = 0; b < n; ++b) (S & bit(b) ? ps.local_bits : ps.free_bits).push_back(b);
+    ps.m = (int)ps.local_bits.size();
+    int run = 0;
+    while (run < ps.m && ps.local_bits[run] == run) ++run;
+    ps.l = run;
+}
+
+}  // namespace
+
+Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
+    Plan plan;
+    plan.n = n;
+    plan.n_gate_ops = (int)ops_in.size();
+
+    if (!opt.fuse) {
+        for (const Op &op : ops_in) {
+            Pass ps;
+            ps.kind = PASS_SWEEP;
+            ps.ops.push_back(op);
+            plan.passes.push_back(std::move(ps));
+        }
+        return plan;
+    }
+
+    const int m = std::min(opt.tile_bits, n);
+    const int l = std::min(opt.low_bits, m);
+
+    // 1. absorb SWAPs into a relabelling
+    std::vector<int> phys(n);
+    std::iota(phys.begin(), phys.end(), 0);
+    std::vector<Op> ops;
+    ops.reserve(ops_in.size());
+    for (const Op &op : ops_in) {
+        if (op.kind == OP_SWAP && op.cmask == 0) {
+            std::swap(phys[op.a], phys[op.b]);
+            continue;
+        }
+        ops.push_back(remap(op, phys));
+    }
+
+    // 2. merge runs of fixed-angle controlled phases with a common control
+    //    into ladders when their angles are a common multiple of the
+    //    target's binary weight (the controlled-phase cascades of the QFT).
+    {
+        std::vector<Op> merged;
+        merged.reserve(ops.size());
+        size_t i = 0;
+        while (i < ops.size()) {
+            const Op &o = ops[i];
+            auto is_cp = [](const Op &p) {
+                return p.kind == OP_DIAG && !p.param && p.b >= 0 && p.cmask == 0 &&
+                       p.ang > 0.0 && p.m[0] == cd(1) && p.m[1] == cd(1) && p.m[2] == cd(1);
+            };
+            bool cp = is_cp(o);
+            if (!cp) { merged.push_back(o); ++i; continue; }
+            // the control is whichever bit is shared by the run: try o.a then o.b
+            Op best;
+            size_t best_end = i + 1;
+            for (int side = 0; side < 2; ++side) {
+                const int c = side == 0 ? o.a : o.b;
+                double turns = -1.0;
+                uint64_t mask = 0;
+                size_t j = i;
+                for (; j < ops.size(); ++j) {
+                    const Op &p = ops[j];
+                    if (!is_cp(p) || (p.a != c && p.b != c)) break;
+                    const int t = (p.a == c) ? p.b : p.a;
+                    if (mask & bit(t)) break;
+                    // phase 2 pi * turns * 2^t when bits c and t are set
+                    double tu = p.ang / (2.0 * M_PI) / std::ldexp(1.0, t);
+                    if (turns < 0) {
+                        if (tu <= 0) break;
+                        turns = tu;
+                    } else if (std::abs(tu - turns) > 1e-15 * turns) {
+                        break;
+                    }
+                    mask |= bit(t);
+                }
+                if (j - i >= 2 && j > best_end) {
+                    best = Op();
+                    best.kind = OP_LADDER;
+                    best.a = c;
+                    best.lmask = mask;
+                    best.turns = turns;
+                    best.gate = o.gate;
+                    best_end = j;
+                }
+            }
+            if (best_end > i + 1) {
+                merged.push_back(best);
+                i = best_end;
+            } else {
+                merged.push_back(o);
+                ++i;
+            }
+        }
+        ops.swap(merged);
+    }
+
+    // 3. greedy tile passes with commutation-aware deferral
+    const uint64_t low = (l >= 64) ? ~0ull : (bit(l) - 1);
+    std::vector<Op> rest = ops;
+    std::vector<OpSets> rsets(rest.size());
+    for (size_t i = 0; i < rest.size(); ++i) rsets[i] = sets_of(rest[i]);
+    while (!rest.empty()) {
+        Pass ps;
+        uint64_t S = low;
+        int nS = l;
+        uint64_t DT = 0, DC = 0, DZ = 0;
+        std::vector<Op> deferred;
+        std::vector<OpSets> dsets;
+        const uint64_t all = (n >= 64) ? ~0ull : (bit(n) - 1);
+        for (size_t i = 0; i < rest.size(); ++i) {
+            const Op &o = rest[i];
+            const OpSets &s = rsets[i];
+            bool can;
+            if (s.diag) can = (s.touch & DT) == 0;
+            else can = (s.target & (DT | DC | DZ)) == 0 && (s.control & DT) == 0;
+            if (can && !s.diag) {
+                uint64_t need = s.target & ~S;
+                int add = __builtin_popcountll(need);
+                if (nS + add <= m) { S |= need; nS += add; }
+                else can = false;
+            }
+            if (can) {
+                ps.ops.push_back(o);
+            } else {
+                deferred.push_back(o);
+                dsets.push_back(s);
+                if (s.diag) DZ |= s.touch;
+                else { DT |= s.target; DC |= s.control; }
+                // once every bit is blocked for mixing, nothing else can join
+                if ((DT & all) == all) {
+                    for (size_t j = i + 1; j < rest.size(); ++j) {
+                        deferred.push_back(rest[j]);
+                        dsets.push_back(rsets[j]);
+                    }
+                    break;
+                }
+            }
+        }
+        // pad the tile with the lowest unused bits (longer contiguous runs)
+        for (int b = 0; b < n && nS < m; ++b)
+            if (!(S & bit(b))) { S |= bit(b); ++nS; }
+        finish_tile_pass(n, ps, S);
+        if (ps.ops.empty()) fail(SV_EDEVICE, "internal: planner made no progress");
+        plan.passes.push_back(std::move(ps));
+        rest.swap(deferred);
+        rsets.swap(dsets);
+    }
+
+    // 4. restore the layout
+    bool ident = true;
+    for (int i = 0; i < n; ++i) ident &= phys[i] == i;
+    if (!ident) {
+        // two tiles live in LDS at once: 2 * 2^11 * 16 B = 64 KiB at most
+        const int mp = std::min(n, std::max(l, std::min(opt.tile_bits, 11)));
+        for (auto &inv : involutions(phys)) plan.passes.push_back(make_perm_pass(n, inv, mp, l));
+    }
+    return plan;
+}
+
+}  // namespace sv

@@ -1,0 +1,281 @@
+// Internal declarations of libsv: the lowered gate IR, the pass plan, the
+// context / state objects and the kernel launchers.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <complex>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sv.h"
+
+namespace sv {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+
+struct Error {
+    int code;
+    std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string &msg);
+void set_last_error(const std::string &msg);
+
+#define SV_HIP(call)                                                          \
+    do {                                                                      \
+        hipError_t e_ = (call);                                               \
+        if (e_ != hipSuccess)                                                 \
+            ::sv::fail(SV_EDEVICE, std::string(#call) + ": " +                \
+                                       hipGetErrorString(e_));                \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Lowered operations.  Every gate lowers to exactly one Op acting on index
+// BIT positions (bit = n-1-qubit).  Matrices are computed on the host in FP64
+// and rounded once to the state's precision when uploaded.
+// ---------------------------------------------------------------------------
+
+enum OpKind : int32_t {
+    OP_U1 = 0,      // 2x2 matrix m[0..3] on bit a, where all cmask bits set
+    OP_U2 = 1,      // 4x4 matrix m[0..15] on bits (a, b), a = high matrix bit
+    OP_DIAG = 2,    // amplitude *= m[2*bit_a + bit_b] (b < 0: m[bit_a]), cmask
+    OP_LADDER = 3,  // if bit a set: amplitude *= exp(2 pi i turns (k & lmask))
+    OP_SWAP = 4,    // exchange bits a and b, where all cmask bits set
+    OP_XPERM = 5,   // CNOT-like: swap pair on bit a where all cmask bits set
+};
+
+struct Op {
+    int32_t kind = OP_U1;
+    int32_t a = -1, b = -1;
+    uint64_t cmask = 0;
+    uint64_t lmask = 0;
+    double turns = 0.0;
+    double ang = 0.0;      // CP: its angle (kept exact for ladder merging)
+    cd m[16];
+    int32_t gate = -1;     // source gate index (-1 = synthesised)
+    bool param = false;    // angle depends on the parameter vector
+    bool diagonal() const { return kind == OP_DIAG || kind == OP_LADDER; }
+};
+
+// Device copy of an op in precision R (float for complex64, double for
+// complex128).  la / lb are the tile-local positions of a / b in the pass
+// that holds the op; lcmask / gcmask split cmask into tile-local (re-indexed)
+// and fixed-per-tile parts.
+template <typename R>
+struct alignas(16) DevOp {
+    int32_t kind, a, b, la, lb;
+    int32_t pad0, pad1, pad2;
+    uint64_t cmask;   // global positions
+    uint64_t lcmask;  // local positions of the controls inside the tile
+    uint64_t gcmask;  // controls outside the tile (constant per tile)
+    uint64_t lmask;
+    double turns;
+    double pad3;
+    R m[32];          // complex entries as (re, im)
+};
+
+// Lower one validated gate (kind, qubits, effective angles, user matrix) to
+// its op.  mat = 8 or 32 doubles for MAT1 / MAT2.
+Op lower_gate(int n, const sv_gate &g, const double ang[3], const double *mat,
+              int gate_index);
+
+// Gate list of Alg. "Gate-Based QFT" over n qubits.
+std::vector<sv_gate> qft_gates(int n);
+
+// Effective angles of gate g (angle[k] + params[param_idx[k]]).
+void effective_angles(const sv_gate &g, const double *params, double out[3]);
+
+// ---------------------------------------------------------------------------
+// Plan: passes over the state.  A TILE pass loads 2^m amplitudes whose index
+// bits outside the tile are fixed (one workgroup per tile), runs its ops in
+// LDS and writes the tile back.  A PERM pass exchanges bit pairs in place.
+// ---------------------------------------------------------------------------
+
+enum PassKind : int32_t { PASS_TILE = 0, PASS_PERM = 1, PASS_SWEEP = 2 };
+
+struct Pass {
+    int32_t kind = PASS_TILE;
+    int32_t m = 0;                    // tile bits
+    int32_t l = 0;                    // low identity bits (coalescing run)
+    std::vector<int> local_bits;      // global bit of local bit i, i < m
+    std::vector<int> free_bits;       // global bits outside the tile
+    std::vector<Op> ops;              // ops of the pass, in order
+    std::vector<std::pair<int, int>> swaps;  // PERM: disjoint bit pairs
+};
+
+struct PlanOptions {
+    int tile_bits = 13;    // m
+    int low_bits = 5;      // l
+    bool fuse = true;      // false: one sweep op per gate
+};
+
+struct Plan {
+    int n = 0;
+    std::vector<Pass> passes;
+    int n_gate_ops = 0;
+};
+
+// Build passes from ops.  SWAP ops are absorbed into a bit relabelling and
+// the final layout is restored by PERM passes.
+Plan make_plan(int n, const std::vector<Op> &ops, const PlanOptions &opt);
+
+// Device pass descriptor.
+struct alignas(16) DevPass {
+    int32_t kind, m, l, nfree;
+    int32_t op_begin, op_end, nswap, pad;
+    int8_t local_bits[48];
+    int8_t free_bits[48];
+    int8_t swap_a[24];
+    int8_t swap_b[24];
+};
+
+// ---------------------------------------------------------------------------
+// Pauli sums lowered to masks (bit positions).
+// ---------------------------------------------------------------------------
+
+struct Term {
+    uint64_t x = 0, z = 0;  // bit masks of X/Y and Z/Y factors
+    int ny = 0;             // number of Y factors (mod 4)
+    double c = 0.0;
+};
+
+struct TermGroups {
+    // terms sorted into groups sharing x; order inside a group = term order
+    std::vector<uint64_t> gx;           // group x mask
+    std::vector<int> g_begin, g_end;    // ranges into `order`
+    std::vector<int> order;             // term indices
+    std::vector<Term> terms;            // as given
+};
+TermGroups lower_pauli_sum(const sv_pauli_sum &h);
+
+struct alignas(16) DevTerm {
+    uint64_t x, z;
+    int32_t ny, idx;    // idx = original term index
+    double c;
+};
+
+// ---------------------------------------------------------------------------
+// Context / state
+// ---------------------------------------------------------------------------
+
+struct ProfileEntry {
+    double ms = 0.0;
+    uint64_t launches = 0;
+    double bytes = 0.0;
+};
+
+struct DeviceBuffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    int cu_count = 0;
+    int tile_bits_c64 = 13, tile_bits_c128 = 12;
+    std::mutex mu;
+    // scratch buffers reused across calls (grown on demand)
+    std::map<std::string, DeviceBuffer> scratch;
+    // profiling
+    bool profile = false;
+    std::map<std::string, ProfileEntry> prof;
+    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> free_events;
+    std::vector<double> pending_bytes;
+};
+
+struct State {
+    Ctx *ctx = nullptr;
+    int n = 0;
+    int dtype = SV_C64;
+    void *ptr = nullptr;
+    bool owned = true;
+    size_t amp_bytes() const { return dtype == SV_C64 ? 8 : 16; }
+    size_t bytes() const { return amp_bytes() << n; }
+};
+
+void *scratch(Ctx *ctx, const std::string &name, size_t bytes);
+
+// Profiling hooks around a launch.
+struct LaunchScope {
+    Ctx *ctx;
+    const char *name;
+    double bytes;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    LaunchScope(Ctx *c, const char *nm, double b);
+    ~LaunchScope();
+};
+void profile_collect(Ctx *ctx);
+
+// ---------------------------------------------------------------------------
+// Executors (implemented in the .hip files)
+// ---------------------------------------------------------------------------
+
+// Run a plan on one state (ops uploaded per call).
+void run_plan(Ctx *ctx, State *st, const Plan &plan);
+// One-gate-per-launch sweeps (the plain path).
+void run_unfused(Ctx *ctx, State *st, const std::vector<Op> &ops);
+void set_zero_state(Ctx *ctx, void *psi, int n, int dtype);
+void device_norm2(Ctx *ctx, const void *psi, int n, int dtype, double *out);
+void device_scale(Ctx *ctx, void *psi, int n, int dtype, double s);
+// FP64 expectation of a lowered Pauli sum: fills per-term values (already
+// divided by the norm) and the energy.
+void device_expectation(Ctx *ctx, const void *psi, int n, int dtype,
+                        const TermGroups &tg, double *energy,
+                        double *term_values, double *norm2);
+
+// Batched evaluation of many independent circuits, each from |0...0>.
+// Circuit c runs op set `op_set`, with op `ovr_index` of that set replaced
+// by `ovr_op` (-1 = none; the parameter-shift copies), and reduces the
+// energy of Hamiltonian `ham`.
+struct BatchCircuit {
+    int n = 0;
+    int op_set = 0;
+    int ovr_index = -1;
+    Op ovr_op;
+    int ham = 0;
+    int out_slot = -1;   // energy slot in the output array (-1 = own index)
+};
+struct BatchSpec {
+    int dtype = SV_C64;
+    std::vector<std::vector<Op>> op_sets;
+    std::vector<TermGroups> hams;
+    std::vector<BatchCircuit> circuits;
+    // optional gradient combination: grad[i] = sum_j w[j] * E[circ[j]],
+    // j in [comb_begin[i], comb_begin[i+1])
+    std::vector<int> comb_begin, comb_circ;
+    std::vector<double> comb_w;
+};
+// Energies of all circuits (and the combined gradient when requested).
+void run_batch(Ctx *ctx, const BatchSpec &spec, uint32_t flags,
+               std::vector<double> &energies, std::vector<double> &grad);
+// Device-resident variant: energies go to d_E[out_slot]; nothing is
+// synchronised.
+void run_batch_dev(Ctx *ctx, const BatchSpec &spec, uint32_t flags, double *d_E);
+// grad[i] = sum_j w[j] * E[circ[j]] on the device (fixed order).
+void combine_dev(Ctx *ctx, const double *d_E, const std::vector<int> &beg,
+                 const std::vector<int> &circ, const std::vector<double> &w,
+                 double *d_grad);
+BatchSpec psr_spec(const sv_circuit *c, const double *params, size_t n_params,
+                   const sv_pauli_sum *ham, int dtype, bool want_grad);
+int small_batch_max_qubits(int dtype);
+
+// Host validation shared by the entry points (lower.cpp).
+void check_circuit(const sv_circuit *c, const double *params, size_t n_params);
+void check_pauli_sum(const sv_pauli_sum *h, int n);
+const std::string &last_error();
+int gate_arity(int kind);
+int gate_n_angles(int kind);
+
+}  // namespace sv
