@@ -19,8 +19,14 @@ ARCH = "gfx950"
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+# -simplifycfg-sink-common=false: the stage engine dispatches each op to one
+# of several fully unrolled register-group bodies; sinking their common
+# stores would merge them into a dynamically indexed stack object (scratch
+# traffic on every group).  Keeping the bodies separate keeps the groups in
+# VGPRs.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-          "-packed-fp32-ops", "-munsafe-fp-atomics"]
+          "-packed-fp32-ops", "-munsafe-fp-atomics",
+          "-mllvm", "-simplifycfg-sink-common=false"]
 
 
 def sources():

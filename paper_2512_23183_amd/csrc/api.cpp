@@ -69,6 +69,7 @@ void apply_ops(State *st, const std::vector<Op> &ops, uint32_t flags) {
     } else {
         PlanOptions po;
         po.tile_bits = st->dtype == SV_C64 ? ctx->tile_bits_c64 : ctx->tile_bits_c128;
+        po.perm_bits = st->dtype == SV_C64 ? 12 : 11;
         run_plan(ctx, st, make_plan(st->n, ops, po));
     }
     if (ctx->profile) {

@@ -22,7 +22,7 @@ namespace sv {
 struct alignas(16) DevCirc {
     int32_t n, op_begin, op_end, ovr_index;  // ovr_index: absolute op index or -1
     int32_t ovr_slot, grp_begin, grp_end, T;
-    int32_t coeff_begin, out_slot, pad0, pad1;
+    int32_t coeff_begin, out_slot, stage_begin, stage_end;
 };
 
 constexpr int SMALL_TPB = 256;
@@ -34,20 +34,21 @@ __global__ void k_fill_u32(unsigned *p, unsigned v, int count) {
     if (i < count) p[i] = v;
 }
 
-// LDS: state[2^max_n], red[TPB/64], vals[max_T + 1].
+// LDS: state[2^max_n], red[TPB/64], vals[max_T + 1], ladder tables.
 template <typename R>
 __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
     const DevCirc *__restrict__ circ, int ncirc, unsigned *__restrict__ counter,
-    const DevOp<R> *__restrict__ ops, const DevOp<R> *__restrict__ ovr_ops,
+    const DevOp<R> *__restrict__ ops, const DevStage *__restrict__ stages, const V2<R> *__restrict__ ltab,
+    const DevOp<R> *__restrict__ ovr_ops,
     const DevTerm *__restrict__ terms, const int *__restrict__ gbeg, const int *__restrict__ gend,
     const uint64_t *__restrict__ gx, const double *__restrict__ coeffs, double *__restrict__ energies,
-    int max_n) {
+    int max_n, int max_T) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cur;
     V2<R> *st = reinterpret_cast<V2<R> *>(smem);
     double *red = reinterpret_cast<double *>(smem + (sizeof(V2<R>) << max_n));
     double *vals = red + SMALL_TPB / 64;
-    auto gidx = [](uint32_t j) -> uint64_t { return j; };
+    V2<R> *tabs = reinterpret_cast<V2<R> *>(vals + ((max_T + 2) & ~1));
     for (;;) {
         if (threadIdx.x == 0) cur = (int)atomicAdd(counter, 1u);
         __syncthreads();
@@ -63,8 +64,19 @@ __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
             v.y = 0;
             st[j] = v;
         }
-        lds_apply_list<R, SMALL_TPB>(st, n, ops, C.op_begin, C.op_end, 0, gidx, C.ovr_index,
-                                     ovr_ops + (C.ovr_slot > 0 ? C.ovr_slot : 0));
+        TileCtx<R> tc;
+        tc.m = n;
+        tc.l = n < 5 ? n : 5;
+        tc.lowm = (1u << tc.l) - 1;
+        tc.ident = true;
+        tc.base = 0;
+        tc.hi_off = nullptr;
+        tc.tabs = tabs;
+        tc.lt = ladder_split(n);
+        tc.tstride = (1 << tc.lt) + (1 << (n - tc.lt));
+        __syncthreads();
+        run_stages<R, SMALL_TPB>(st, nullptr, tc, stages, C.stage_begin, C.stage_end, ops, ltab,
+                                    C.ovr_index, ovr_ops + C.ovr_slot);
         for (int g = C.grp_begin; g < C.grp_end; ++g) {
             const uint64_t x = gx[g];
             const int hb = x ? 63 - __clzll(x) : -1;
@@ -141,18 +153,32 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     std::vector<double> coeffs;
     std::vector<DevCirc> circ;
     std::vector<DevOp<R>> ovr;
-    int max_n = 1, max_T = 0;
+    std::vector<DevStage> stages;
+    std::vector<V2<R>> ltab;
+    std::vector<int> set_sb(spec.op_sets.size(), -1), set_se(spec.op_sets.size(), -1);
+    int max_n = 3, max_T = 0;
     for (int c : idx) {
         const BatchCircuit &bc = spec.circuits[c];
+        // states of fewer than 3 qubits run as 3-qubit states whose extra
+        // (most significant) bits stay |0>: energies are unchanged
+        const int n_eff = std::max(bc.n, 3);
         if (set_begin[bc.op_set] < 0) {
             set_begin[bc.op_set] = (int)dops.size();
-            std::vector<int> loc(all_local.begin(), all_local.begin() + bc.n);
+            std::vector<int> loc(all_local.begin(), all_local.begin() + n_eff);
+            std::vector<uint64_t> hoff;
             for (const Op &op : spec.op_sets[bc.op_set]) {
                 DevOp<R> d = to_dev<R>(op);
                 localise(d, loc);
+                if (op.kind == OP_LADDER) {
+                    if (hoff.empty()) hoff = hi_offsets(loc, ladder_split(n_eff));
+                    append_ladder_tables<R>(d, op, n_eff, hoff, ltab);
+                }
                 dops.push_back(d);
             }
             set_end[bc.op_set] = (int)dops.size();
+            set_sb[bc.op_set] = (int)stages.size();
+            build_stages<R>(dops, set_begin[bc.op_set], set_end[bc.op_set], n_eff, stages);
+            set_se[bc.op_set] = (int)stages.size();
         }
         if (ham_gb[bc.ham] < 0) {
             DevTerms dt = build_dev_terms(spec.hams[bc.ham]);
@@ -171,17 +197,26 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
         }
         DevCirc d;
         std::memset(&d, 0, sizeof d);
-        d.n = bc.n;
+        d.n = n_eff;
         d.op_begin = set_begin[bc.op_set];
         d.op_end = set_end[bc.op_set];
+        d.stage_begin = set_sb[bc.op_set];
+        d.stage_end = set_se[bc.op_set];
         d.ovr_index = -1;
         d.ovr_slot = 0;
         if (bc.ovr_index >= 0) {
             d.ovr_index = d.op_begin + bc.ovr_index;
             d.ovr_slot = (int)ovr.size();
-            std::vector<int> loc(all_local.begin(), all_local.begin() + bc.n);
+            const DevOp<R> &basep = dops[d.ovr_index];
             DevOp<R> o = to_dev<R>(bc.ovr_op);
-            localise(o, loc);
+            // same gate and qubits as the base op: reuse its placement
+            o.la = basep.la;
+            o.lb = basep.lb;
+            o.ra = basep.ra;
+            o.rb = basep.rb;
+            o.tslot = basep.tslot;
+            o.lcmask = basep.lcmask;
+            o.gcmask = basep.gcmask;
             ovr.push_back(o);
         }
         d.grp_begin = ham_gb[bc.ham];
@@ -190,7 +225,7 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
         d.coeff_begin = ham_cb[bc.ham];
         d.out_slot = bc.out_slot >= 0 ? bc.out_slot : c;
         circ.push_back(d);
-        max_n = std::max(max_n, bc.n);
+        max_n = std::max(max_n, n_eff);
         max_T = std::max(max_T, d.T);
     }
     if (ovr.empty()) ovr.resize(1);
@@ -201,6 +236,8 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     Blob blob;
     const size_t o_c = blob.add(circ.data(), circ.size() * sizeof(DevCirc));
     const size_t o_ops = blob.add(dops.data(), dops.size() * sizeof(DevOp<R>));
+    const size_t o_stg = blob.add(stages.data(), stages.size() * sizeof(DevStage));
+    const size_t o_lt = blob.add(ltab.data(), ltab.size() * sizeof(V2<R>));
     const size_t o_ovr = blob.add(ovr.data(), ovr.size() * sizeof(DevOp<R>));
     const size_t o_t = blob.add(terms.data(), terms.size() * sizeof(DevTerm));
     const size_t o_gb = blob.add(gbeg.data(), gbeg.size() * 4);
@@ -212,7 +249,9 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     upload(ctx, base, blob.host.data(), blob.host.size());
     unsigned *d_cnt = (unsigned *)(base + o_cnt);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, ctx->stream, d_cnt, 0u, 1);
-    const size_t lds = (sizeof(V2<R>) << max_n) + 8 * (SMALL_TPB / 64) + 8 * (max_T + 1);
+    const int lts = ladder_split(max_n);
+    const size_t lds = (sizeof(V2<R>) << max_n) + 8 * (SMALL_TPB / 64) + 8 * ((max_T + 2) & ~1) +
+                       STAGE_MAX_LADDERS * sizeof(V2<R>) * ((1u << lts) + (1u << (max_n - lts)) + 1);
     set_lds_limit((const void *)k_small_batch<R>, lds);
     const int nc = (int)circ.size();
     const int per_cu = lds <= 40 * 1024 ? 4 : lds <= 80 * 1024 ? 2 : 1;
@@ -222,9 +261,10 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     LaunchScope ls(ctx, "small_batch", bytes);
     hipLaunchKernelGGL(k_small_batch<R>, dim3(grid), dim3(SMALL_TPB), lds, ctx->stream,
                        (const DevCirc *)(base + o_c), nc, d_cnt, (const DevOp<R> *)(base + o_ops),
-                       (const DevOp<R> *)(base + o_ovr), (const DevTerm *)(base + o_t),
-                       (const int *)(base + o_gb), (const int *)(base + o_ge),
-                       (const uint64_t *)(base + o_gx), (const double *)(base + o_cf), d_E, max_n);
+                       (const DevStage *)(base + o_stg), (const V2<R> *)(base + o_lt),
+                       (const DevOp<R> *)(base + o_ovr),
+                       (const DevTerm *)(base + o_t), (const int *)(base + o_gb), (const int *)(base + o_ge),
+                       (const uint64_t *)(base + o_gx), (const double *)(base + o_cf), d_E, max_n, max_T);
     SV_HIP(hipGetLastError());
 }
 
@@ -254,6 +294,7 @@ void run_large_sequential(Ctx *ctx, const BatchSpec &spec, const std::vector<int
         } else {
             PlanOptions po;
             po.tile_bits = spec.dtype == SV_C64 ? ctx->tile_bits_c64 : ctx->tile_bits_c128;
+            po.perm_bits = spec.dtype == SV_C64 ? 12 : 11;
             run_plan(ctx, &st, make_plan(bc.n, ops, po));
         }
         if (!have[bc.ham]) {

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "sv_internal.h"
@@ -97,113 +98,401 @@ inline std::vector<int> bits_of(uint64_t m) {
 }
 
 // ---------------------------------------------------------------------------
-// Ops applied to a tile held in LDS.  `gidx(j)` maps a local index to the
-// global amplitude index (diagonal ops use it).  Work assignment: element
-// ops use j = tid + s*TPB, pair ops p = tid + s*TPB over the reduced space.
+// Stage engine.  A tile holds 2^m amplitudes; local index j maps to the
+// global index gaddr(j) = base | hi_off[j >> l] | (j & lowm) (or j itself for
+// a whole state in LDS).  A stage takes 8-amplitude groups that differ only
+// in its three register bits, loads each group into registers, applies the
+// stage's ops there and stores it back -- one LDS (or HBM) round trip for
+// up to three mixing gates and any number of diagonal ones.
 // ---------------------------------------------------------------------------
 
-template <typename R, int TPB, typename GI>
-__device__ __forceinline__ void lds_apply(V2<R> *tile, int m, const DevOp<R> &op, uint64_t tile_base,
-                                          GI gidx) {
-    const uint32_t T = 1u << m;
-    const int tid = threadIdx.x;
-    const int kind = op.kind;
-    if (kind == OP_U1 || kind == OP_XPERM) {
-        if ((tile_base & op.gcmask) != op.gcmask) return;
-        const int la = op.la;
-        const uint32_t lc = (uint32_t)op.lcmask;
-        const uint32_t lo = (1u << la) - 1;
-        if (kind == OP_XPERM) {
-            for (uint32_t p = tid; p < T / 2; p += TPB) {
-                const uint32_t i0 = ((p & ~lo) << 1) | (p & lo);
-                if ((i0 & lc) != lc) continue;
-                const uint32_t i1 = i0 | (1u << la);
-                const V2<R> x = tile[i0], y = tile[i1];
-                tile[i0] = y;
-                tile[i1] = x;
-            }
-        } else {
-            const V2<R> m0 = mat_at(op, 0), m1 = mat_at(op, 1), m2 = mat_at(op, 2), m3 = mat_at(op, 3);
-            for (uint32_t p = tid; p < T / 2; p += TPB) {
-                const uint32_t i0 = ((p & ~lo) << 1) | (p & lo);
-                if ((i0 & lc) != lc) continue;
-                const uint32_t i1 = i0 | (1u << la);
-                const V2<R> x = tile[i0], y = tile[i1];
-                tile[i0] = cmac2(m0, x, m1, y);
-                tile[i1] = cmac2(m2, x, m3, y);
-            }
-        }
-    } else if (kind == OP_U2 || kind == OP_SWAP) {
-        if ((tile_base & op.gcmask) != op.gcmask) return;
-        const int la = op.la, lb = op.lb;
-        const int p0 = la < lb ? la : lb, p1 = la < lb ? lb : la;
-        const uint32_t lc = (uint32_t)op.lcmask;
-        for (uint32_t p = tid; p < T / 4; p += TPB) {
-            uint32_t k = ((p >> p0) << (p0 + 1)) | (p & ((1u << p0) - 1));
-            k = ((k >> p1) << (p1 + 1)) | (k & ((1u << p1) - 1));
-            if ((k & lc) != lc) continue;
-            if (kind == OP_SWAP) {
-                const uint32_t i = k | (1u << la), j = k | (1u << lb);
-                const V2<R> x = tile[i], y = tile[j];
-                tile[i] = y;
-                tile[j] = x;
-            } else {
-                const uint32_t idx[4] = {k, k | (1u << lb), k | (1u << la), k | (1u << la) | (1u << lb)};
-                V2<R> v[4], w[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = tile[idx[i]];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    V2<R> acc = cmul(mat_at(op, 4 * i), v[0]);
-#pragma unroll
-                    for (int jj = 1; jj < 4; ++jj) {
-                        V2<R> t = cmul(mat_at(op, 4 * i + jj), v[jj]);
-                        acc.x += t.x;
-                        acc.y += t.y;
-                    }
-                    w[i] = acc;
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) tile[idx[i]] = w[i];
-            }
-        }
-    } else if (kind == OP_DIAG) {
-        const int a = op.a, b = op.b;
-        const uint64_t cm = op.cmask;
-        const V2<R> d0 = mat_at(op, 0), d1 = mat_at(op, 1), d2 = mat_at(op, 2), d3 = mat_at(op, 3);
-        for (uint32_t j = tid; j < T; j += TPB) {
-            const uint64_t k = gidx(j);
-            if ((k & cm) != cm) continue;
-            int idx = (int)((k >> a) & 1);
-            if (b >= 0) idx = 2 * idx + (int)((k >> b) & 1);
-            const V2<R> f = idx == 0 ? d0 : idx == 1 ? d1 : idx == 2 ? d2 : d3;
-            tile[j] = cmul(tile[j], f);
-        }
-    } else if (kind == OP_LADDER) {
-        const int a = op.a;
-        const uint64_t lm = op.lmask;
-        const double tu = op.turns;
-        for (uint32_t j = tid; j < T; j += TPB) {
-            const uint64_t k = gidx(j);
-            if (!((k >> a) & 1)) continue;
-            tile[j] = cmul(tile[j], ladder_phase<R>(tu, k & lm));
-        }
+template <typename R>
+struct TileCtx {
+    int m, l;
+    uint32_t lowm;
+    bool ident;               // global index == local index
+    uint64_t base;            // global bits fixed for this tile
+    const uint64_t *hi_off;   // LDS: global offset of the high local bits
+    V2<R> *tabs;              // LDS: ladder phase tables
+    int lt;                   // table split: low table over local bits < lt
+    int tstride;              // entries per table slot (2^lt + 2^(m-lt))
+};
+
+// Low-part width of the ladder tables (local bits below it are global bits).
+__host__ __device__ constexpr int ladder_split(int m) { return m < 5 ? m : 5; }
+
+template <typename R>
+__device__ __forceinline__ uint64_t gaddr(const TileCtx<R> &tc, uint32_t j) {
+    return tc.ident ? (uint64_t)j : (tc.base | tc.hi_off[j >> tc.l] | (uint64_t)(j & tc.lowm));
+}
+
+__device__ __forceinline__ uint32_t ins0(uint32_t x, int p) {
+    return ((x >> p) << (p + 1)) | (x & ((1u << p) - 1));
+}
+
+// Ladder phase tables of a stage.  The host builds, per ladder, the
+// tile-independent tables TLc[v] = exp(2 pi i tau (v & M)) over the 2^lt
+// lowest local bits and THc[h] = exp(2 pi i tau (off(h << lt) & M)) over the
+// remaining local bits (off = global offset within the tile).  Per tile the
+// factor G = exp(2 pi i tau (base & M)) of the fixed bits is folded into TH;
+// the phase of local index j is then TL[j & (2^lt - 1)] * TH[j >> lt].
+template <typename R, int TPB>
+__device__ __forceinline__ void build_ladder_tables(const TileCtx<R> &tc, const DevStage &S,
+                                                    const DevOp<R> *ops, const V2<R> *__restrict__ ltab) {
+    V2<R> *Gs = tc.tabs + STAGE_MAX_LADDERS * tc.tstride;
+    if ((int)threadIdx.x < S.nlad) {
+        const DevOp<R> &op = ops[S.lad[threadIdx.x]];
+        Gs[threadIdx.x] = ladder_phase<R>(op.turns, tc.base & op.lmask);
+    }
+    __syncthreads();
+    const int nl = 1 << tc.lt;
+    for (int s = 0; s < S.nlad; ++s) {
+        const DevOp<R> &op = ops[S.lad[s]];
+        const V2<R> *src = ltab + op.tab;
+        const V2<R> G = Gs[s];
+        V2<R> *T = tc.tabs + s * tc.tstride;
+        for (int i = threadIdx.x; i < tc.tstride; i += TPB) T[i] = i < nl ? src[i] : cmul(G, src[i]);
     }
 }
 
-template <typename R, int TPB, typename GI>
-__device__ __forceinline__ void lds_apply_list(V2<R> *tile, int m, const DevOp<R> *ops, int begin,
-                                               int end, uint64_t tile_base, GI gidx,
-                                               int ovr_index = -1, const DevOp<R> *ovr = nullptr) {
-    bool prev_diag = false;
-    for (int o = begin; o < end; ++o) {
-        const DevOp<R> &op = (o == ovr_index) ? *ovr : ops[o];
-        const bool d = op.kind == OP_DIAG || op.kind == OP_LADDER;
-        if (!(d && prev_diag)) __syncthreads();
-        lds_apply<R, TPB>(tile, m, op, tile_base, gidx);
-        prev_diag = d;
+// Global bit mask of local bit r.
+template <typename R>
+__device__ __forceinline__ uint64_t gbit(const TileCtx<R> &tc, int r) {
+    if (tc.ident || r < tc.l) return 1ull << r;
+    return tc.hi_off[1u << (r - tc.l)];
+}
+
+// Offset of element e (bits of e -> register bits 0, 1, 2) given the three
+// per-register offsets; e is a constant after unrolling.
+template <typename T>
+__device__ __forceinline__ T eoff(int e, T o0, T o1, T o2) {
+    return ((e & 1) ? o0 : (T)0) | ((e & 2) ? o1 : (T)0) | ((e & 4) ? o2 : (T)0);
+}
+
+template <typename V>
+__device__ __forceinline__ V vsel(bool c, V a, V b) {
+    V r;
+    r.x = c ? a.x : b.x;
+    r.y = c ? a.y : b.y;
+    return r;
+}
+
+// One group of 8 amplitudes held in registers as eight named values (no
+// array: an array indexed from several dispatch branches can be merged by
+// the optimiser into a dynamically indexed stack object).
+template <typename R>
+struct Grp {
+    V2<R> e0, e1, e2, e3, e4, e5, e6, e7;
+    uint32_t j0;   // local index of element 0
+    uint64_t k0;   // global index of element 0
+    bool live;
+};
+
+template <int E, typename R>
+__device__ __forceinline__ V2<R> &el(Grp<R> &g) {
+    if constexpr (E == 0) return g.e0;
+    else if constexpr (E == 1) return g.e1;
+    else if constexpr (E == 2) return g.e2;
+    else if constexpr (E == 3) return g.e3;
+    else if constexpr (E == 4) return g.e4;
+    else if constexpr (E == 5) return g.e5;
+    else if constexpr (E == 6) return g.e6;
+    else return g.e7;
+}
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
     }
-    __syncthreads();
+}
+
+template <int E>
+__device__ __forceinline__ uint32_t loff(const uint32_t (&L)[3]) {
+    return ((E & 1) ? L[0] : 0u) | ((E & 2) ? L[1] : 0u) | ((E & 4) ? L[2] : 0u);
+}
+template <int E>
+__device__ __forceinline__ uint64_t goff(const uint64_t (&G)[3]) {
+    return ((E & 1) ? G[0] : 0ull) | ((E & 2) ? G[1] : 0ull) | ((E & 4) ? G[2] : 0ull);
+}
+
+// 2x2 on register bit I.  K: 0 complex matrix, 1 real matrix, 2 exchange
+// (X / CNOT).  CTRL: some control bits are local (checked per pair against
+// lc); otherwise the op applies to every pair.
+template <int I, int K, bool CTRL, typename R>
+__device__ __forceinline__ void rg_u1(Grp<R> &g, uint32_t lc, const uint32_t (&L)[3], V2<R> m0, V2<R> m1,
+                                      V2<R> m2, V2<R> m3) {
+    static_for<0, 8>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        if constexpr (!(e & (1 << I))) {
+            constexpr int f = e | (1 << I);
+            V2<R> &px = el<e>(g), &py = el<f>(g);
+            const V2<R> x = px, y = py;
+            V2<R> nx, ny;
+            if constexpr (K == 2) {
+                nx = y;
+                ny = x;
+            } else if constexpr (K == 1) {
+                nx.x = m0.x * x.x + m1.x * y.x;
+                nx.y = m0.x * x.y + m1.x * y.y;
+                ny.x = m2.x * x.x + m3.x * y.x;
+                ny.y = m2.x * x.y + m3.x * y.y;
+            } else {
+                nx = cmac2(m0, x, m1, y);
+                ny = cmac2(m2, x, m3, y);
+            }
+            if constexpr (CTRL) {
+                const bool ok = ((g.j0 | loff<e>(L)) & lc) == lc;
+                nx = vsel(ok, nx, x);
+                ny = vsel(ok, ny, y);
+            }
+            px = nx;
+            py = ny;
+        }
+    });
+}
+
+template <int K, bool CTRL, typename R>
+__device__ __forceinline__ void rg_u1_at(Grp<R> &g, uint32_t lc, const uint32_t (&L)[3], const DevOp<R> &op) {
+    const V2<R> m0 = mat_at(op, 0), m1 = mat_at(op, 1), m2 = mat_at(op, 2), m3 = mat_at(op, 3);
+    if (op.ra == 0) rg_u1<0, K, CTRL>(g, lc, L, m0, m1, m2, m3);
+    else if (op.ra == 1) rg_u1<1, K, CTRL>(g, lc, L, m0, m1, m2, m3);
+    else rg_u1<2, K, CTRL>(g, lc, L, m0, m1, m2, m3);
+}
+
+template <int K, typename R>
+__device__ __forceinline__ void rg_u1_dispatch(Grp<R> &g, const uint32_t (&L)[3], const DevOp<R> &op) {
+    const uint32_t lc = (uint32_t)op.lcmask;
+    if (lc) rg_u1_at<K, true>(g, lc, L, op);
+    else rg_u1_at<K, false>(g, lc, L, op);
+}
+
+// 4x4 on register bits A (high matrix bit) and B; plain exchange when !W.
+template <int A, int B, bool W, bool CTRL, typename R>
+__device__ __forceinline__ void rg_u2(Grp<R> &g, uint32_t lc, const uint32_t (&L)[3], const DevOp<R> &op) {
+    static_for<0, 8>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        if constexpr (!(e & ((1 << A) | (1 << B)))) {
+            constexpr int i01 = e | (1 << B), i10 = e | (1 << A), i11 = e | (1 << A) | (1 << B);
+            V2<R> &p0 = el<e>(g), &p1 = el<i01>(g), &p2 = el<i10>(g), &p3 = el<i11>(g);
+            const V2<R> x0 = p0, x1 = p1, x2 = p2, x3 = p3;
+            V2<R> w0, w1, w2, w3;
+            if constexpr (!W) {
+                w0 = x0;
+                w1 = x2;
+                w2 = x1;
+                w3 = x3;
+            } else {
+                auto row = [&](int r) {
+                    V2<R> acc = cmul(mat_at(op, 4 * r), x0);
+                    V2<R> t = cmul(mat_at(op, 4 * r + 1), x1);
+                    acc.x += t.x;
+                    acc.y += t.y;
+                    t = cmul(mat_at(op, 4 * r + 2), x2);
+                    acc.x += t.x;
+                    acc.y += t.y;
+                    t = cmul(mat_at(op, 4 * r + 3), x3);
+                    acc.x += t.x;
+                    acc.y += t.y;
+                    return acc;
+                };
+                w0 = row(0);
+                w1 = row(1);
+                w2 = row(2);
+                w3 = row(3);
+            }
+            if constexpr (CTRL) {
+                const bool ok = ((g.j0 | loff<e>(L)) & lc) == lc;
+                w0 = vsel(ok, w0, x0);
+                w1 = vsel(ok, w1, x1);
+                w2 = vsel(ok, w2, x2);
+                w3 = vsel(ok, w3, x3);
+            }
+            p0 = w0;
+            p1 = w1;
+            p2 = w2;
+            p3 = w3;
+        }
+    });
+}
+
+template <bool W, bool CTRL, typename R>
+__device__ __forceinline__ void rg_u2_at(Grp<R> &g, uint32_t lc, const uint32_t (&L)[3], const DevOp<R> &op) {
+    switch (op.ra * 3 + op.rb) {
+    case 1: rg_u2<0, 1, W, CTRL>(g, lc, L, op); break;
+    case 2: rg_u2<0, 2, W, CTRL>(g, lc, L, op); break;
+    case 3: rg_u2<1, 0, W, CTRL>(g, lc, L, op); break;
+    case 5: rg_u2<1, 2, W, CTRL>(g, lc, L, op); break;
+    case 6: rg_u2<2, 0, W, CTRL>(g, lc, L, op); break;
+    case 7: rg_u2<2, 1, W, CTRL>(g, lc, L, op); break;
+    default: break;
+    }
+}
+
+template <bool W, typename R>
+__device__ __forceinline__ void rg_u2_dispatch(Grp<R> &g, uint32_t lc, const uint32_t (&L)[3], const DevOp<R> &op) {
+    if (lc) rg_u2_at<W, true>(g, lc, L, op);
+    else rg_u2_at<W, false>(g, lc, L, op);
+}
+
+// Diagonal factor d[2*bit_a + bit_b] (or d[bit_a]) where all cmask bits
+// set.  PAT: only the all-ones pattern has a factor != 1 (CZ, CP, controlled
+// phases): then a single condition and multiply (a sign flip when NEG).
+template <bool PAT, bool NEG, typename R>
+__device__ __forceinline__ void rg_diag(Grp<R> &g, const uint64_t (&G)[3], const DevOp<R> &op) {
+    const int a = op.a, b = op.b;
+    const uint64_t cm = op.cmask;
+    const uint64_t all = cm | (1ull << a) | (b >= 0 ? (1ull << b) : 0ull);
+    const V2<R> d0 = mat_at(op, 0), d1 = mat_at(op, 1), d2 = mat_at(op, 2), d3 = mat_at(op, 3);
+    const V2<R> dl = b >= 0 ? d3 : d1;
+    static_for<0, 8>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        V2<R> &v = el<e>(g);
+        const uint64_t k = g.k0 | goff<e>(G);
+        if constexpr (PAT) {
+            const bool on = (k & all) == all;
+            if constexpr (NEG) {
+                v.x = on ? -v.x : v.x;
+                v.y = on ? -v.y : v.y;
+            } else {
+                v = vsel(on, cmul(v, dl), v);
+            }
+        } else {
+            const bool ba = (k >> a) & 1;
+            V2<R> f;
+            if (b >= 0) {
+                const bool bb = (k >> b) & 1;
+                f = vsel(ba, vsel(bb, d3, d2), vsel(bb, d1, d0));
+            } else {
+                f = vsel(ba, d1, d0);
+            }
+            const bool on = (k & cm) == cm;
+            v = vsel(on, cmul(v, f), v);
+        }
+    });
+}
+
+// Ladder: where bit a is set, multiply by TL[j & ltm] * TH[j >> lt].  When
+// a is register bit RA (template), exactly the elements with that bit set
+// are touched; otherwise (RA < 0) bit a is the same for the whole group.
+template <int RA, typename R>
+__device__ __forceinline__ void rg_ladder(Grp<R> &g, const uint32_t (&L)[3], const DevOp<R> &op,
+                                          const TileCtx<R> &tc) {
+    const V2<R> *T = tc.tabs + op.tslot * tc.tstride;
+    const V2<R> *TH = T + (1 << tc.lt);
+    const uint32_t ltm = (1u << tc.lt) - 1;
+    if (RA < 0 && !((g.k0 >> op.a) & 1)) return;
+    static_for<0, 8>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        if constexpr (RA < 0 || (e & (1 << (RA < 0 ? 0 : RA)))) {
+            const uint32_t je = g.j0 | loff<e>(L);
+            V2<R> &v = el<e>(g);
+            v = cmul(v, cmul(T[je & ltm], TH[je >> tc.lt]));
+        }
+    });
+}
+
+// MODE bit 0: read the group from global memory (else from the LDS tile);
+// MODE bit 1: write it to global memory (else to the LDS tile).  Each
+// thread handles groups threadIdx.x, +TPB, ... one at a time.
+template <typename R, int TPB, int MODE>
+__device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
+                                          const DevStage &S, const DevOp<R> *__restrict__ ops,
+                                          int ovr_index, const DevOp<R> *ovr) {
+    const uint32_t nitems = (1u << tc.m) >> 3;
+    const int r0 = S.r0, r1 = S.r1, r2 = S.r2;
+    const uint32_t L[3] = {1u << r0, 1u << r1, 1u << r2};
+    const uint64_t G[3] = {gbit(tc, r0), gbit(tc, r1), gbit(tc, r2)};
+    for (uint32_t it = threadIdx.x; it < nitems; it += TPB) {
+        Grp<R> g;
+        g.live = true;
+        g.j0 = ins0(ins0(ins0(it, r0), r1), r2);
+        g.k0 = gaddr(tc, g.j0);
+        static_for<0, 8>([&](auto EC) {
+            constexpr int e = decltype(EC)::value;
+            if constexpr (MODE & 1) el<e>(g) = gpsi[g.k0 | goff<e>(G)];
+            else el<e>(g) = tile[g.j0 | loff<e>(L)];
+        });
+        for (int o = S.op_begin; o < S.op_end; ++o) {
+            const DevOp<R> &op = (o == ovr_index) ? *ovr : ops[o];
+            const int kind = op.kind;
+            if (kind == OP_U1 || kind == OP_XPERM) {
+                if ((tc.base & op.gcmask) != op.gcmask) continue;
+                if (kind == OP_XPERM) rg_u1_dispatch<2>(g, L, op);
+                else if (op.flags & OPF_REAL) rg_u1_dispatch<1>(g, L, op);
+                else rg_u1_dispatch<0>(g, L, op);
+            } else if (kind == OP_U2 || kind == OP_SWAP) {
+                if ((tc.base & op.gcmask) != op.gcmask) continue;
+                if (kind == OP_U2) rg_u2_dispatch<true>(g, (uint32_t)op.lcmask, L, op);
+                else rg_u2_dispatch<false>(g, (uint32_t)op.lcmask, L, op);
+            } else if (kind == OP_DIAG) {
+                if (op.flags & OPF_NEG) rg_diag<true, true>(g, G, op);
+                else if (op.flags & OPF_PAT) rg_diag<true, false>(g, G, op);
+                else rg_diag<false, false>(g, G, op);
+            } else if (kind == OP_LADDER) {
+                if (op.ra == 0) rg_ladder<0>(g, L, op, tc);
+                else if (op.ra == 1) rg_ladder<1>(g, L, op, tc);
+                else if (op.ra == 2) rg_ladder<2>(g, L, op, tc);
+                else rg_ladder<-1>(g, L, op, tc);
+            }
+        }
+        static_for<0, 8>([&](auto EC) {
+            constexpr int e = decltype(EC)::value;
+            if constexpr (MODE & 2) gpsi[g.k0 | goff<e>(G)] = el<e>(g);
+            else tile[g.j0 | loff<e>(L)] = el<e>(g);
+        });
+    }
+}
+
+// 16-byte access to two adjacent complex64 amplitudes / one complex128.
+template <typename R> struct Pair;
+template <> struct Pair<float> { using T = float4; };
+template <> struct Pair<double> { using T = double2; };
+__device__ __forceinline__ float4 pack_pair(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
+
+// Run stages [sb, se) of a tile.  With gpsi: a one-stage pass streams
+// HBM -> registers -> HBM; a multi-stage pass bulk-loads the tile into
+// LDS, runs every stage there and bulk-stores it.  Without gpsi everything
+// stays in the LDS tile.  NI = groups per thread per chunk; MAXA = 16-byte
+// accesses per thread for the bulk moves (2^m / (EPA * TPB) at most).
+template <typename R, int TPB>
+__device__ __forceinline__ void run_stages(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
+                                           const DevStage *__restrict__ stages, int sb, int se,
+                                           const DevOp<R> *__restrict__ ops, const V2<R> *__restrict__ ltab,
+                                           int ovr_index = -1, const DevOp<R> *ovr = nullptr) {
+    for (int s = sb; s < se; ++s) {
+        const DevStage &S = stages[s];
+        if (S.nlad) {
+            build_ladder_tables<R, TPB>(tc, S, ops, ltab);
+            __syncthreads();
+        }
+        const bool first = gpsi && s == sb, last = gpsi && s == se - 1;
+        if (first && last) run_stage<R, TPB, 3>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        else if (first) run_stage<R, TPB, 1>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        else if (last) run_stage<R, TPB, 2>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        else run_stage<R, TPB, 0>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        __syncthreads();
+    }
+}
+
+// Host: the tile-independent ladder tables of op d in a tile of m local bits
+// whose local index j has in-tile global offset off(j) (FP64, rounded once).
+template <typename R>
+inline void append_ladder_tables(DevOp<R> &d, const Op &op, int m, const std::vector<uint64_t> &off_of_hi,
+                                 std::vector<V2<R>> &ltab) {
+    const int lt = ladder_split(m);
+    d.tab = (int)ltab.size();
+    auto ph = [&](uint64_t v) {
+        double t = op.turns * (double)v;
+        t -= std::floor(t);
+        V2<R> z;
+        z.x = (R)std::cos(2.0 * M_PI * t);
+        z.y = (R)std::sin(2.0 * M_PI * t);
+        return z;
+    };
+    for (uint32_t v = 0; v < (1u << lt); ++v) ltab.push_back(ph(v & op.lmask));
+    for (uint32_t h = 0; h < (1u << (m - lt)); ++h) ltab.push_back(ph(off_of_hi[h] & op.lmask));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -266,11 +555,35 @@ inline DevOp<R> to_dev(const Op &op) {
     d.cmask = op.cmask;
     d.lmask = op.lmask;
     d.turns = op.turns;
+    d.tab = -1;
     for (int k = 0; k < 16; ++k) {
         d.m[2 * k] = (R)op.m[k].real();
         d.m[2 * k + 1] = (R)op.m[k].imag();
     }
+    if (op.kind == OP_U1 && op.m[0].imag() == 0.0 && op.m[1].imag() == 0.0 && op.m[2].imag() == 0.0 &&
+        op.m[3].imag() == 0.0)
+        d.flags |= OPF_REAL;
+    if (op.kind == OP_DIAG) {
+        const int last = op.b >= 0 ? 3 : 1;
+        bool pat = true;
+        for (int k = 0; k < last; ++k) pat &= op.m[k] == cd(1.0);
+        if (pat) d.flags |= OPF_PAT;
+        if (pat && op.m[last] == cd(-1.0)) d.flags |= OPF_NEG;
+    }
     return d;
+}
+
+// In-tile global offset of every combination of the local bits >= lt.
+inline std::vector<uint64_t> hi_offsets(const std::vector<int> &local_bits, int lt) {
+    const int m = (int)local_bits.size();
+    std::vector<uint64_t> out(1u << (m - lt));
+    for (uint32_t h = 0; h < out.size(); ++h) {
+        uint64_t o = 0;
+        for (int i = 0; i < m - lt; ++i)
+            if ((h >> i) & 1) o |= 1ull << local_bits[lt + i];
+        out[h] = o;
+    }
+    return out;
 }
 
 // Fill the tile-local fields of an op for a pass with local bits `lb`.
@@ -279,6 +592,7 @@ inline void localise(DevOp<R> &d, const std::vector<int> &local_bits) {
     int pos[64];
     for (int i = 0; i < 64; ++i) pos[i] = -1;
     for (size_t i = 0; i < local_bits.size(); ++i) pos[local_bits[i]] = (int)i;
+    if (d.kind == OP_DIAG || d.kind == OP_LADDER) d.la = d.a >= 0 ? pos[d.a] : -1;
     if (d.kind == OP_U1 || d.kind == OP_XPERM || d.kind == OP_U2 || d.kind == OP_SWAP) {
         d.la = pos[d.a];
         if (d.la < 0) fail(SV_EDEVICE, "internal: target bit outside tile");
@@ -297,6 +611,69 @@ inline void localise(DevOp<R> &d, const std::vector<int> &local_bits) {
 
 // Device term layout: terms in group order plus the norm pseudo-term
 // (x = z = 0, idx = T) appended to the x = 0 group (created if absent).
+
+// Group the localised ops [ob, oe) of a tile (m local bits, m >= 3) into
+// stages: a mixing op joins the current stage while the union of targets
+// stays within three bits; diagonal ops always join; at most
+// STAGE_MAX_LADDERS ladders per stage.  Fills ra / rb / tslot of every op.
+template <typename R>
+inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, int m, std::vector<DevStage> &out) {
+    int start = ob;
+    std::vector<int> regs;
+    int nlad = 0;
+    bool diag = false;
+    auto close = [&](int end) {
+        if (end <= start) return;
+        // fill with the highest unused local bits (keeps the low bits on the
+        // lanes, so global loads of a group stay coalesced)
+        for (int b = m - 1; b >= 0 && (int)regs.size() < 3; --b)
+            if (std::find(regs.begin(), regs.end(), b) == regs.end()) regs.push_back(b);
+        std::sort(regs.begin(), regs.end());
+        DevStage S;
+        std::memset(&S, 0, sizeof S);
+        S.r0 = regs[0];
+        S.r1 = regs[1];
+        S.r2 = regs[2];
+        S.op_begin = start;
+        S.op_end = end;
+        S.has_diag = diag ? 1 : 0;
+        int ls = 0;
+        for (int o = start; o < end; ++o) {
+            DevOp<R> &d = ops[o];
+            auto slot = [&](int lb) { return (int)(std::find(regs.begin(), regs.end(), lb) - regs.begin()); };
+            if (d.kind == OP_U1 || d.kind == OP_XPERM || d.kind == OP_U2 || d.kind == OP_SWAP) d.ra = slot(d.la);
+            if (d.kind == OP_U2 || d.kind == OP_SWAP) d.rb = slot(d.lb);
+            if (d.kind == OP_LADDER) {
+                d.tslot = ls;
+                S.lad[ls++] = o;
+                const int sl = d.la >= 0 ? slot(d.la) : 3;
+                d.ra = sl < 3 ? sl : -1;
+            }
+        }
+        S.nlad = ls;
+        out.push_back(S);
+        start = end;
+        regs.clear();
+        nlad = 0;
+        diag = false;
+    };
+    for (int o = ob; o < oe; ++o) {
+        const DevOp<R> &d = ops[o];
+        std::vector<int> tg;
+        if (d.kind == OP_U1 || d.kind == OP_XPERM) tg = {d.la};
+        else if (d.kind == OP_U2 || d.kind == OP_SWAP) tg = {d.la, d.lb};
+        int add = 0;
+        for (int t : tg)
+            if (std::find(regs.begin(), regs.end(), t) == regs.end()) ++add;
+        if ((int)regs.size() + add > 3 || (d.kind == OP_LADDER && nlad == STAGE_MAX_LADDERS)) close(o);
+        for (int t : tg)
+            if (std::find(regs.begin(), regs.end(), t) == regs.end()) regs.push_back(t);
+        if (d.kind == OP_LADDER) ++nlad;
+        if (d.kind == OP_DIAG || d.kind == OP_LADDER) diag = true;
+    }
+    close(oe);
+}
+
 struct DevTerms {
     std::vector<DevTerm> terms;
     std::vector<int> gbeg, gend;

@@ -147,46 +147,73 @@ __global__ __launch_bounds__(SWEEP_TPB) void k_scale(V2<R> *__restrict__ psi, ui
     }
 }
 
-constexpr int TILE_TPB = 256;
+constexpr int TILE_TPB = 512;
 
-// One workgroup per tile.  LDS: tile[2^m] then hi_off[2^(m-l)].
+// Deposit the bits of t into the set bits of mask (ascending): the global
+// index bits of tile t.  Uniform, so it runs on the scalar unit.
+__device__ __forceinline__ uint64_t deposit(uint64_t t, uint64_t mask) {
+    uint64_t r = 0;
+    while (mask) {
+        const uint64_t low = mask & (~mask + 1);
+        if (t & 1) r |= low;
+        t >>= 1;
+        mask ^= low;
+    }
+    return r;
+}
+
+// Tile passes: each workgroup walks tiles blockIdx.x, +gridDim.x, ...
+// LDS layout: hi_off[2^(m-l)], ladder tables [STAGE_MAX_LADDERS][2^lt +
+// 2^(m-lt)], then the tile (2^m amplitudes, only for multi-stage passes).
 template <typename R>
 __global__ __launch_bounds__(TILE_TPB) void k_tile(V2<R> *__restrict__ psi,
                                                    const DevPass *__restrict__ passes, int pidx,
-                                                   const DevOp<R> *__restrict__ ops) {
+                                                   const DevStage *__restrict__ stages,
+                                                   const DevOp<R> *__restrict__ ops,
+                                                   const uint64_t *__restrict__ aux,
+                                                   const V2<R> *__restrict__ ltab, uint64_t ntiles) {
     extern __shared__ __align__(16) unsigned char smem[];
     const DevPass &P = passes[pidx];
-    const int m = P.m, l = P.l;
-    V2<R> *tile = reinterpret_cast<V2<R> *>(smem);
-    uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem + (sizeof(V2<R>) << m));
-    const uint32_t T = 1u << m;
-    const uint32_t nhi = 1u << (m - l);
-    const uint32_t lowm = (1u << l) - 1;
-    for (uint32_t h = threadIdx.x; h < nhi; h += TILE_TPB) {
-        uint64_t o = 0;
-        for (int i = 0; i < m - l; ++i)
-            if ((h >> i) & 1) o |= 1ull << P.local_bits[l + i];
-        hi_off[h] = o;
-    }
-    uint64_t base = 0;
-    {
-        const uint64_t t = blockIdx.x;
-        for (int i = 0; i < P.nfree; ++i)
-            if ((t >> i) & 1) base |= 1ull << P.free_bits[i];
-    }
+    TileCtx<R> tc;
+    tc.m = P.m;
+    tc.l = P.l;
+    tc.lowm = (1u << P.l) - 1;
+    tc.ident = false;
+    const uint32_t nhi = 1u << (P.m - P.l);
+    uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem);
+    tc.hi_off = hi_off;
+    tc.lt = ladder_split(P.m);
+    tc.tstride = (1 << tc.lt) + (1 << (P.m - tc.lt));
+    tc.tabs = reinterpret_cast<V2<R> *>(smem + ((8 * nhi + 15) & ~15u));
+    V2<R> *tile = tc.tabs + STAGE_MAX_LADDERS * (tc.tstride + 1);
+    for (uint32_t h = threadIdx.x; h < nhi; h += TILE_TPB) hi_off[h] = aux[P.hi_begin + h];
+    const uint64_t fmask = P.free_mask;
+    const int sb = P.stage_begin, se = P.stage_end;
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < T; j += TILE_TPB) tile[j] = psi[base | hi_off[j >> l] | (j & lowm)];
-    auto gidx = [&](uint32_t j) -> uint64_t { return base | hi_off[j >> l] | (j & lowm); };
-    lds_apply_list<R, TILE_TPB>(tile, m, ops, P.op_begin, P.op_end, base, gidx);
-    for (uint32_t j = threadIdx.x; j < T; j += TILE_TPB) psi[base | hi_off[j >> l] | (j & lowm)] = tile[j];
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        tc.base = deposit(t, fmask);
+        run_stages<R, TILE_TPB>(tile, psi, tc, stages, sb, se, ops, ltab);
+    }
 }
 
-// In-place involution on index bits: pairs (swap_a[i], swap_b[i]).  The
-// local bit set is closed under the involution, so tile v maps onto tile
-// w = P(v); the workgroup owning min(v, w) exchanges both.
+// LDS position of tile element x: XOR-swizzled within rows of 256 bytes
+// (32 complex64 / 16 complex128) by two folds of the row index, so that the
+// permuted (e.g. bit-reversed) reads of a wave spread over the banks.
+template <typename R>
+__device__ __forceinline__ uint32_t swz(uint32_t x) {
+    constexpr int S = sizeof(V2<R>) == 8 ? 5 : 4;
+    constexpr uint32_t M = (1u << S) - 1;
+    return x ^ ((x >> S) & M) ^ ((x >> (2 * S)) & M);
+}
+
+// In-place involution on index bits.  The local bit set is closed under the
+// involution, so tile v maps onto tile w = P(v); the workgroup owning
+// min(v, w) exchanges both.  lperm[j] is the image of local position j.
 template <typename R>
 __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ psi,
-                                                   const DevPass *__restrict__ passes, int pidx) {
+                                                   const DevPass *__restrict__ passes, int pidx,
+                                                   const uint64_t *__restrict__ aux,
+                                                   const uint32_t *__restrict__ aux32, uint64_t ntiles) {
     extern __shared__ __align__(16) unsigned char smem[];
     const DevPass &P = passes[pidx];
     const int m = P.m, l = P.l;
@@ -196,60 +223,72 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ psi,
     uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem + 2 * (sizeof(V2<R>) << m));
     const uint32_t nhi = 1u << (m - l);
     const uint32_t lowm = (1u << l) - 1;
-    for (uint32_t h = threadIdx.x; h < nhi; h += TILE_TPB) {
-        uint64_t o = 0;
-        for (int i = 0; i < m - l; ++i)
-            if ((h >> i) & 1) o |= 1ull << P.local_bits[l + i];
-        hi_off[h] = o;
-    }
-    uint64_t bv = 0;
-    {
-        const uint64_t t = blockIdx.x;
-        for (int i = 0; i < P.nfree; ++i)
-            if ((t >> i) & 1) bv |= 1ull << P.free_bits[i];
-    }
-    // partner base and the local permutation (pairs inside the tile)
-    uint64_t bw = bv;
-    uint32_t lsa[24], lsb[24];
-    int nl = 0;
-    for (int i = 0; i < P.nswap; ++i) {
-        const int a = P.swap_a[i], b = P.swap_b[i];
-        int la = -1, lb = -1;
-        for (int j = 0; j < m; ++j) {
-            if (P.local_bits[j] == a) la = j;
-            if (P.local_bits[j] == b) lb = j;
-        }
-        if (la >= 0 && lb >= 0) {
-            lsa[nl] = la;
-            lsb[nl] = lb;
-            ++nl;
-        } else {
-            const uint64_t ba = (bv >> a) & 1, bb = (bv >> b) & 1;
-            if (ba != bb) bw ^= (1ull << a) | (1ull << b);
-        }
-    }
-    if (bw < bv) return;  // the partner workgroup does both tiles
+    for (uint32_t h = threadIdx.x; h < nhi; h += TILE_TPB) hi_off[h] = aux[P.hi_begin + h];
+    const uint32_t *lperm = aux32 + P.lperm_begin;
+    const uint64_t fmask = P.free_mask;
+    const int nfp = P.nfp;
     __syncthreads();
-    const bool two = bw != bv;
-    for (uint32_t j = threadIdx.x; j < T; j += TILE_TPB) {
-        const uint64_t off = hi_off[j >> l] | (j & lowm);
-        A[j] = psi[bv | off];
-        if (two) B[j] = psi[bw | off];
-    }
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < T; j += TILE_TPB) {
-        uint32_t s = j;
-        for (int i = 0; i < nl; ++i) {
-            const uint32_t x = ((s >> lsa[i]) ^ (s >> lsb[i])) & 1;
-            s ^= (x << lsa[i]) | (x << lsb[i]);
+    typedef typename Pair<R>::T PT;
+    constexpr int EPA = sizeof(PT) / sizeof(V2<R>);
+    constexpr int MAXA = 4;  // m <= 11: 2^11 / (EPA * TILE_TPB) accesses per thread and tile at most
+    const uint32_t nacc = T / EPA;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint64_t bv = deposit(t, fmask);
+        uint64_t bw = bv;
+        for (int i = 0; i < nfp; ++i) {
+            const int a = P.fpa[i], b = P.fpb[i];
+            if (((bv >> a) ^ (bv >> b)) & 1) bw ^= (1ull << a) | (1ull << b);
         }
-        const uint64_t off = hi_off[j >> l] | (j & lowm);
-        if (two) {
-            psi[bw | off] = A[s];
-            psi[bv | off] = B[s];
-        } else {
-            psi[bv | off] = A[s];
+        if (bw < bv) continue;  // the workgroup of the partner tile does both
+        const bool two = bw != bv;
+#pragma unroll
+        for (int a = 0; a < MAXA; ++a) {
+            const uint32_t q = threadIdx.x + (uint32_t)a * TILE_TPB;
+            if (q < nacc) {
+                const uint32_t j = q * EPA;
+                const uint64_t off = hi_off[j >> l] | (j & lowm);
+                const PT x = *reinterpret_cast<const PT *>(psi + (bv | off));
+                PT y;
+                if (two) y = *reinterpret_cast<const PT *>(psi + (bw | off));
+                if constexpr (EPA == 2) {
+                    A[swz<R>(j)] = make_float2(x.x, x.y);
+                    A[swz<R>(j + 1)] = make_float2(x.z, x.w);
+                    if (two) {
+                        B[swz<R>(j)] = make_float2(y.x, y.y);
+                        B[swz<R>(j + 1)] = make_float2(y.z, y.w);
+                    }
+                } else {
+                    A[swz<R>(j)] = x;
+                    if (two) B[swz<R>(j)] = y;
+                }
+            }
         }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < MAXA; ++a) {
+            const uint32_t q = threadIdx.x + (uint32_t)a * TILE_TPB;
+            if (q < nacc) {
+                const uint32_t j = q * EPA;
+                const uint64_t off = hi_off[j >> l] | (j & lowm);
+                PT x, y;
+                if constexpr (EPA == 2) {
+                    const uint32_t s0 = swz<R>(lperm[j]), s1 = swz<R>(lperm[j + 1]);
+                    x = pack_pair(A[s0], A[s1]);
+                    if (two) y = pack_pair(B[s0], B[s1]);
+                } else {
+                    const uint32_t s0 = swz<R>(lperm[j]);
+                    x = A[s0];
+                    if (two) y = B[s0];
+                }
+                if (two) {
+                    *reinterpret_cast<PT *>(psi + (bw | off)) = x;
+                    *reinterpret_cast<PT *>(psi + (bv | off)) = y;
+                } else {
+                    *reinterpret_cast<PT *>(psi + (bv | off)) = x;
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -408,11 +447,27 @@ unsigned grid_for(uint64_t items, int tpb, int cu) {
 
 void set_lds_limit(const void *fn, size_t bytes) {
     static std::mutex mu;
+    static int max_lds = 0;
     std::lock_guard<std::mutex> g(mu);
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (max_lds == 0) {
+        int dev = 0;
+        SV_HIP(hipGetDevice(&dev));
+        SV_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    }
+    if (bytes > (size_t)max_lds)
+        fail(SV_EDEVICE, "internal: LDS request of " + std::to_string(bytes) + " bytes exceeds the device limit of " +
+                             std::to_string(max_lds));
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(SV_EDEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    }
 }
 
-static DevPass to_dev_pass(const Pass &ps, int op_begin, int op_end) {
+// Device descriptor of a pass; appends its hi_off table (and for PERM
+// passes the local permutation) to the auxiliary arrays.
+static DevPass to_dev_pass(const Pass &ps, int op_begin, int op_end, std::vector<uint64_t> &aux,
+                           std::vector<uint32_t> &aux32) {
     DevPass d;
     std::memset(&d, 0, sizeof d);
     d.kind = ps.kind;
@@ -421,14 +476,47 @@ static DevPass to_dev_pass(const Pass &ps, int op_begin, int op_end) {
     d.nfree = (int)ps.free_bits.size();
     d.op_begin = op_begin;
     d.op_end = op_end;
-    d.nswap = (int)ps.swaps.size();
-    for (size_t i = 0; i < ps.local_bits.size(); ++i) d.local_bits[i] = (int8_t)ps.local_bits[i];
-    for (size_t i = 0; i < ps.free_bits.size(); ++i) d.free_bits[i] = (int8_t)ps.free_bits[i];
-    for (size_t i = 0; i < ps.swaps.size(); ++i) {
-        d.swap_a[i] = (int8_t)ps.swaps[i].first;
-        d.swap_b[i] = (int8_t)ps.swaps[i].second;
+    for (int b : ps.free_bits) d.free_mask |= 1ull << b;
+    d.hi_begin = (int)aux.size();
+    const uint32_t nhi = 1u << (ps.m - ps.l);
+    for (uint32_t h = 0; h < nhi; ++h) {
+        uint64_t o = 0;
+        for (int i = 0; i < ps.m - ps.l; ++i)
+            if ((h >> i) & 1) o |= 1ull << ps.local_bits[ps.l + i];
+        aux.push_back(o);
+    }
+    if (ps.kind == PASS_PERM) {
+        int pos[64];
+        for (int i = 0; i < 64; ++i) pos[i] = -1;
+        for (size_t i = 0; i < ps.local_bits.size(); ++i) pos[ps.local_bits[i]] = (int)i;
+        std::vector<std::pair<int, int>> local_pairs;
+        for (auto &pr : ps.swaps) {
+            if (pos[pr.first] >= 0 && pos[pr.second] >= 0) {
+                local_pairs.push_back({pos[pr.first], pos[pr.second]});
+            } else if (pos[pr.first] < 0 && pos[pr.second] < 0) {
+                d.fpa[d.nfp] = (int8_t)pr.first;
+                d.fpb[d.nfp] = (int8_t)pr.second;
+                ++d.nfp;
+            } else {
+                fail(SV_EDEVICE, "internal: permutation pass tile not closed under its pairs");
+            }
+        }
+        d.lperm_begin = (int)aux32.size();
+        for (uint32_t j = 0; j < (1u << ps.m); ++j) {
+            uint32_t s = j;
+            for (auto &lp : local_pairs) {
+                const uint32_t x = ((s >> lp.first) ^ (s >> lp.second)) & 1;
+                s ^= (x << lp.first) | (x << lp.second);
+            }
+            aux32.push_back(s);
+        }
     }
     return d;
+}
+
+static unsigned tile_grid(uint64_t tiles, int cu) {
+    const uint64_t cap = (uint64_t)cu * 8;
+    return (unsigned)std::max<uint64_t>(1, std::min(tiles, cap));
 }
 
 template <typename R>
@@ -526,27 +614,58 @@ static void run_plan_t(Ctx *ctx, State *st, const Plan &plan) {
     const int n = st->n;
     std::vector<DevOp<R>> dops;
     std::vector<DevPass> dpass;
+    std::vector<DevStage> dstages;
+    std::vector<uint64_t> aux;
+    std::vector<uint32_t> aux32;
+    std::vector<V2<R>> ltab;
     for (const Pass &ps : plan.passes) {
         if (ps.kind == PASS_SWEEP) {
             dpass.push_back(DevPass{});
             continue;
         }
         const int b = (int)dops.size();
+        std::vector<uint64_t> hoff;
         for (const Op &op : ps.ops) {
             DevOp<R> d = to_dev<R>(op);
             localise(d, ps.local_bits);
+            if (op.kind == OP_LADDER) {
+                if (hoff.empty()) hoff = hi_offsets(ps.local_bits, ladder_split(ps.m));
+                append_ladder_tables<R>(d, op, ps.m, hoff, ltab);
+            }
             dops.push_back(d);
         }
-        dpass.push_back(to_dev_pass(ps, b, (int)dops.size()));
+        DevPass dp = to_dev_pass(ps, b, (int)dops.size(), aux, aux32);
+        dp.stage_begin = (int)dstages.size();
+        if (ps.kind == PASS_TILE) build_stages<R>(dops, b, (int)dops.size(), ps.m, dstages);
+        dp.stage_end = (int)dstages.size();
+        dpass.push_back(dp);
     }
-    DevOp<R> *d_ops = nullptr;
-    DevPass *d_pass = nullptr;
-    if (!dops.empty()) {
-        d_ops = (DevOp<R> *)scratch(ctx, "plan_ops", dops.size() * sizeof(DevOp<R>));
-        upload(ctx, d_ops, dops.data(), dops.size() * sizeof(DevOp<R>));
-    }
-    d_pass = (DevPass *)scratch(ctx, "plan_passes", dpass.size() * sizeof(DevPass) + 16);
-    upload(ctx, d_pass, dpass.data(), dpass.size() * sizeof(DevPass));
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t s_ops = al(dops.size() * sizeof(DevOp<R>) + 16), s_pass = al(dpass.size() * sizeof(DevPass) + 16);
+    const size_t s_st = al(dstages.size() * sizeof(DevStage) + 16), s_aux = al(aux.size() * 8 + 16);
+    const size_t s_aux32 = al(aux32.size() * 4 + 16), s_lt = al(ltab.size() * sizeof(V2<R>) + 16);
+    std::vector<unsigned char> host(s_ops + s_pass + s_st + s_aux + s_aux32 + s_lt, 0);
+    size_t off = 0;
+    auto put = [&](const void *src, size_t bytes, size_t slot) {
+        if (bytes) std::memcpy(host.data() + off, src, bytes);
+        const size_t o = off;
+        off += slot;
+        return o;
+    };
+    const size_t o_ops = put(dops.data(), dops.size() * sizeof(DevOp<R>), s_ops);
+    const size_t o_pass = put(dpass.data(), dpass.size() * sizeof(DevPass), s_pass);
+    const size_t o_st = put(dstages.data(), dstages.size() * sizeof(DevStage), s_st);
+    const size_t o_aux = put(aux.data(), aux.size() * 8, s_aux);
+    const size_t o_aux32 = put(aux32.data(), aux32.size() * 4, s_aux32);
+    const size_t o_lt = put(ltab.data(), ltab.size() * sizeof(V2<R>), s_lt);
+    char *dbase = (char *)scratch(ctx, "plan", host.size());
+    upload(ctx, dbase, host.data(), host.size());
+    const DevOp<R> *d_ops = (const DevOp<R> *)(dbase + o_ops);
+    const DevPass *d_pass = (const DevPass *)(dbase + o_pass);
+    const DevStage *d_st = (const DevStage *)(dbase + o_st);
+    const uint64_t *d_aux = (const uint64_t *)(dbase + o_aux);
+    const uint32_t *d_aux32 = (const uint32_t *)(dbase + o_aux32);
+    const V2<R> *d_lt = (const V2<R> *)(dbase + o_lt);
     const double S = (double)st->bytes();
     for (size_t i = 0; i < plan.passes.size(); ++i) {
         const Pass &ps = plan.passes[i];
@@ -557,17 +676,24 @@ static void run_plan_t(Ctx *ctx, State *st, const Plan &plan) {
         const uint64_t tiles = 1ull << ps.free_bits.size();
         const uint32_t nhi = 1u << (ps.m - ps.l);
         if (ps.kind == PASS_TILE) {
-            const size_t lds = (sizeof(V2<R>) << ps.m) + 8 * nhi;
+            const DevPass &dp = dpass[i];
+            const int lt = ladder_split(ps.m);
+            const size_t tstride = (size_t)(1u << lt) + (1u << (ps.m - lt));
+            size_t lds = ((8 * (size_t)nhi + 15) & ~(size_t)15) + STAGE_MAX_LADDERS * (tstride + 1) * sizeof(V2<R>);
+            if (dp.stage_end - dp.stage_begin > 1) lds += sizeof(V2<R>) << ps.m;
             set_lds_limit((const void *)k_tile<R>, lds);
             LaunchScope ls(ctx, "tile", 2.0 * S);
-            hipLaunchKernelGGL(k_tile<R>, dim3((unsigned)tiles), dim3(TILE_TPB), lds, ctx->stream, psi,
-                               d_pass, (int)i, d_ops);
+            hipLaunchKernelGGL(k_tile<R>, dim3(tile_grid(tiles, ctx->cu_count)), dim3(TILE_TPB), lds, ctx->stream,
+                               psi, d_pass, (int)i, d_st, d_ops, d_aux, d_lt, tiles);
         } else {
+            // k_perm moves at most 4 accesses per thread per tile
+            if ((1u << ps.m) > 4u * TILE_TPB * (16 / sizeof(V2<R>)))
+                fail(SV_EDEVICE, "internal: permutation tile too wide");
             const size_t lds = 2 * (sizeof(V2<R>) << ps.m) + 8 * nhi;
             set_lds_limit((const void *)k_perm<R>, lds);
             LaunchScope ls(ctx, "perm", 2.0 * S);
-            hipLaunchKernelGGL(k_perm<R>, dim3((unsigned)tiles), dim3(TILE_TPB), lds, ctx->stream, psi,
-                               d_pass, (int)i);
+            hipLaunchKernelGGL(k_perm<R>, dim3(tile_grid(tiles, ctx->cu_count)), dim3(TILE_TPB), lds, ctx->stream,
+                               psi, d_pass, (int)i, d_aux, d_aux32, tiles);
         }
         SV_HIP(hipGetLastError());
     }

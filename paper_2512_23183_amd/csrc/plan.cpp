@@ -160,7 +160,9 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
     plan.n = n;
     plan.n_gate_ops = (int)ops_in.size();
 
-    if (!opt.fuse) {
+    // fused passes work on 8-amplitude groups: states of 1-2 qubits (and the
+    // plain path) take one sweep per gate
+    if (!opt.fuse || n < 3) {
         for (const Op &op : ops_in) {
             Pass ps;
             ps.kind = PASS_SWEEP;
@@ -301,8 +303,8 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
     bool ident = true;
     for (int i = 0; i < n; ++i) ident &= phys[i] == i;
     if (!ident) {
-        // two tiles live in LDS at once: 2 * 2^11 * 16 B = 64 KiB at most
-        const int mp = std::min(n, std::max(l, std::min(opt.tile_bits, 11)));
+        // two tiles live in LDS at once: 2 * 2^perm_bits amplitudes (64 KiB)
+        const int mp = std::min(n, std::max(l, std::min(opt.tile_bits, opt.perm_bits)));
         for (auto &inv : involutions(phys)) plan.passes.push_back(make_perm_pass(n, inv, mp, l));
     }
     return plan;

@@ -73,14 +73,21 @@ struct Op {
 template <typename R>
 struct alignas(16) DevOp {
     int32_t kind, a, b, la, lb;
-    int32_t pad0, pad1, pad2;
+    int32_t ra, rb;   // register slots (0..2) of la / lb within the op's stage
+    int32_t tslot;    // LADDER: phase-table slot within the stage
     uint64_t cmask;   // global positions
     uint64_t lcmask;  // local positions of the controls inside the tile
     uint64_t gcmask;  // controls outside the tile (constant per tile)
     uint64_t lmask;
     double turns;
-    double pad3;
+    int32_t flags;    // OPF_* below
+    int32_t tab;      // LADDER: offset of its host-built phase tables
     R m[32];          // complex entries as (re, im)
+};
+enum {
+    OPF_REAL = 1,  // 2x2 matrix with real entries (H, RY): cheaper butterfly
+    OPF_PAT = 2,   // DIAG whose only factor != 1 is on the all-ones pattern
+    OPF_NEG = 4,   // ... and that factor is exactly -1 (CZ)
 };
 
 // Lower one validated gate (kind, qubits, effective angles, user matrix) to
@@ -115,6 +122,7 @@ struct Pass {
 struct PlanOptions {
     int tile_bits = 13;    // m
     int low_bits = 5;      // l
+    int perm_bits = 11;    // tile width of permutation passes
     bool fuse = true;      // false: one sweep op per gate
 };
 
@@ -128,14 +136,31 @@ struct Plan {
 // the final layout is restored by PERM passes.
 Plan make_plan(int n, const std::vector<Op> &ops, const PlanOptions &opt);
 
-// Device pass descriptor.
+// A stage: ops whose mixing targets lie in three local bits (r0 < r1 < r2),
+// applied to 8-amplitude groups held in registers, one LDS or HBM round
+// trip per stage.  Ladders get per-tile phase tables (slots 0..nlad-1).
+constexpr int STAGE_MAX_LADDERS = 4;
+struct alignas(16) DevStage {
+    int32_t r0, r1, r2;
+    int32_t op_begin, op_end;
+    int32_t nlad;
+    int32_t has_diag;
+    int32_t pad;
+    int32_t lad[STAGE_MAX_LADDERS];
+};
+
+// Device pass descriptor.  Per-pass tables live in an auxiliary array:
+// hi_off (global offset of each combination of the high local bits) and,
+// for PERM passes, the local permutation of tile positions.
 struct alignas(16) DevPass {
     int32_t kind, m, l, nfree;
-    int32_t op_begin, op_end, nswap, pad;
-    int8_t local_bits[48];
-    int8_t free_bits[48];
-    int8_t swap_a[24];
-    int8_t swap_b[24];
+    int32_t op_begin, op_end, stage_begin, stage_end;
+    uint64_t free_mask;        // index bits outside the tile
+    int32_t hi_begin;          // offset of hi_off in the 64-bit aux array
+    int32_t lperm_begin;       // PERM: offset of the local permutation (32-bit aux)
+    int32_t nfp;               // PERM: bit pairs outside the tile
+    int32_t pad;
+    int8_t fpa[24], fpb[24];   // PERM: those pairs
 };
 
 // ---------------------------------------------------------------------------
