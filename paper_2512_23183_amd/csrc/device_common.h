@@ -116,6 +116,7 @@ struct TileCtx {
     V2<R> *tabs;              // LDS: ladder phase tables
     int lt;                   // table split: low table over local bits < lt
     int tstride;              // entries per table slot (2^lt + 2^(m-lt))
+    bool zero;                // first global read synthesises |0...0>
 };
 
 // Low-part width of the ladder tables (local bits below it are global bits).
@@ -180,6 +181,19 @@ __device__ __forceinline__ V vsel(bool c, V a, V b) {
 // One group of 8 amplitudes held in registers as eight named values (no
 // array: an array indexed from several dispatch branches can be merged by
 // the optimiser into a dynamically indexed stack object).
+// Deposit the bits of t into the set bits of mask (ascending): the global
+// index bits of tile t.  Uniform, so it runs on the scalar unit.
+__device__ __forceinline__ uint64_t deposit(uint64_t t, uint64_t mask) {
+    uint64_t r = 0;
+    while (mask) {
+        const uint64_t low = mask & (~mask + 1);
+        if (t & 1) r |= low;
+        t >>= 1;
+        mask ^= low;
+    }
+    return r;
+}
+
 template <typename R>
 struct Grp {
     V2<R> e0, e1, e2, e3, e4, e5, e6, e7;
@@ -411,7 +425,16 @@ __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi,
         g.k0 = gaddr(tc, g.j0);
         static_for<0, 8>([&](auto EC) {
             constexpr int e = decltype(EC)::value;
-            if constexpr (MODE & 1) el<e>(g) = gpsi[g.k0 | goff<e>(G)];
+            if constexpr (MODE & 1) {
+                if (tc.zero) {
+                    V2<R> z;
+                    z.x = (g.k0 | goff<e>(G)) == 0 ? (R)1 : (R)0;
+                    z.y = 0;
+                    el<e>(g) = z;
+                } else {
+                    el<e>(g) = gpsi[g.k0 | goff<e>(G)];
+                }
+            }
             else el<e>(g) = tile[g.j0 | loff<e>(L)];
         });
         for (int o = S.op_begin; o < S.op_end; ++o) {
@@ -535,6 +558,32 @@ __device__ __forceinline__ double pair_contrib(double pre, double pim, uint64_t 
 // ---------------------------------------------------------------------------
 // Host helpers shared by the launchers
 // ---------------------------------------------------------------------------
+
+// A plan in device form: host arrays, then their device copies.
+template <typename R>
+struct DevPlanHost {
+    std::vector<DevOp<R>> dops;
+    std::vector<int> gate;        // source gate index of each op (-1 = merged)
+    std::vector<DevPass> dpass;
+    std::vector<DevStage> dstages;
+    std::vector<uint64_t> aux;
+    std::vector<uint32_t> aux32;
+    std::vector<V2<R>> ltab;
+};
+template <typename R>
+struct DevPlanDev {
+    const DevOp<R> *ops;
+    const DevPass *pass;
+    const DevStage *stages;
+    const uint64_t *aux;
+    const uint32_t *aux32;
+    const V2<R> *ltab;
+};
+template <typename R> DevPlanHost<R> build_dev_plan(const Plan &plan);
+template <typename R> DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const char *slot);
+template <typename R>
+void launch_plan(Ctx *ctx, const Plan &plan, const DevPlanHost<R> &h, const DevPlanDev<R> &d, V2<R> *slab,
+                 uint64_t dim, int nc, const int *ovr_idx, const DevOp<R> *ovr, bool from_zero);
 
 void upload(Ctx *ctx, void *dst, const void *src, size_t bytes);
 unsigned grid_for(uint64_t items, int tpb, int cu);

@@ -149,29 +149,22 @@ __global__ __launch_bounds__(SWEEP_TPB) void k_scale(V2<R> *__restrict__ psi, ui
 
 constexpr int TILE_TPB = 512;
 
-// Deposit the bits of t into the set bits of mask (ascending): the global
-// index bits of tile t.  Uniform, so it runs on the scalar unit.
-__device__ __forceinline__ uint64_t deposit(uint64_t t, uint64_t mask) {
-    uint64_t r = 0;
-    while (mask) {
-        const uint64_t low = mask & (~mask + 1);
-        if (t & 1) r |= low;
-        t >>= 1;
-        mask ^= low;
-    }
-    return r;
-}
-
-// Tile passes: each workgroup walks tiles blockIdx.x, +gridDim.x, ...
+// Tile passes over a slab of nc states of dim amplitudes each (one state:
+// nc = 1).  Each workgroup walks the work items w = blockIdx.x,
+// +gridDim.x, ... with w = circuit * ntiles + tile, so neighbouring
+// workgroups share a circuit.  Circuit c applies op ovr_idx[c] as ovr[c]
+// (parameter-shift copies); from_zero makes the reads synthesise |0...0>.
 // LDS layout: hi_off[2^(m-l)], ladder tables [STAGE_MAX_LADDERS][2^lt +
-// 2^(m-lt)], then the tile (2^m amplitudes, only for multi-stage passes).
+// 2^(m-lt) + 1], then the tile (2^m amplitudes, only for multi-stage passes).
 template <typename R>
-__global__ __launch_bounds__(TILE_TPB) void k_tile(V2<R> *__restrict__ psi,
+__global__ __launch_bounds__(TILE_TPB) void k_tile(V2<R> *__restrict__ slab, uint64_t dim, int nc,
+                                                   const int *__restrict__ ovr_idx,
+                                                   const DevOp<R> *__restrict__ ovr,
                                                    const DevPass *__restrict__ passes, int pidx,
                                                    const DevStage *__restrict__ stages,
                                                    const DevOp<R> *__restrict__ ops,
                                                    const uint64_t *__restrict__ aux,
-                                                   const V2<R> *__restrict__ ltab, uint64_t ntiles) {
+                                                   const V2<R> *__restrict__ ltab, uint64_t ntiles, int from_zero) {
     extern __shared__ __align__(16) unsigned char smem[];
     const DevPass &P = passes[pidx];
     TileCtx<R> tc;
@@ -179,6 +172,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_tile(V2<R> *__restrict__ psi,
     tc.l = P.l;
     tc.lowm = (1u << P.l) - 1;
     tc.ident = false;
+    tc.zero = from_zero != 0;
     const uint32_t nhi = 1u << (P.m - P.l);
     uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem);
     tc.hi_off = hi_off;
@@ -190,9 +184,12 @@ __global__ __launch_bounds__(TILE_TPB) void k_tile(V2<R> *__restrict__ psi,
     const uint64_t fmask = P.free_mask;
     const int sb = P.stage_begin, se = P.stage_end;
     __syncthreads();
-    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t nw = (uint64_t)nc * ntiles;
+    for (uint64_t w = blockIdx.x; w < nw; w += gridDim.x) {
+        const uint64_t c = w / ntiles, t = w - c * ntiles;
         tc.base = deposit(t, fmask);
-        run_stages<R, TILE_TPB>(tile, psi, tc, stages, sb, se, ops, ltab);
+        const int oi = ovr_idx ? ovr_idx[c] : -1;
+        run_stages<R, TILE_TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, ltab, oi, ovr ? ovr + c : nullptr);
     }
 }
 
@@ -210,7 +207,7 @@ __device__ __forceinline__ uint32_t swz(uint32_t x) {
 // involution, so tile v maps onto tile w = P(v); the workgroup owning
 // min(v, w) exchanges both.  lperm[j] is the image of local position j.
 template <typename R>
-__global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ psi,
+__global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uint64_t dim, int nc,
                                                    const DevPass *__restrict__ passes, int pidx,
                                                    const uint64_t *__restrict__ aux,
                                                    const uint32_t *__restrict__ aux32, uint64_t ntiles) {
@@ -232,7 +229,10 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ psi,
     constexpr int EPA = sizeof(PT) / sizeof(V2<R>);
     constexpr int MAXA = 4;  // m <= 11: 2^11 / (EPA * TILE_TPB) accesses per thread and tile at most
     const uint32_t nacc = T / EPA;
-    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t nw = (uint64_t)nc * ntiles;
+    for (uint64_t w = blockIdx.x; w < nw; w += gridDim.x) {
+        const uint64_t c = w / ntiles, t = w - c * ntiles;
+        V2<R> *__restrict__ psi = slab + c * dim;
         const uint64_t bv = deposit(t, fmask);
         uint64_t bw = bv;
         for (int i = 0; i < nfp; ++i) {
@@ -520,7 +520,7 @@ static unsigned tile_grid(uint64_t tiles, int cu) {
 }
 
 template <typename R>
-static void sweep_one(Ctx *ctx, V2<R> *psi, int n, const Op &op) {
+void sweep_one(Ctx *ctx, V2<R> *psi, int n, const Op &op) {
     const int cu = ctx->cu_count;
     const double amp = (double)sizeof(V2<R>);
     DevOp<R> d = to_dev<R>(op);
@@ -609,94 +609,123 @@ static void sweep_one(Ctx *ctx, V2<R> *psi, int n, const Op &op) {
 }
 
 template <typename R>
-static void run_plan_t(Ctx *ctx, State *st, const Plan &plan) {
-    V2<R> *psi = reinterpret_cast<V2<R> *>(st->ptr);
-    const int n = st->n;
-    std::vector<DevOp<R>> dops;
-    std::vector<DevPass> dpass;
-    std::vector<DevStage> dstages;
-    std::vector<uint64_t> aux;
-    std::vector<uint32_t> aux32;
-    std::vector<V2<R>> ltab;
+DevPlanHost<R> build_dev_plan(const Plan &plan) {
+    DevPlanHost<R> h;
     for (const Pass &ps : plan.passes) {
         if (ps.kind == PASS_SWEEP) {
-            dpass.push_back(DevPass{});
+            h.dpass.push_back(DevPass{});
             continue;
         }
-        const int b = (int)dops.size();
+        const int b = (int)h.dops.size();
         std::vector<uint64_t> hoff;
         for (const Op &op : ps.ops) {
             DevOp<R> d = to_dev<R>(op);
             localise(d, ps.local_bits);
             if (op.kind == OP_LADDER) {
                 if (hoff.empty()) hoff = hi_offsets(ps.local_bits, ladder_split(ps.m));
-                append_ladder_tables<R>(d, op, ps.m, hoff, ltab);
+                append_ladder_tables<R>(d, op, ps.m, hoff, h.ltab);
             }
-            dops.push_back(d);
+            h.gate.push_back(op.gate);
+            h.dops.push_back(d);
         }
-        DevPass dp = to_dev_pass(ps, b, (int)dops.size(), aux, aux32);
-        dp.stage_begin = (int)dstages.size();
-        if (ps.kind == PASS_TILE) build_stages<R>(dops, b, (int)dops.size(), ps.m, dstages);
-        dp.stage_end = (int)dstages.size();
-        dpass.push_back(dp);
+        DevPass dp = to_dev_pass(ps, b, (int)h.dops.size(), h.aux, h.aux32);
+        dp.stage_begin = (int)h.dstages.size();
+        if (ps.kind == PASS_TILE) build_stages<R>(h.dops, b, (int)h.dops.size(), ps.m, h.dstages);
+        dp.stage_end = (int)h.dstages.size();
+        h.dpass.push_back(dp);
     }
+    return h;
+}
+template DevPlanHost<float> build_dev_plan<float>(const Plan &);
+template DevPlanHost<double> build_dev_plan<double>(const Plan &);
+
+template <typename R>
+DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const char *slot) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t s_ops = al(dops.size() * sizeof(DevOp<R>) + 16), s_pass = al(dpass.size() * sizeof(DevPass) + 16);
-    const size_t s_st = al(dstages.size() * sizeof(DevStage) + 16), s_aux = al(aux.size() * 8 + 16);
-    const size_t s_aux32 = al(aux32.size() * 4 + 16), s_lt = al(ltab.size() * sizeof(V2<R>) + 16);
+    const size_t s_ops = al(h.dops.size() * sizeof(DevOp<R>) + 16), s_pass = al(h.dpass.size() * sizeof(DevPass) + 16);
+    const size_t s_st = al(h.dstages.size() * sizeof(DevStage) + 16), s_aux = al(h.aux.size() * 8 + 16);
+    const size_t s_aux32 = al(h.aux32.size() * 4 + 16), s_lt = al(h.ltab.size() * sizeof(V2<R>) + 16);
     std::vector<unsigned char> host(s_ops + s_pass + s_st + s_aux + s_aux32 + s_lt, 0);
     size_t off = 0;
-    auto put = [&](const void *src, size_t bytes, size_t slot) {
+    auto put = [&](const void *src, size_t bytes, size_t sz) {
         if (bytes) std::memcpy(host.data() + off, src, bytes);
         const size_t o = off;
-        off += slot;
+        off += sz;
         return o;
     };
-    const size_t o_ops = put(dops.data(), dops.size() * sizeof(DevOp<R>), s_ops);
-    const size_t o_pass = put(dpass.data(), dpass.size() * sizeof(DevPass), s_pass);
-    const size_t o_st = put(dstages.data(), dstages.size() * sizeof(DevStage), s_st);
-    const size_t o_aux = put(aux.data(), aux.size() * 8, s_aux);
-    const size_t o_aux32 = put(aux32.data(), aux32.size() * 4, s_aux32);
-    const size_t o_lt = put(ltab.data(), ltab.size() * sizeof(V2<R>), s_lt);
-    char *dbase = (char *)scratch(ctx, "plan", host.size());
+    const size_t o_ops = put(h.dops.data(), h.dops.size() * sizeof(DevOp<R>), s_ops);
+    const size_t o_pass = put(h.dpass.data(), h.dpass.size() * sizeof(DevPass), s_pass);
+    const size_t o_st = put(h.dstages.data(), h.dstages.size() * sizeof(DevStage), s_st);
+    const size_t o_aux = put(h.aux.data(), h.aux.size() * 8, s_aux);
+    const size_t o_aux32 = put(h.aux32.data(), h.aux32.size() * 4, s_aux32);
+    const size_t o_lt = put(h.ltab.data(), h.ltab.size() * sizeof(V2<R>), s_lt);
+    char *dbase = (char *)scratch(ctx, slot, host.size());
     upload(ctx, dbase, host.data(), host.size());
-    const DevOp<R> *d_ops = (const DevOp<R> *)(dbase + o_ops);
-    const DevPass *d_pass = (const DevPass *)(dbase + o_pass);
-    const DevStage *d_st = (const DevStage *)(dbase + o_st);
-    const uint64_t *d_aux = (const uint64_t *)(dbase + o_aux);
-    const uint32_t *d_aux32 = (const uint32_t *)(dbase + o_aux32);
-    const V2<R> *d_lt = (const V2<R> *)(dbase + o_lt);
-    const double S = (double)st->bytes();
+    DevPlanDev<R> d;
+    d.ops = (const DevOp<R> *)(dbase + o_ops);
+    d.pass = (const DevPass *)(dbase + o_pass);
+    d.stages = (const DevStage *)(dbase + o_st);
+    d.aux = (const uint64_t *)(dbase + o_aux);
+    d.aux32 = (const uint32_t *)(dbase + o_aux32);
+    d.ltab = (const V2<R> *)(dbase + o_lt);
+    return d;
+}
+template DevPlanDev<float> upload_dev_plan<float>(Ctx *, const DevPlanHost<float> &, const char *);
+template DevPlanDev<double> upload_dev_plan<double>(Ctx *, const DevPlanHost<double> &, const char *);
+
+// Launch every pass of a plan over a slab of nc states (dim amplitudes
+// each).  Sweep passes (the plain path) only exist for nc == 1.  With
+// from_zero the first pass synthesises |0...0> instead of reading memory
+// (it must be a tile pass then).
+template <typename R>
+void launch_plan(Ctx *ctx, const Plan &plan, const DevPlanHost<R> &h, const DevPlanDev<R> &d, V2<R> *slab,
+                 uint64_t dim, int nc, const int *ovr_idx, const DevOp<R> *ovr, bool from_zero) {
+    const double S = (double)sizeof(V2<R>) * (double)dim * nc;
     for (size_t i = 0; i < plan.passes.size(); ++i) {
         const Pass &ps = plan.passes[i];
         if (ps.kind == PASS_SWEEP) {
-            sweep_one<R>(ctx, psi, n, ps.ops[0]);
+            if (nc != 1 || ovr_idx) fail(SV_EDEVICE, "internal: sweep pass in a batched plan");
+            sweep_one<R>(ctx, slab, plan.n, ps.ops[0]);
             continue;
         }
         const uint64_t tiles = 1ull << ps.free_bits.size();
         const uint32_t nhi = 1u << (ps.m - ps.l);
+        const unsigned grid = tile_grid(tiles * (uint64_t)nc, ctx->cu_count);
         if (ps.kind == PASS_TILE) {
-            const DevPass &dp = dpass[i];
+            const DevPass &dp = h.dpass[i];
             const int lt = ladder_split(ps.m);
             const size_t tstride = (size_t)(1u << lt) + (1u << (ps.m - lt));
             size_t lds = ((8 * (size_t)nhi + 15) & ~(size_t)15) + STAGE_MAX_LADDERS * (tstride + 1) * sizeof(V2<R>);
             if (dp.stage_end - dp.stage_begin > 1) lds += sizeof(V2<R>) << ps.m;
             set_lds_limit((const void *)k_tile<R>, lds);
             LaunchScope ls(ctx, "tile", 2.0 * S);
-            hipLaunchKernelGGL(k_tile<R>, dim3(tile_grid(tiles, ctx->cu_count)), dim3(TILE_TPB), lds, ctx->stream,
-                               psi, d_pass, (int)i, d_st, d_ops, d_aux, d_lt, tiles);
+            hipLaunchKernelGGL(k_tile<R>, dim3(grid), dim3(TILE_TPB), lds, ctx->stream, slab, dim, nc, ovr_idx, ovr,
+                               d.pass, (int)i, d.stages, d.ops, d.aux, d.ltab, tiles,
+                               (from_zero && i == 0) ? 1 : 0);
         } else {
+            if (from_zero && i == 0) fail(SV_EDEVICE, "internal: plan starts with a permutation");
             // k_perm moves at most 4 accesses per thread per tile
             if ((1u << ps.m) > 4u * TILE_TPB * (16 / sizeof(V2<R>)))
                 fail(SV_EDEVICE, "internal: permutation tile too wide");
             const size_t lds = 2 * (sizeof(V2<R>) << ps.m) + 8 * nhi;
             set_lds_limit((const void *)k_perm<R>, lds);
             LaunchScope ls(ctx, "perm", 2.0 * S);
-            hipLaunchKernelGGL(k_perm<R>, dim3(tile_grid(tiles, ctx->cu_count)), dim3(TILE_TPB), lds, ctx->stream,
-                               psi, d_pass, (int)i, d_aux, d_aux32, tiles);
+            hipLaunchKernelGGL(k_perm<R>, dim3(grid), dim3(TILE_TPB), lds, ctx->stream, slab, dim, nc, d.pass, (int)i,
+                               d.aux, d.aux32, tiles);
         }
         SV_HIP(hipGetLastError());
     }
+}
+template void launch_plan<float>(Ctx *, const Plan &, const DevPlanHost<float> &, const DevPlanDev<float> &,
+                                 V2<float> *, uint64_t, int, const int *, const DevOp<float> *, bool);
+template void launch_plan<double>(Ctx *, const Plan &, const DevPlanHost<double> &, const DevPlanDev<double> &,
+                                  V2<double> *, uint64_t, int, const int *, const DevOp<double> *, bool);
+
+template <typename R>
+static void run_plan_t(Ctx *ctx, State *st, const Plan &plan) {
+    DevPlanHost<R> h = build_dev_plan<R>(plan);
+    DevPlanDev<R> d = upload_dev_plan<R>(ctx, h, "plan");
+    launch_plan<R>(ctx, plan, h, d, reinterpret_cast<V2<R> *>(st->ptr), 1ull << st->n, 1, nullptr, nullptr, false);
 }
 
 void run_plan(Ctx *ctx, State *st, const Plan &plan) {
