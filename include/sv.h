@@ -158,9 +158,13 @@ enum {
  * SV_ENODEV if the device is missing or not gfx950.
  */
 typedef struct sv_config {
-    int32_t tile_bits_c64;   /* LDS tile width for complex64, 0 = default */
-    int32_t tile_bits_c128;  /* LDS tile width for complex128, 0 = default */
-    int32_t reserved[6];
+    int32_t tile_bits_c64;     /* gate tile pass width (bits), complex64: 6..14, 0 = default 13 */
+    int32_t tile_bits_c128;    /* same for complex128: 6..13, 0 = default 12 */
+    int32_t expect_bits_c64;   /* expectation pass tile width, complex64: 6..14, 0 = default 13 */
+    int32_t expect_bits_c128;  /* same for complex128: 6..13, 0 = default 12 */
+    int32_t perm_bits_c64;     /* permutation pass tile width, complex64: 6..12, 0 = default 12 */
+    int32_t perm_bits_c128;    /* same for complex128: 6..11, 0 = default 11 */
+    int32_t reserved[2];       /* must be 0 */
 } sv_config;
 
 int sv_init(sv_ctx **out, int device, const sv_config *cfg);

@@ -68,8 +68,8 @@ void apply_ops(State *st, const std::vector<Op> &ops, uint32_t flags) {
         run_unfused(ctx, st, ops);
     } else {
         PlanOptions po;
-        po.tile_bits = st->dtype == SV_C64 ? ctx->tile_bits_c64 : ctx->tile_bits_c128;
-        po.perm_bits = st->dtype == SV_C64 ? 12 : 11;
+        po.tile_bits = ctx->tile_bits[st->dtype];
+        po.perm_bits = ctx->perm_bits[st->dtype];
         run_plan(ctx, st, make_plan(st->n, ops, po));
     }
     if (ctx->profile) {
@@ -194,8 +194,15 @@ int sv_init(sv_ctx **out, int device, const sv_config *cfg) {
         }
         ctx->stream = ctx->own_stream;
         if (cfg) {
-            if (cfg->tile_bits_c64 > 0) ctx->tile_bits_c64 = std::max(6, std::min(14, (int)cfg->tile_bits_c64));
-            if (cfg->tile_bits_c128 > 0) ctx->tile_bits_c128 = std::max(6, std::min(13, (int)cfg->tile_bits_c128));
+            auto pick = [](int32_t v, int lo, int hi, int &dst) {
+                if (v > 0) dst = std::max(lo, std::min(hi, (int)v));
+            };
+            pick(cfg->tile_bits_c64, 6, 14, ctx->tile_bits[SV_C64]);
+            pick(cfg->tile_bits_c128, 6, 13, ctx->tile_bits[SV_C128]);
+            pick(cfg->expect_bits_c64, 6, 14, ctx->expect_bits[SV_C64]);
+            pick(cfg->expect_bits_c128, 6, 13, ctx->expect_bits[SV_C128]);
+            pick(cfg->perm_bits_c64, 6, 12, ctx->perm_bits[SV_C64]);
+            pick(cfg->perm_bits_c128, 6, 11, ctx->perm_bits[SV_C128]);
         }
         *out = ctx;
     });

@@ -270,227 +270,7 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     SV_HIP(hipGetLastError());
 }
 
-// ---------------------------------------------------------------------------
-// Batched expectation tile passes: read-only passes over a slab of states.
-// Pass e holds the Pauli groups whose X/Y support lies inside its local
-// bits; every workgroup reduces its tile's FP64 contribution to each of the
-// pass's terms into partial[c][term slot][tile] (fixed order).
-// ---------------------------------------------------------------------------
-
-struct alignas(16) DevEPass {
-    int32_t m, l, g_begin, g_end;
-    int32_t hi_begin, part_off, pad0, pad1;
-    uint64_t free_mask;
-    uint64_t ntiles;
-};
-
-constexpr int EXPT_TPB = 256;
-constexpr int EXPT_CHUNK = 8;
-
-template <typename R>
-__global__ __launch_bounds__(EXPT_TPB) void k_expect_tile(
-    const V2<R> *__restrict__ slab, uint64_t dim, int nc, const DevEPass *__restrict__ eps, int e,
-    const uint64_t *__restrict__ aux, const uint32_t *__restrict__ gxl, const int *__restrict__ gbeg,
-    const int *__restrict__ gend, const DevTerm *__restrict__ terms, const int *__restrict__ tslot,
-    uint64_t part_stride, double *__restrict__ partial) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[EXPT_TPB / 64];
-    const DevEPass &P = eps[e];
-    const int m = P.m, l = P.l;
-    const uint32_t T = 1u << m, lowm = (1u << l) - 1;
-    const uint32_t nhi = 1u << (m - l);
-    V2<R> *tile = reinterpret_cast<V2<R> *>(smem);
-    uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem + (sizeof(V2<R>) << m));
-    for (uint32_t h = threadIdx.x; h < nhi; h += EXPT_TPB) hi_off[h] = aux[P.hi_begin + h];
-    __syncthreads();
-    const uint64_t ntiles = P.ntiles, nw = (uint64_t)nc * ntiles;
-    for (uint64_t w = blockIdx.x; w < nw; w += gridDim.x) {
-        const uint64_t c = w / ntiles, t = w - c * ntiles;
-        const uint64_t base = deposit(t, P.free_mask);
-        const V2<R> *__restrict__ psi = slab + c * dim;
-        for (uint32_t j = threadIdx.x; j < T; j += EXPT_TPB) tile[j] = psi[base | hi_off[j >> l] | (j & lowm)];
-        __syncthreads();
-        for (int g = P.g_begin; g < P.g_end; ++g) {
-            const uint32_t xl = gxl[g];
-            const int hb = xl ? 31 - __clz(xl) : -1;
-            const uint32_t items = xl ? T / 2 : T;
-            for (int t0 = gbeg[g]; t0 < gend[g]; t0 += EXPT_CHUNK) {
-                const int cnt = min(EXPT_CHUNK, gend[g] - t0);
-                double acc[EXPT_CHUNK];
-#pragma unroll
-                for (int q = 0; q < EXPT_CHUNK; ++q) acc[q] = 0.0;
-                for (uint32_t it = threadIdx.x; it < items; it += EXPT_TPB) {
-                    if (!xl) {
-                        const V2<R> a = tile[it];
-                        const uint64_t k = base | hi_off[it >> l] | (it & lowm);
-                        const double pr = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
-#pragma unroll
-                        for (int q = 0; q < EXPT_CHUNK; ++q)
-                            if (q < cnt) acc[q] += (__popcll(k & terms[t0 + q].z) & 1) ? -pr : pr;
-                    } else {
-                        const uint32_t j = ins0(it, hb), j2 = j ^ xl;
-                        const V2<R> a = tile[j], b = tile[j2];
-                        const uint64_t k = base | hi_off[j >> l] | (j & lowm);
-                        const uint64_t k2 = base | hi_off[j2 >> l] | (j2 & lowm);
-                        const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
-                        const double pre = bx * ax + by * ay, pim = bx * ay - by * ax;
-#pragma unroll
-                        for (int q = 0; q < EXPT_CHUNK; ++q)
-                            if (q < cnt) acc[q] += pair_contrib(pre, pim, k, k2, terms[t0 + q].z, terms[t0 + q].ny);
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < EXPT_CHUNK; ++q) {
-                    if (q < cnt) {
-                        const double sum = block_sum<EXPT_TPB>(acc[q], red);
-                        if (threadIdx.x == 0)
-                            partial[c * part_stride + P.part_off + (uint64_t)tslot[t0 + q] * ntiles + t] = sum;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// One workgroup per circuit: value[t] = sum of its partial row in order,
-// E = (sum_t c_t value[t]) / value[T], written to E[out_slot[c]].
-__global__ void k_expect_final(double *__restrict__ partial, uint64_t part_stride, int nc,
-                               const int *__restrict__ t_off, const int *__restrict__ t_cnt, int T,
-                               const double *__restrict__ coeffs, const int *__restrict__ out_slot,
-                               double *__restrict__ E) {
-    for (int c = blockIdx.x; c < nc; c += gridDim.x) {
-        double *row = partial + (uint64_t)c * part_stride;
-        for (int t = threadIdx.x; t <= T; t += blockDim.x) {
-            double v = 0.0;
-            for (int i = 0; i < t_cnt[t]; ++i) v += row[t_off[t] + i];
-            row[t_off[t]] = v;
-        }
-        __threadfence_block();
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double e = 0.0;
-            for (int t = 0; t < T; ++t) e += coeffs[t] * row[t_off[t]];
-            E[out_slot[c]] = e / row[t_off[T]];
-        }
-        __syncthreads();
-    }
-}
-
 namespace {
-
-// Expectation passes for a lowered Pauli sum: greedy cover of the X/Y
-// supports by tile bit-sets that keep the low bits local.
-struct EPlan {
-    std::vector<DevEPass> eps;
-    std::vector<uint64_t> aux;
-    std::vector<uint32_t> gxl;
-    std::vector<int> gbeg, gend, tslot;
-    std::vector<DevTerm> terms;
-    std::vector<int> t_off, t_cnt;  // per term index 0..T
-    std::vector<double> coeffs;
-    uint64_t part_stride = 0;
-    int T = 0;
-    bool ok = true;
-};
-
-EPlan make_eplan(int n, int m_max, const TermGroups &tg) {
-    EPlan E;
-    DevTerms dt = build_dev_terms(tg);
-    E.T = dt.T;
-    E.coeffs = dt.coeffs;
-    const int m = std::min(m_max, n);
-    const int l0 = std::min(5, m);
-    const uint64_t low = (1ull << l0) - 1;
-    const int G = (int)dt.gx.size();
-    std::vector<int> order(G);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return __builtin_popcountll(dt.gx[a]) > __builtin_popcountll(dt.gx[b]);
-    });
-    std::vector<bool> done(G, false);
-    int remaining = G;
-    E.t_off.assign(E.T + 1, 0);
-    E.t_cnt.assign(E.T + 1, 0);
-    uint64_t part = 0;
-    while (remaining > 0) {
-        uint64_t S = low;
-        std::vector<int> chosen;
-        for (int g : order) {
-            if (done[g]) continue;
-            const uint64_t need = dt.gx[g] & ~S;
-            if (__builtin_popcountll(S) + __builtin_popcountll(need) <= m) {
-                S |= dt.gx[g];
-                chosen.push_back(g);
-            }
-        }
-        if (chosen.empty()) {
-            // a support wider than the tile's free room: drop the low bits
-            for (int g : order)
-                if (!done[g]) {
-                    if (__builtin_popcountll(dt.gx[g]) > m) {
-                        E.ok = false;
-                        return E;
-                    }
-                    S = dt.gx[g];
-                    chosen.push_back(g);
-                    break;
-                }
-        }
-        for (int b = 0; b < n && __builtin_popcountll(S) < m; ++b) S |= 1ull << b;
-        std::vector<int> local, freeb;
-        int pos[64];
-        for (int b = 0; b < n; ++b) {
-            if (S & (1ull << b)) {
-                pos[b] = (int)local.size();
-                local.push_back(b);
-            } else {
-                pos[b] = -1;
-                freeb.push_back(b);
-            }
-        }
-        DevEPass ep;
-        std::memset(&ep, 0, sizeof ep);
-        ep.m = (int)local.size();
-        int run = 0;
-        while (run < ep.m && local[run] == run) ++run;
-        ep.l = run;
-        for (int b : freeb) ep.free_mask |= 1ull << b;
-        ep.ntiles = 1ull << freeb.size();
-        ep.hi_begin = (int)E.aux.size();
-        for (uint32_t h = 0; h < (1u << (ep.m - ep.l)); ++h) {
-            uint64_t o = 0;
-            for (int i = 0; i < ep.m - ep.l; ++i)
-                if ((h >> i) & 1) o |= 1ull << local[ep.l + i];
-            E.aux.push_back(o);
-        }
-        ep.g_begin = (int)E.gxl.size();
-        ep.part_off = (int)part;
-        int slot = 0;
-        for (int g : chosen) {
-            done[g] = true;
-            --remaining;
-            uint32_t xl = 0;
-            for (int b = 0; b < n; ++b)
-                if (dt.gx[g] & (1ull << b)) xl |= 1u << pos[b];
-            E.gxl.push_back(xl);
-            E.gbeg.push_back((int)E.terms.size());
-            for (int t = dt.gbeg[g]; t < dt.gend[g]; ++t) {
-                E.terms.push_back(dt.terms[t]);
-                E.tslot.push_back(slot);
-                E.t_off[dt.terms[t].idx] = (int)(part + (uint64_t)slot * ep.ntiles);
-                E.t_cnt[dt.terms[t].idx] = (int)ep.ntiles;
-                ++slot;
-            }
-            E.gend.push_back((int)E.terms.size());
-        }
-        ep.g_end = (int)E.gxl.size();
-        part += (uint64_t)slot * ep.ntiles;
-        E.eps.push_back(ep);
-    }
-    E.part_stride = part;
-    return E;
-}
 
 // Circuits too large for one workgroup, batched: one plan per (op set,
 // Hamiltonian); per pass one launch over all (circuit, tile) items of a
@@ -504,11 +284,11 @@ void run_large_batched(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &
         const std::vector<int> &cs = kv.second;
         const int n = spec.circuits[cs[0]].n;
         PlanOptions po;
-        po.tile_bits = spec.dtype == SV_C64 ? ctx->tile_bits_c64 : ctx->tile_bits_c128;
-        po.perm_bits = spec.dtype == SV_C64 ? 12 : 11;
+        po.tile_bits = ctx->tile_bits[spec.dtype];
+        po.perm_bits = ctx->perm_bits[spec.dtype];
         const std::vector<Op> &ops = spec.op_sets[kv.first.first];
         Plan plan = make_plan(n, ops, po);
-        EPlan E = make_eplan(n, po.tile_bits, spec.hams[kv.first.second]);
+        EPlanHost E = make_eplan(n, expect_tile_bits(ctx, spec.dtype), build_dev_terms(spec.hams[kv.first.second]));
         bool plan_ok = !plan.passes.empty() && plan.passes[0].kind == PASS_TILE;
         for (const Pass &ps : plan.passes) plan_ok = plan_ok && ps.kind != PASS_SWEEP;
         if (!E.ok || !plan_ok) {
@@ -520,20 +300,7 @@ void run_large_batched(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &
         std::map<int, int> dop_of_gate;
         for (size_t i = 0; i < h.gate.size(); ++i)
             if (h.gate[i] >= 0) dop_of_gate[h.gate[i]] = (int)i;
-        // expectation metadata (one upload)
-        Blob eb;
-        const size_t o_ep = eb.add(E.eps.data(), E.eps.size() * sizeof(DevEPass));
-        const size_t o_aux = eb.add(E.aux.data(), E.aux.size() * 8);
-        const size_t o_gxl = eb.add(E.gxl.data(), E.gxl.size() * 4);
-        const size_t o_gb = eb.add(E.gbeg.data(), E.gbeg.size() * 4);
-        const size_t o_ge = eb.add(E.gend.data(), E.gend.size() * 4);
-        const size_t o_t = eb.add(E.terms.data(), E.terms.size() * sizeof(DevTerm));
-        const size_t o_ts = eb.add(E.tslot.data(), E.tslot.size() * 4);
-        const size_t o_to = eb.add(E.t_off.data(), E.t_off.size() * 4);
-        const size_t o_tc = eb.add(E.t_cnt.data(), E.t_cnt.size() * 4);
-        const size_t o_cf = eb.add(E.coeffs.data(), E.coeffs.size() * 8);
-        char *ebase = (char *)scratch(ctx, "mp_eplan", eb.host.size());
-        upload(ctx, ebase, eb.host.data(), eb.host.size());
+        EPlanDev ed = upload_eplan(ctx, E, "mp_eplan");
         // chunks of circuits whose states fit the slab budget
         const uint64_t dim = 1ull << n;
         const size_t sbytes = sizeof(V2<R>) * dim;
@@ -542,7 +309,6 @@ void run_large_batched(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &
         const int chunk = (int)std::max<size_t>(
             1, std::min<size_t>(cs.size(), std::min(budget / sbytes, pbudget / std::max<size_t>(pbytes, 1))));
         V2<R> *slab = (V2<R> *)scratch(ctx, "mp_slab", sbytes * chunk);
-        double *part = (double *)scratch(ctx, "mp_partial", 8 * E.part_stride * chunk + 64);
         for (size_t c0 = 0; c0 < cs.size(); c0 += chunk) {
             const int nc = (int)std::min<size_t>(chunk, cs.size() - c0);
             std::vector<int> oidx(nc, -1), oslot(nc);
@@ -581,24 +347,7 @@ void run_large_batched(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &
             upload(ctx, obase, ob.host.data(), ob.host.size());
             launch_plan<R>(ctx, plan, h, d, slab, dim, nc, (const int *)(obase + o_oi),
                            (const DevOp<R> *)(obase + o_ov), true);
-            for (size_t e = 0; e < E.eps.size(); ++e) {
-                const DevEPass &ep = E.eps[e];
-                const size_t lds = (sizeof(V2<R>) << ep.m) + 8 * (1u << (ep.m - ep.l));
-                set_lds_limit((const void *)k_expect_tile<R>, lds);
-                const unsigned grid =
-                    (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ep.ntiles * nc, (uint64_t)ctx->cu_count * 8));
-                LaunchScope ls(ctx, "expect_tile", (double)sbytes * nc);
-                hipLaunchKernelGGL(k_expect_tile<R>, dim3(grid), dim3(EXPT_TPB), lds, ctx->stream, slab, dim, nc,
-                                   (const DevEPass *)(ebase + o_ep), (int)e, (const uint64_t *)(ebase + o_aux),
-                                   (const uint32_t *)(ebase + o_gxl), (const int *)(ebase + o_gb),
-                                   (const int *)(ebase + o_ge), (const DevTerm *)(ebase + o_t),
-                                   (const int *)(ebase + o_ts), E.part_stride, part);
-                SV_HIP(hipGetLastError());
-            }
-            hipLaunchKernelGGL(k_expect_final, dim3(std::min(nc, ctx->cu_count * 4)), dim3(256), 0, ctx->stream, part,
-                               E.part_stride, nc, (const int *)(ebase + o_to), (const int *)(ebase + o_tc), E.T,
-                               (const double *)(ebase + o_cf), (const int *)(obase + o_os), d_E);
-            SV_HIP(hipGetLastError());
+            launch_expect<R>(ctx, E, ed, slab, dim, nc, (const int *)(obase + o_os), d_E, nullptr);
         }
     }
 }
@@ -630,8 +379,8 @@ void run_large_sequential(Ctx *ctx, const BatchSpec &spec, const std::vector<int
             run_unfused(ctx, &st, ops);
         } else {
             PlanOptions po;
-            po.tile_bits = spec.dtype == SV_C64 ? ctx->tile_bits_c64 : ctx->tile_bits_c128;
-            po.perm_bits = spec.dtype == SV_C64 ? 12 : 11;
+            po.tile_bits = ctx->tile_bits[spec.dtype];
+            po.perm_bits = ctx->perm_bits[spec.dtype];
             run_plan(ctx, &st, make_plan(bc.n, ops, po));
         }
         if (!have[bc.ham]) {

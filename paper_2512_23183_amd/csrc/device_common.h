@@ -769,4 +769,67 @@ inline DevTerms build_dev_terms(const TermGroups &tg) {
     return d;
 }
 
+
+// ---------------------------------------------------------------------------
+// Expectation plans: passes of tile-resident Pauli groups (see expect.hip)
+// ---------------------------------------------------------------------------
+
+struct alignas(16) EPass {
+    int32_t m, l;              // local bits, low contiguous run
+    int32_t g_begin, g_end;    // group chunks
+    int32_t hi_begin, nslots;  // hi-offset table in aux; terms (LDS slots)
+    uint32_t vb;               // workgroups per circuit
+    int32_t wide;              // 1: supports wider than a tile, read from HBM
+    uint64_t free_mask, ntiles;  // wide: ntiles = pairs per workgroup
+    uint64_t part_off;         // this pass's partials inside a circuit's row
+};
+
+struct alignas(16) EGroup {
+    uint32_t xl;       // X/Y support in tile coordinates
+    int32_t pim;       // uses Im (odd ny) instead of Re of conj(b) a
+    int32_t tbeg, tend;
+    uint64_t x, pad;   // X/Y support (global bits)
+};
+
+struct alignas(16) ETerm {
+    uint64_t z;        // Z/Y support (global bits)
+    uint32_t zl;       // its local part in tile coordinates
+    uint16_t slot;
+    uint8_t diag, neg;
+};
+
+struct ETermRef {
+    uint64_t off;      // first partial in a circuit's row
+    uint32_t stride, cnt;
+};
+
+struct EPlanHost {
+    int n = 0, T = 0;
+    bool ok = true;
+    std::string why;
+    std::vector<EPass> passes;
+    std::vector<uint64_t> aux;
+    std::vector<EGroup> groups;
+    std::vector<ETerm> terms;
+    std::vector<ETermRef> refs;  // by term index, T = norm
+    std::vector<double> coeffs;
+    uint64_t part_stride = 0;    // doubles per circuit
+};
+
+struct EPlanDev {
+    const EPass *passes;
+    const uint64_t *aux;
+    const EGroup *groups;
+    const ETerm *terms;
+    const ETermRef *refs;
+    const double *coeffs;
+};
+
+EPlanHost make_eplan(int n, int m_max, const DevTerms &dt);
+EPlanDev upload_eplan(Ctx *ctx, const EPlanHost &E, const char *slot);
+int expect_tile_bits(const Ctx *ctx, int dtype);
+template <typename R>
+void launch_expect(Ctx *ctx, const EPlanHost &E, const EPlanDev &d, const V2<R> *slab, uint64_t dim, int nc,
+                   const int *d_out_slot, double *d_E, double *d_vals);
+
 }  // namespace sv

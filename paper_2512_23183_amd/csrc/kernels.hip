@@ -292,87 +292,6 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uin
     }
 }
 
-// ---------------------------------------------------------------------------
-// FP64 expectation values
-// ---------------------------------------------------------------------------
-
-constexpr int EXP_TPB = 256;
-constexpr int EXP_CHUNK = 8;  // terms accumulated per sweep over the items
-
-// grid (nb, ngroups).  Terms of group g are tg[gbeg[g] .. gend[g]).
-// partial[term.idx * nb + blockIdx.x] receives the block's FP64 sum.
-template <typename R>
-__global__ __launch_bounds__(EXP_TPB) void k_expect1(const V2<R> *__restrict__ psi, int n,
-                                                     const DevTerm *__restrict__ tg,
-                                                     const int *__restrict__ gbeg,
-                                                     const int *__restrict__ gend,
-                                                     const uint64_t *__restrict__ gx, int nb,
-                                                     double *__restrict__ partial) {
-    __shared__ double red[EXP_TPB / 64];
-    const int g = blockIdx.y;
-    const uint64_t x = gx[g];
-    const int hb = x ? 63 - __clzll(x) : -1;
-    const uint64_t items = x ? (1ull << (n - 1)) : (1ull << n);
-    const uint64_t stride = (uint64_t)nb * EXP_TPB;
-    const uint64_t start = (uint64_t)blockIdx.x * EXP_TPB + threadIdx.x;
-    for (int t0 = gbeg[g]; t0 < gend[g]; t0 += EXP_CHUNK) {
-        const int cnt = min(EXP_CHUNK, gend[g] - t0);
-        double acc[EXP_CHUNK];
-#pragma unroll
-        for (int i = 0; i < EXP_CHUNK; ++i) acc[i] = 0.0;
-        for (uint64_t it = start; it < items; it += stride) {
-            if (x == 0) {
-                const V2<R> a = psi[it];
-                const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
-#pragma unroll
-                for (int i = 0; i < EXP_CHUNK; ++i)
-                    if (i < cnt) acc[i] += (__popcll(it & tg[t0 + i].z) & 1) ? -p : p;
-            } else {
-                const uint64_t k = ((it >> hb) << (hb + 1)) | (it & ((1ull << hb) - 1));
-                const uint64_t k2 = k ^ x;
-                const V2<R> a = psi[k], b = psi[k2];
-                const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
-                const double pre = bx * ax + by * ay, pim = bx * ay - by * ax;  // conj(b) a
-#pragma unroll
-                for (int i = 0; i < EXP_CHUNK; ++i)
-                    if (i < cnt) acc[i] += pair_contrib(pre, pim, k, k2, tg[t0 + i].z, tg[t0 + i].ny);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < EXP_CHUNK; ++i) {
-            if (i < cnt) {
-                const double s = block_sum<EXP_TPB>(acc[i], red);
-                if (threadIdx.x == 0) partial[(size_t)tg[t0 + i].idx * nb + blockIdx.x] = s;
-            }
-        }
-    }
-}
-
-// Stage 2: value[t] = sum_b partial[t*nb + b] (ascending b); then
-// E = (sum_t c_t value[t]) / value[T] in term order.  vals_out[t] =
-// value[t] / norm for t < T, vals_out[T] = norm; *energy_out = E.
-__global__ void k_expect2(double *__restrict__ partial, int nb, int T, const double *__restrict__ coeffs,
-                          double *__restrict__ vals_out, double *__restrict__ energy_out) {
-    // each thread owns rows t: sums them in ascending b and parks the value
-    // in partial[t * nb] (the row's first slot)
-    for (int t = threadIdx.x; t <= T; t += blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += partial[(size_t)t * nb + b];
-        partial[(size_t)t * nb] = s;
-    }
-    __threadfence_block();
-    __syncthreads();
-    const double norm = partial[(size_t)T * nb];
-    if (threadIdx.x == 0) {
-        double e = 0.0;
-        for (int t = 0; t < T; ++t) e += coeffs[t] * partial[(size_t)t * nb];
-        *energy_out = e / norm;
-        if (vals_out) vals_out[T] = norm;
-    }
-    if (vals_out)
-        for (int t = threadIdx.x; t < T; t += blockDim.x) vals_out[t] = partial[(size_t)t * nb] / norm;
-}
-
 // ===========================================================================
 // Host side
 // ===========================================================================
@@ -760,72 +679,5 @@ void device_scale(Ctx *ctx, void *psi, int n, int dtype, double s) {
     SV_HIP(hipGetLastError());
 }
 
-// Two-stage FP64 expectation of a lowered Pauli sum.  The energy is written
-// to the device scalar d_energy; d_vals (nullable) receives the T + 1 values.
-template <typename R>
-static void expectation_dev_t(Ctx *ctx, const V2<R> *psi, int n, const DevTerms &dt, double *d_energy,
-                              double *d_vals) {
-    const int T = dt.T, G = (int)dt.gx.size();
-    if (G > 65535) fail(SV_EINVAL, "more than 65535 distinct X/Y supports in one Pauli sum");
-    const uint64_t items = 1ull << (n > 0 ? n - 1 : 0);
-    const int nb = (int)std::min<uint64_t>(1024, std::max<uint64_t>(1, items / (EXP_TPB * 16)));
-    const size_t tb = dt.terms.size() * sizeof(DevTerm);
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t o_gb = al(tb), o_ge = o_gb + al(G * 4), o_gx = o_ge + al(G * 4), o_c = o_gx + al(G * 8);
-    const size_t total = o_c + al(dt.coeffs.size() * 8);
-    std::vector<unsigned char> host(total, 0);
-    std::memcpy(host.data(), dt.terms.data(), tb);
-    std::memcpy(host.data() + o_gb, dt.gbeg.data(), G * 4);
-    std::memcpy(host.data() + o_ge, dt.gend.data(), G * 4);
-    std::memcpy(host.data() + o_gx, dt.gx.data(), G * 8);
-    std::memcpy(host.data() + o_c, dt.coeffs.data(), dt.coeffs.size() * 8);
-    char *buf = (char *)scratch(ctx, "exp_meta", total);
-    upload(ctx, buf, host.data(), total);
-    double *d_partial = (double *)scratch(ctx, "exp_partial", (size_t)(T + 1) * nb * 8);
-    {
-        LaunchScope ls(ctx, "expect1", (double)sizeof(V2<R>) * (double)(1ull << n) * G);
-        hipLaunchKernelGGL(k_expect1<R>, dim3(nb, G), dim3(EXP_TPB), 0, ctx->stream, psi, n,
-                           (const DevTerm *)buf, (const int *)(buf + o_gb), (const int *)(buf + o_ge),
-                           (const uint64_t *)(buf + o_gx), nb, d_partial);
-        SV_HIP(hipGetLastError());
-    }
-    hipLaunchKernelGGL(k_expect2, dim3(1), dim3(256), 0, ctx->stream, d_partial, nb, T,
-                       (const double *)(buf + o_c), d_vals, d_energy);
-    SV_HIP(hipGetLastError());
-}
-
-void expectation_dev(Ctx *ctx, const void *psi, int n, int dtype, const DevTerms &dt, double *d_energy,
-                     double *d_vals) {
-    if (dtype == SV_C64) expectation_dev_t<float>(ctx, (const V2<float> *)psi, n, dt, d_energy, d_vals);
-    else expectation_dev_t<double>(ctx, (const V2<double> *)psi, n, dt, d_energy, d_vals);
-}
-
-template <typename R>
-static void expectation_t(Ctx *ctx, const V2<R> *psi, int n, const TermGroups &tg, double *energy,
-                          double *term_values, double *norm2) {
-    DevTerms dt = build_dev_terms(tg);
-    const int T = dt.T;
-    double *d_out = (double *)scratch(ctx, "exp_out", (size_t)(T + 2) * 8);
-    expectation_dev_t<R>(ctx, psi, n, dt, d_out, d_out + 1);
-    std::vector<double> out(T + 2);
-    SV_HIP(hipMemcpyAsync(out.data(), d_out, (T + 2) * 8, hipMemcpyDeviceToHost, ctx->stream));
-    SV_HIP(hipStreamSynchronize(ctx->stream));
-    if (ctx->profile) profile_collect(ctx);
-    if (energy) *energy = out[0];
-    if (term_values)
-        for (int t = 0; t < T; ++t) term_values[t] = out[1 + t];
-    if (norm2) *norm2 = out[1 + T];
-}
-
-void device_expectation(Ctx *ctx, const void *psi, int n, int dtype, const TermGroups &tg,
-                        double *energy, double *term_values, double *norm2) {
-    if (dtype == SV_C64) expectation_t<float>(ctx, (const V2<float> *)psi, n, tg, energy, term_values, norm2);
-    else expectation_t<double>(ctx, (const V2<double> *)psi, n, tg, energy, term_values, norm2);
-}
-
-void device_norm2(Ctx *ctx, const void *psi, int n, int dtype, double *out) {
-    TermGroups empty;
-    device_expectation(ctx, psi, n, dtype, empty, nullptr, nullptr, out);
-}
 
 }  // namespace sv

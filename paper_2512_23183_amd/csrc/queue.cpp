@@ -329,8 +329,11 @@ int sv_queue_create(sv_ctx *ctx_, size_t hbm_budget_bytes, sv_queue **out) {
         q->ctx = new Ctx();
         q->ctx->device = ctx->device;
         q->ctx->cu_count = ctx->cu_count;
-        q->ctx->tile_bits_c64 = ctx->tile_bits_c64;
-        q->ctx->tile_bits_c128 = ctx->tile_bits_c128;
+        for (int d = 0; d < 2; ++d) {
+            q->ctx->tile_bits[d] = ctx->tile_bits[d];
+            q->ctx->expect_bits[d] = ctx->expect_bits[d];
+            q->ctx->perm_bits[d] = ctx->perm_bits[d];
+        }
         if (hipStreamCreateWithFlags(&q->ctx->own_stream, hipStreamNonBlocking) != hipSuccess) {
             delete q->ctx;
             delete q;

@@ -208,7 +208,11 @@ struct Ctx {
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
     int cu_count = 0;
-    int tile_bits_c64 = 13, tile_bits_c128 = 12;
+    // widths in bits, indexed by dtype (0 = complex64, 1 = complex128):
+    // gate tile passes, expectation passes, permutation passes
+    int tile_bits[2] = {13, 12};
+    int expect_bits[2] = {13, 12};
+    int perm_bits[2] = {12, 11};
     std::mutex mu;
     // scratch buffers reused across calls (grown on demand)
     std::map<std::string, DeviceBuffer> scratch;

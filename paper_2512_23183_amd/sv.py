@@ -46,7 +46,9 @@ class _PauliSum(ctypes.Structure):
 
 class _Config(ctypes.Structure):
     _fields_ = [("tile_bits_c64", ctypes.c_int32), ("tile_bits_c128", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("expect_bits_c64", ctypes.c_int32), ("expect_bits_c128", ctypes.c_int32),
+                ("perm_bits_c64", ctypes.c_int32), ("perm_bits_c128", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class _Request(ctypes.Structure):
@@ -188,8 +190,11 @@ def _np_dtype(dtype: int):
 
 
 class Context:
-    def __init__(self, device: int = 0, tile_bits_c64: int = 0, tile_bits_c128: int = 0):
-        cfg = _Config(tile_bits_c64, tile_bits_c128)
+    def __init__(self, device: int = 0, tile_bits_c64: int = 0, tile_bits_c128: int = 0,
+                 expect_bits_c64: int = 0, expect_bits_c128: int = 0,
+                 perm_bits_c64: int = 0, perm_bits_c128: int = 0):
+        cfg = _Config(tile_bits_c64, tile_bits_c128, expect_bits_c64, expect_bits_c128,
+                      perm_bits_c64, perm_bits_c128)
         h = _vp()
         _check(lib().sv_init(ctypes.byref(h), device, ctypes.byref(cfg)))
         self.h = h

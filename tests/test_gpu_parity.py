@@ -149,6 +149,80 @@ def test_expectation_vs_oracle(ctx, n, T, seed, dtype):
     st.free()
 
 
+def _mixed_pauli_sum(n, seed, n_random, n_diag):
+    """Random strings of every weight (X/Y supports up to the full width),
+    one X/Y support shared by 32 terms of every Y parity, and n_diag Z-only
+    strings (more than one expectation pass holds)."""
+    rng = np.random.default_rng(seed)
+    terms = []
+    for _ in range(n_random):
+        w = int(rng.integers(1, n + 1))
+        s = ["I"] * n
+        for q in rng.choice(n, w, replace=False):
+            s[q] = "XYZ"[int(rng.integers(0, 3))]
+        terms.append((float(rng.normal()), "".join(s)))
+    for a in "XY":
+        for b in "XY":
+            for zpat in range(8):
+                s = ["I"] * n
+                s[0], s[n - 1] = a, b
+                for i, q in enumerate((1, 2, n - 2)):
+                    if (zpat >> i) & 1:
+                        s[q] = "Z"
+                terms.append((float(rng.normal()), "".join(s)))
+    seen = set()
+    while len(seen) < n_diag:
+        z = int(rng.integers(1, 1 << n))
+        if z in seen:
+            continue
+        seen.add(z)
+        terms.append((float(rng.normal()) * 0.01,
+                      "".join("Z" if (z >> q) & 1 else "I" for q in range(n))))
+    order = rng.permutation(len(terms))
+    return I.PauliSum.from_strings(n, [terms[i] for i in order])
+
+
+@pytest.mark.parametrize("bits", [0, 6, 9])
+@pytest.mark.parametrize("n", [7, 12])
+def test_expectation_widths_supports_and_many_terms(sv, n, bits):
+    # tile widths from 6 bits (wide supports go to the HBM pair pass) to the
+    # default; > 1024 diagonal terms split the diagonal group across passes
+    ham = _mixed_pauli_sum(n, 100 + n + bits, 120, min(1100, (1 << n) - 1))
+    psi = I.gaussian_state(n, 7 + bits)
+    strings = ham.strings()
+    ref = np.array([oracle.pauli_expectation(psi, s).real for s in strings])
+    e_ref = float(np.dot(ham.coeffs, ref))
+    c = sv.Context(0, expect_bits_c64=bits, expect_bits_c128=bits)
+    try:
+        for dtype, tol in ((C128, 1e-10), (C64, 1e-5)):
+            st = c.alloc(n, dtype)
+            st.set_amplitudes(psi)
+            e, tv = st.expectation(ham, terms=True)
+            st.free()
+            assert abs(e - e_ref) <= tol * max(1.0, np.sum(np.abs(ham.coeffs)) / 50), (dtype, e, e_ref)
+            assert np.max(np.abs(tv - ref)) <= tol, dtype
+    finally:
+        c.close()
+
+
+def test_batched_gradient_narrow_expectation_tiles(sv):
+    # the multi-pass batched path with several expectation passes per circuit
+    n = 14
+    circ = I.hea_circuit(n, 1)
+    params = I.uniform_params(circ.n_params, 21)
+    ham = _mixed_pauli_sum(n, 22, 40, 30)
+    e_ref, g_ref = oracle.param_shift(circ, params, ham)
+    c = sv.Context(0, expect_bits_c64=7, expect_bits_c128=7)
+    try:
+        for dtype, tol in ((C128, 1e-10), (C64, 1e-5)):
+            e, g = c.param_shift_grad(circ, params, ham, dtype)
+            scale = max(1.0, np.sum(np.abs(ham.coeffs)) / 50)
+            assert abs(e - e_ref) <= tol * scale
+            assert np.max(np.abs(g - g_ref)) <= tol * scale
+    finally:
+        c.close()
+
+
 def test_expectation_renormalises(ctx):
     n = 9
     ham = I.random_2local(n, 40, 5)
