@@ -41,20 +41,26 @@ def qft_gates(n):
     return n + n * (n - 1) // 2 + n // 2
 
 
+def sync_all(ctx):
+    import torch
+    ctx.synchronize()
+    torch.cuda.synchronize()
+
+
 def time_qft(ctx, sv, n, dtype, steps, warmup, flags=0, psi=None, profile=False):
     st = ctx.alloc(n, dtype)
     if psi is not None:
         st.set_amplitudes(psi)
     for _ in range(warmup):
         st.qft(flags)
-    ctx.synchronize()
+    sync_all(ctx)
     if profile:
         ctx.profile_reset()
         ctx.profile(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         st.qft(flags)
-    ctx.synchronize()
+    sync_all(ctx)
     dt = time.perf_counter() - t0
     prof = {}
     if profile:
@@ -190,8 +196,10 @@ def bench_serving(ctx, sv, inputs, count, seed=5):
         if r.grad:
             ctx.param_shift_grad(r.circuit, r.params, r.hamiltonian, sv.C64, sv.FLAG_SEQUENTIAL)
         else:
-            ctx.param_shift_grad(r.circuit, r.params[:0] if False else r.params, r.hamiltonian, sv.C64,
-                                 sv.FLAG_SEQUENTIAL)
+            st = ctx.alloc(r.circuit.n, sv.C64)
+            st.apply(r.circuit, r.params)
+            st.expectation(r.hamiltonian)
+            st.free()
     serial_dt = (time.perf_counter() - t0) / max(4, count // 8)
     mu = 1.0 / serial_dt
     out = {"requests": count, "serial_req_per_s": mu, "n_range": [8, 20], "depth_range": [2, 6]}
@@ -205,8 +213,7 @@ def bench_serving(ctx, sv, inputs, count, seed=5):
             now = time.perf_counter() - t_start
             if r.arrival_s > now:
                 time.sleep(r.arrival_s - now)
-            p = r.params if r.grad else r.params
-            tickets.append(q.submit(r.circuit, p, r.hamiltonian, r.grad, sv.C64))
+            tickets.append(q.submit(r.circuit, r.params, r.hamiltonian, r.grad, sv.C64))
         lat = []
         for t in tickets:
             _, _, l = q.wait(t)
@@ -221,6 +228,52 @@ def bench_serving(ctx, sv, inputs, count, seed=5):
                                "launches": st["launches"], "circuits": st["circuits_run"]}
         log(f"[bench] serving load {load}: p50 {out[f'load_{load}']['p50_ms']:.1f} ms")
     return out
+
+
+# Sources that decide what the headline tile kernel reads and writes; the
+# recorded counter traffic is reported only while they are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_qft28_c64_traffic.md")
+TRAFFIC_SOURCES = ["paper_2512_23183_amd/csrc/kernels.hip", "paper_2512_23183_amd/csrc/device_common.h",
+                   "paper_2512_23183_amd/csrc/plan.cpp", "paper_2512_23183_amd/csrc/lower.cpp"]
+
+
+def traffic_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per headline tile launch from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when it is missing or stale."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    vals = dict(line.split(":", 1) for line in text.splitlines()
+                if line.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+    if vals.get("source_sha256", "").strip() != traffic_sources_sha():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain streaming kernel of known size (read 1 GiB, write 1 GiB per
+    dispatch) whose FETCH_SIZE / WRITE_SIZE scale the counter readings."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "dispatches": 3}), flush=True)
 
 
 def cpu_baseline(oracle_mod, inputs):
@@ -243,7 +296,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--serving", type=int, default=48, help="serving sample size (0 = skip)")
+    ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain streaming kernel used to scale HBM byte counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(this build runs on a single MI355X)", file=sys.stderr)
@@ -270,7 +329,7 @@ def main():
         extras["deep30_c64"] = bench_deep30(ctx, sv, inputs)
         if args.serving > 0:
             extras["serving"] = bench_serving(ctx, sv, inputs, args.serving)
-    cpu = cpu_baseline(oracle, inputs) if rank == 0 else None
+    cpu = cpu_baseline(oracle, inputs) if rank == 0 and not args.skip_cpu else None
     ctx.close()
     frac = head["achieved_gbs"] / HBM_PEAK_GBS
     line = {
@@ -282,7 +341,7 @@ def main():
                    "input": "iid complex Gaussian, normalised (seed 2)",
                    "passes_per_step": head["passes_per_step"]},
         "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": frac, "traffic": None, "kernel": "k_tile (fused LDS tile pass)",
+                     "frac": frac, "traffic": recorded_traffic(), "kernel": "k_tile (fused LDS tile pass)",
                      "bytes_per_launch": 2 * head["S"], "avg_launch_ms": head["tile_avg_ms"]},
         "cpu_baseline": cpu,
         "extras": extras,
