@@ -313,6 +313,12 @@ def main():
     from paper_2512_23183_amd import sv
 
     ctx = sv.Context(0)
+    # tile widths from the library's autotuner (cache in the temp directory)
+    import tempfile
+    cache = os.path.join(tempfile.gettempdir(), "sv_autotune_cache.txt")
+    ctx.autotune(sv.C128, 27, cache)
+    tuned = ctx.autotune(sv.C64, 28, cache)
+    log(f"[bench] autotuned widths: {tuned}")
     head = bench_qft_headline(ctx, sv, inputs, args)
     extras = {}
     if not args.quick:
@@ -339,7 +345,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "qft_gate_based_n28_complex64", "n_qubits": 28, "logical_gates": head["gates"],
                    "input": "iid complex Gaussian, normalised (seed 2)",
-                   "passes_per_step": head["passes_per_step"]},
+                   "passes_per_step": head["passes_per_step"], "autotuned_widths": tuned},
         "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": frac, "traffic": recorded_traffic(), "kernel": "k_tile (fused LDS tile pass)",
                      "bytes_per_launch": 2 * head["S"], "avg_launch_ms": head["tile_avg_ms"]},

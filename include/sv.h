@@ -159,7 +159,7 @@ enum {
  */
 typedef struct sv_config {
     int32_t tile_bits_c64;     /* gate tile pass width (bits), complex64: 6..14, 0 = default 13 */
-    int32_t tile_bits_c128;    /* same for complex128: 6..13, 0 = default 12 */
+    int32_t tile_bits_c128;    /* same for complex128: 6..12, 0 = default 12 */
     int32_t expect_bits_c64;   /* expectation pass tile width, complex64: 6..14, 0 = default 13 */
     int32_t expect_bits_c128;  /* same for complex128: 6..13, 0 = default 12 */
     int32_t perm_bits_c64;     /* permutation pass tile width, complex64: 6..12, 0 = default 12 */
@@ -308,6 +308,18 @@ int sv_profile_get(sv_ctx *ctx, const char *name, double *total_ms,
 int sv_profile_reset(sv_ctx *ctx);
 
 const char *sv_last_error(void);
+/*
+ * Autotuner: times the gate tile width, then the permutation width, then the
+ * expectation tile width of dtype on synthetic work of n_qubits qubits (a
+ * gate-based QFT plus two RY/RZ + CNOT-ladder layers; a 2-local Pauli sum),
+ * clamped to 8..28 qubits (27 for complex128), and keeps the fastest in ctx.
+ * cache_path (nullable): a text file with one line per device, dtype and
+ * size; a valid line is used without timing, a new result is appended.
+ * chosen (nullable) receives every width of ctx afterwards.  Needs a free
+ * state of the clamped size in HBM; takes about a second at 28 qubits.
+ */
+int sv_autotune(sv_ctx *ctx, int dtype, int n_qubits, const char *cache_path, sv_config *chosen);
+
 const char *sv_version(void);
 
 #ifdef __cplusplus

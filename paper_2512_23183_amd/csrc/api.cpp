@@ -197,12 +197,12 @@ int sv_init(sv_ctx **out, int device, const sv_config *cfg) {
             auto pick = [](int32_t v, int lo, int hi, int &dst) {
                 if (v > 0) dst = std::max(lo, std::min(hi, (int)v));
             };
-            pick(cfg->tile_bits_c64, 6, 14, ctx->tile_bits[SV_C64]);
-            pick(cfg->tile_bits_c128, 6, 13, ctx->tile_bits[SV_C128]);
-            pick(cfg->expect_bits_c64, 6, 14, ctx->expect_bits[SV_C64]);
-            pick(cfg->expect_bits_c128, 6, 13, ctx->expect_bits[SV_C128]);
-            pick(cfg->perm_bits_c64, 6, 12, ctx->perm_bits[SV_C64]);
-            pick(cfg->perm_bits_c128, 6, 11, ctx->perm_bits[SV_C128]);
+            pick(cfg->tile_bits_c64, 6, TILE_MAX[SV_C64], ctx->tile_bits[SV_C64]);
+            pick(cfg->tile_bits_c128, 6, TILE_MAX[SV_C128], ctx->tile_bits[SV_C128]);
+            pick(cfg->expect_bits_c64, 6, EXPECT_MAX[SV_C64], ctx->expect_bits[SV_C64]);
+            pick(cfg->expect_bits_c128, 6, EXPECT_MAX[SV_C128], ctx->expect_bits[SV_C128]);
+            pick(cfg->perm_bits_c64, 6, PERM_MAX[SV_C64], ctx->perm_bits[SV_C64]);
+            pick(cfg->perm_bits_c128, 6, PERM_MAX[SV_C128], ctx->perm_bits[SV_C128]);
         }
         *out = ctx;
     });
@@ -486,6 +486,24 @@ int sv_profile_reset(sv_ctx *ctx) {
         SV_HIP(hipStreamSynchronize(ctx->stream));
         profile_collect(ctx);
         ctx->prof.clear();
+    });
+}
+
+int sv_autotune(sv_ctx *ctx, int dtype, int n_qubits, const char *cache_path, sv_config *chosen) {
+    return guard([&] {
+        need(ctx != nullptr, "ctx is NULL");
+        check_dtype(dtype);
+        use_device(ctx);
+        autotune(ctx, ctx, dtype, n_qubits, cache_path);
+        if (chosen) {
+            std::memset(chosen, 0, sizeof *chosen);
+            chosen->tile_bits_c64 = ctx->tile_bits[SV_C64];
+            chosen->tile_bits_c128 = ctx->tile_bits[SV_C128];
+            chosen->expect_bits_c64 = ctx->expect_bits[SV_C64];
+            chosen->expect_bits_c128 = ctx->expect_bits[SV_C128];
+            chosen->perm_bits_c64 = ctx->perm_bits[SV_C64];
+            chosen->perm_bits_c128 = ctx->perm_bits[SV_C128];
+        }
     });
 }
 

@@ -203,6 +203,13 @@ struct DeviceBuffer {
     size_t bytes = 0;
 };
 
+// Largest tile widths whose LDS footprint fits one workgroup (160 KiB):
+// gate tiles hold 2^m amplitudes plus up to four ladder tables, expectation
+// tiles 2^m amplitudes plus term accumulators, permutation passes two tiles.
+constexpr int TILE_MAX[2] = {14, 12};
+constexpr int EXPECT_MAX[2] = {14, 13};
+constexpr int PERM_MAX[2] = {12, 11};
+
 struct Ctx {
     int device = 0;
     hipStream_t own_stream = nullptr;
@@ -210,6 +217,7 @@ struct Ctx {
     int cu_count = 0;
     // widths in bits, indexed by dtype (0 = complex64, 1 = complex128):
     // gate tile passes, expectation passes, permutation passes
+    // (ranges: TILE_MAX / EXPECT_MAX / PERM_MAX below, minimum 6)
     int tile_bits[2] = {13, 12};
     int expect_bits[2] = {13, 12};
     int perm_bits[2] = {12, 11};
@@ -256,6 +264,9 @@ void run_plan(Ctx *ctx, State *st, const Plan &plan);
 // One-gate-per-launch sweeps (the plain path).
 void run_unfused(Ctx *ctx, State *st, const std::vector<Op> &ops);
 void set_zero_state(Ctx *ctx, void *psi, int n, int dtype);
+// Tile-width autotuner (tune.cpp): times candidates through the public
+// entry points on the handle ctx_ (the same context as ctx).
+void autotune(Ctx *ctx, sv_ctx *ctx_, int dtype, int n_qubits, const char *cache_path);
 void device_norm2(Ctx *ctx, const void *psi, int n, int dtype, double *out);
 void device_scale(Ctx *ctx, void *psi, int n, int dtype, double s);
 // FP64 expectation of a lowered Pauli sum: fills per-term values (already

@@ -123,6 +123,7 @@ def lib():
             "sv_profile_enable": [_vp, ctypes.c_int],
             "sv_profile_get": [_vp, ctypes.c_char_p, _dp, ctypes.POINTER(ctypes.c_uint64), _dp],
             "sv_profile_reset": [_vp],
+            "sv_autotune": [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(_Config)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -215,6 +216,14 @@ class Context:
 
     def synchronize(self):
         _check(lib().sv_synchronize(self.h))
+
+    def autotune(self, dtype: int, n_qubits: int, cache_path: Optional[str] = None) -> dict:
+        """Time candidate tile widths for dtype at n_qubits and keep the
+        fastest in this context; returns every width of the context."""
+        cfg = _Config()
+        _check(lib().sv_autotune(self.h, dtype, n_qubits,
+                                 cache_path.encode() if cache_path else None, ctypes.byref(cfg)))
+        return {k: getattr(cfg, k) for k, _ in _Config._fields_ if k != "reserved"}
 
     def profile(self, on: bool = True):
         _check(lib().sv_profile_enable(self.h, 1 if on else 0))

@@ -134,3 +134,9 @@ def test_no_device_is_reported(sv):
     with pytest.raises(sv.SvError) as e:
         sv.Context(0)
     assert e.value.name == "SV_ENODEV"
+
+
+def test_autotune_rejects_bad_arguments(sv):
+    L = sv.lib()
+    cfg = sv._Config()
+    assert L.sv_autotune(None, 0, 20, None, ctypes.byref(cfg)) == -1      # SV_EINVAL: no context

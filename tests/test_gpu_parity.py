@@ -382,3 +382,31 @@ def test_torch_tensor_as_state(ctx, sv):
     want = oracle.run_circuit(c, p, psi0)
     assert np.max(np.abs(got - want)) <= 1e-12
     st.free()
+
+
+def test_autotune_picks_valid_widths_and_caches(sv, tmp_path):
+    cache = str(tmp_path / "tune.txt")
+    c = sv.Context(0)
+    try:
+        first = c.autotune(C64, 14, cache)
+        assert 11 <= first["tile_bits_c64"] <= 14 and 11 <= first["expect_bits_c64"] <= 14
+        assert 10 <= first["perm_bits_c64"] <= 12
+        lines = open(cache).read().splitlines()
+        assert len(lines) == 1 and "dtype0 n14" in lines[0]
+        second = c.autotune(C64, 14, cache)        # cache hit: same widths, no new line
+        assert second == first
+        assert len(open(cache).read().splitlines()) == 1
+        tuned = c.autotune(C128, 13)
+        assert 9 <= tuned["tile_bits_c128"] <= 12
+        # the tuned context still matches the oracle
+        n = 14
+        circ = I.random_circuit(n, 120, 31, n_params=4)
+        params = I.uniform_params(circ.n_params, 32)
+        psi0 = I.gaussian_state(n, 33)
+        want = oracle.run_circuit(circ, params, psi0)
+        for dtype in (C64, C128):
+            got = run_gpu(c, circ, params, psi0, dtype)
+            ok, err = amp_tol_ok(got, want, dtype, circ.n_gates)
+            assert ok, (dtype, err)
+    finally:
+        c.close()
