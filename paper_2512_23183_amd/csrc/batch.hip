@@ -40,7 +40,7 @@ template <typename R>
 __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
     const DevCirc *__restrict__ circ, int ncirc, unsigned *__restrict__ counter,
     const DevOp<R> *__restrict__ ops, const DevStage *__restrict__ stages, const V2<R> *__restrict__ ltab,
-    const DevOp<R> *__restrict__ ovr_ops,
+    const uint32_t *__restrict__ paux, const DevOp<R> *__restrict__ ovr_ops,
     const DevTerm *__restrict__ terms, const int *__restrict__ gbeg, const int *__restrict__ gend,
     const uint64_t *__restrict__ gx, const double *__restrict__ coeffs, double *__restrict__ energies,
     int max_n, int max_T) {
@@ -71,6 +71,7 @@ __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
         tc.lowm = (1u << tc.l) - 1;
         tc.ident = true;
         tc.zero = false;
+        tc.paux = paux;
         tc.base = 0;
         tc.hi_off = nullptr;
         tc.tabs = tabs;
@@ -157,6 +158,7 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     std::vector<DevOp<R>> ovr;
     std::vector<DevStage> stages;
     std::vector<V2<R>> ltab;
+    std::vector<uint32_t> paux;
     std::vector<int> set_sb(spec.op_sets.size(), -1), set_se(spec.op_sets.size(), -1);
     int max_n = 3, max_T = 0;
     for (int c : idx) {
@@ -179,7 +181,7 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
             }
             set_end[bc.op_set] = (int)dops.size();
             set_sb[bc.op_set] = (int)stages.size();
-            build_stages<R>(dops, set_begin[bc.op_set], set_end[bc.op_set], n_eff, stages);
+            build_stages<R>(dops, set_begin[bc.op_set], set_end[bc.op_set], n_eff, stages, paux, false);
             set_se[bc.op_set] = (int)stages.size();
         }
         if (ham_gb[bc.ham] < 0) {
@@ -219,6 +221,7 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
             o.tslot = basep.tslot;
             o.lcmask = basep.lcmask;
             o.gcmask = basep.gcmask;
+            o.flags = (o.flags & ~OPF_PLACEMENT) | (basep.flags & OPF_PLACEMENT);
             ovr.push_back(o);
         }
         d.grp_begin = ham_gb[bc.ham];
@@ -231,6 +234,7 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
         max_T = std::max(max_T, d.T);
     }
     if (ovr.empty()) ovr.resize(1);
+    if (paux.empty()) paux.resize(1);
     // largest circuits first: better balance of the dynamic schedule
     std::stable_sort(circ.begin(), circ.end(), [](const DevCirc &a, const DevCirc &b) {
         return (a.op_end - a.op_begin) * (1ll << a.n) > (b.op_end - b.op_begin) * (1ll << b.n);
@@ -240,6 +244,7 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     const size_t o_ops = blob.add(dops.data(), dops.size() * sizeof(DevOp<R>));
     const size_t o_stg = blob.add(stages.data(), stages.size() * sizeof(DevStage));
     const size_t o_lt = blob.add(ltab.data(), ltab.size() * sizeof(V2<R>));
+    const size_t o_pa = blob.add(paux.data(), paux.size() * 4);
     const size_t o_ovr = blob.add(ovr.data(), ovr.size() * sizeof(DevOp<R>));
     const size_t o_t = blob.add(terms.data(), terms.size() * sizeof(DevTerm));
     const size_t o_gb = blob.add(gbeg.data(), gbeg.size() * 4);
@@ -264,7 +269,7 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     hipLaunchKernelGGL(k_small_batch<R>, dim3(grid), dim3(SMALL_TPB), lds, ctx->stream,
                        (const DevCirc *)(base + o_c), nc, d_cnt, (const DevOp<R> *)(base + o_ops),
                        (const DevStage *)(base + o_stg), (const V2<R> *)(base + o_lt),
-                       (const DevOp<R> *)(base + o_ovr),
+                       (const uint32_t *)(base + o_pa), (const DevOp<R> *)(base + o_ovr),
                        (const DevTerm *)(base + o_t), (const int *)(base + o_gb), (const int *)(base + o_ge),
                        (const uint64_t *)(base + o_gx), (const double *)(base + o_cf), d_E, max_n, max_T);
     SV_HIP(hipGetLastError());
@@ -336,6 +341,7 @@ void run_large_batched(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &
                 o.lcmask = bp.lcmask;
                 o.gcmask = bp.gcmask;
                 o.lmask = bp.lmask;
+                o.flags = (o.flags & ~OPF_PLACEMENT) | (bp.flags & OPF_PLACEMENT);
                 ovr[c] = o;
                 oidx[c] = it->second;
             }

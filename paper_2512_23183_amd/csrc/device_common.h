@@ -117,6 +117,7 @@ struct TileCtx {
     int lt;                   // table split: low table over local bits < lt
     int tstride;              // entries per table slot (2^lt + 2^(m-lt))
     bool zero;                // first global read synthesises |0...0>
+    const uint32_t *paux;     // stage store permutation tables
 };
 
 // Low-part width of the ladder tables (local bits below it are global bits).
@@ -387,6 +388,41 @@ __device__ __forceinline__ void rg_diag(Grp<R> &g, const uint64_t (&G)[3], const
     });
 }
 
+// Group factor of a DIAG op none of whose bits is a register bit: with k0
+// the global index of the group's element 0, the factor is d[2 bit_a +
+// bit_b] (or d[bit_a]) where all cmask bits are set, else 1.
+template <typename R>
+__device__ __forceinline__ V2<R> rg_diag_grp(V2<R> acc, uint64_t k0, const DevOp<R> &op) {
+    const uint64_t cm = op.cmask;
+    if ((k0 & cm) != cm) return acc;
+    const bool ba = (k0 >> op.a) & 1;
+    if (op.flags & OPF_NEG) {
+        const bool on = ba && (op.b < 0 || ((k0 >> op.b) & 1));
+        if (on) {
+            acc.x = -acc.x;
+            acc.y = -acc.y;
+        }
+        return acc;
+    }
+    V2<R> f;
+    if (op.b >= 0) {
+        const bool bb = (k0 >> op.b) & 1;
+        f = vsel(ba, vsel(bb, mat_at(op, 3), mat_at(op, 2)), vsel(bb, mat_at(op, 1), mat_at(op, 0)));
+    } else {
+        f = vsel(ba, mat_at(op, 1), mat_at(op, 0));
+    }
+    return cmul(acc, f);
+}
+
+// Multiply the elements whose register bit RB is set by r.
+template <int RB, typename R>
+__device__ __forceinline__ void rg_bit_scale(Grp<R> &g, const V2<R> r) {
+    static_for<0, 8>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        if constexpr ((e >> RB) & 1) el<e>(g) = cmul(el<e>(g), r);
+    });
+}
+
 // Ladder: where bit a is set, multiply by TL[j & ltm] * TH[j >> lt].  When
 // a is register bit RA (template), exactly the elements with that bit set
 // are touched; otherwise (RA < 0) bit a is the same for the whole group.
@@ -410,6 +446,64 @@ __device__ __forceinline__ void rg_ladder(Grp<R> &g, const uint32_t (&L)[3], con
 // MODE bit 0: read the group from global memory (else from the LDS tile);
 // MODE bit 1: write it to global memory (else to the LDS tile).  Each
 // thread handles groups threadIdx.x, +TPB, ... one at a time.
+// Apply the ops [op_begin, op_end) of stage S to one register group.
+template <typename R>
+__device__ __forceinline__ void stage_ops(Grp<R> &g, const TileCtx<R> &tc, const DevStage &S,
+                                          const uint32_t (&L)[3], const uint64_t (&G)[3],
+                                          const DevOp<R> *__restrict__ ops, int ovr_index, const DevOp<R> *ovr) {
+    // diagonal factor common to the whole group (OPF_GRP / OPF_REG1 ops):
+    // diagonal ops commute with each other and with every op on other bits,
+    // so it is applied once after the stage's ops
+    V2<R> acc;
+    acc.x = (R)1;
+    acc.y = (R)0;
+    for (int o = S.op_begin; o < S.op_end; ++o) {
+        const DevOp<R> &op = (o == ovr_index) ? *ovr : ops[o];
+        const int kind = op.kind;
+        if (kind == OP_U1 || kind == OP_XPERM) {
+            if ((tc.base & op.gcmask) != op.gcmask) continue;
+            if (kind == OP_XPERM) rg_u1_dispatch<2>(g, L, op);
+            else if (op.flags & OPF_REAL) rg_u1_dispatch<1>(g, L, op);
+            else rg_u1_dispatch<0>(g, L, op);
+        } else if (kind == OP_U2 || kind == OP_SWAP) {
+            if ((tc.base & op.gcmask) != op.gcmask) continue;
+            if (kind == OP_U2) rg_u2_dispatch<true>(g, (uint32_t)op.lcmask, L, op);
+            else rg_u2_dispatch<false>(g, (uint32_t)op.lcmask, L, op);
+        } else if (kind == OP_DIAG) {
+            if (op.flags & OPF_GRP) acc = rg_diag_grp<R>(acc, g.k0, op);
+            else if (op.flags & OPF_REG1) {
+                acc = cmul(acc, mat_at(op, 0));
+                const V2<R> r = mat_at(op, 4);
+                if (op.ra == 0) rg_bit_scale<0>(g, r);
+                else if (op.ra == 1) rg_bit_scale<1>(g, r);
+                else rg_bit_scale<2>(g, r);
+            }
+            else if (op.flags & OPF_NEG) rg_diag<true, true>(g, G, op);
+            else if (op.flags & OPF_PAT) rg_diag<true, false>(g, G, op);
+            else rg_diag<false, false>(g, G, op);
+        } else if (kind == OP_LADDER) {
+            if (op.ra == 0) rg_ladder<0>(g, L, op, tc);
+            else if (op.ra == 1) rg_ladder<1>(g, L, op, tc);
+            else if (op.ra == 2) rg_ladder<2>(g, L, op, tc);
+            else rg_ladder<-1>(g, L, op, tc);
+        }
+    }
+    if (S.acc) {
+        static_for<0, 8>([&](auto EC) {
+            constexpr int e = decltype(EC)::value;
+            el<e>(g) = cmul(el<e>(g), acc);
+        });
+    }
+}
+
+// MODE bit 0: read the groups from global memory (else from the LDS tile);
+// MODE bit 1: write them to global memory (else to the LDS tile).  Each
+// thread handles groups threadIdx.x, +TPB, ... one at a time.  Groups are
+// logical: element e of a group is local index j0 | loff(e).  With S.perm
+// the LDS holds local index j at position Q(j) = tab_lo[j & 127] ^
+// tab_hi[j >> 7] ^ q (the layout left by CNOT runs folded out of earlier
+// stages); loads and stores of a group use the same positions, so no
+// thread writes where another has yet to read.
 template <typename R, int TPB, int MODE>
 __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
                                           const DevStage &S, const DevOp<R> *__restrict__ ops,
@@ -418,11 +512,15 @@ __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi,
     const int r0 = S.r0, r1 = S.r1, r2 = S.r2;
     const uint32_t L[3] = {1u << r0, 1u << r1, 1u << r2};
     const uint64_t G[3] = {gbit(tc, r0), gbit(tc, r1), gbit(tc, r2)};
+    const bool perm = S.perm != 0;
     for (uint32_t it = threadIdx.x; it < nitems; it += TPB) {
         Grp<R> g;
         g.live = true;
         g.j0 = ins0(ins0(ins0(it, r0), r1), r2);
         g.k0 = gaddr(tc, g.j0);
+        // LDS position of element e: pos0 ^ pd[e] (layout map) or j0 | loff(e)
+        const uint32_t pos0 = perm ? tc.paux[S.perm_tab + (g.j0 & 127u)] ^ tc.paux[S.perm_tab + 128 + (g.j0 >> 7)]
+                                   : g.j0;
         static_for<0, 8>([&](auto EC) {
             constexpr int e = decltype(EC)::value;
             if constexpr (MODE & 1) {
@@ -434,36 +532,15 @@ __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi,
                 } else {
                     el<e>(g) = gpsi[g.k0 | goff<e>(G)];
                 }
+            } else {
+                el<e>(g) = tile[perm ? pos0 ^ (uint32_t)S.pd[e] : pos0 | loff<e>(L)];
             }
-            else el<e>(g) = tile[g.j0 | loff<e>(L)];
         });
-        for (int o = S.op_begin; o < S.op_end; ++o) {
-            const DevOp<R> &op = (o == ovr_index) ? *ovr : ops[o];
-            const int kind = op.kind;
-            if (kind == OP_U1 || kind == OP_XPERM) {
-                if ((tc.base & op.gcmask) != op.gcmask) continue;
-                if (kind == OP_XPERM) rg_u1_dispatch<2>(g, L, op);
-                else if (op.flags & OPF_REAL) rg_u1_dispatch<1>(g, L, op);
-                else rg_u1_dispatch<0>(g, L, op);
-            } else if (kind == OP_U2 || kind == OP_SWAP) {
-                if ((tc.base & op.gcmask) != op.gcmask) continue;
-                if (kind == OP_U2) rg_u2_dispatch<true>(g, (uint32_t)op.lcmask, L, op);
-                else rg_u2_dispatch<false>(g, (uint32_t)op.lcmask, L, op);
-            } else if (kind == OP_DIAG) {
-                if (op.flags & OPF_NEG) rg_diag<true, true>(g, G, op);
-                else if (op.flags & OPF_PAT) rg_diag<true, false>(g, G, op);
-                else rg_diag<false, false>(g, G, op);
-            } else if (kind == OP_LADDER) {
-                if (op.ra == 0) rg_ladder<0>(g, L, op, tc);
-                else if (op.ra == 1) rg_ladder<1>(g, L, op, tc);
-                else if (op.ra == 2) rg_ladder<2>(g, L, op, tc);
-                else rg_ladder<-1>(g, L, op, tc);
-            }
-        }
+        stage_ops<R>(g, tc, S, L, G, ops, ovr_index, ovr);
         static_for<0, 8>([&](auto EC) {
             constexpr int e = decltype(EC)::value;
             if constexpr (MODE & 2) gpsi[g.k0 | goff<e>(G)] = el<e>(g);
-            else tile[g.j0 | loff<e>(L)] = el<e>(g);
+            else tile[perm ? pos0 ^ (uint32_t)S.pd[e] : pos0 | loff<e>(L)] = el<e>(g);
         });
     }
 }
@@ -612,6 +689,11 @@ inline DevOp<R> to_dev(const Op &op) {
     if (op.kind == OP_U1 && op.m[0].imag() == 0.0 && op.m[1].imag() == 0.0 && op.m[2].imag() == 0.0 &&
         op.m[3].imag() == 0.0)
         d.flags |= OPF_REAL;
+    if (op.kind == OP_DIAG && op.b < 0 && op.m[0] != cd(0.0)) {
+        const cd r = op.m[1] / op.m[0];
+        d.m[8] = (R)r.real();
+        d.m[9] = (R)r.imag();
+    }
     if (op.kind == OP_DIAG) {
         const int last = op.b >= 0 ? 3 : 1;
         bool pat = true;
@@ -642,6 +724,15 @@ inline void localise(DevOp<R> &d, const std::vector<int> &local_bits) {
     for (int i = 0; i < 64; ++i) pos[i] = -1;
     for (size_t i = 0; i < local_bits.size(); ++i) pos[local_bits[i]] = (int)i;
     if (d.kind == OP_DIAG || d.kind == OP_LADDER) d.la = d.a >= 0 ? pos[d.a] : -1;
+    if (d.kind == OP_DIAG) {
+        d.lb = d.b >= 0 ? pos[d.b] : -1;
+        d.lcmask = 0;
+        d.gcmask = 0;
+        for (int b : bits_of(d.cmask)) {
+            if (pos[b] >= 0) d.lcmask |= 1ull << pos[b];
+            else d.gcmask |= 1ull << b;
+        }
+    }
     if (d.kind == OP_U1 || d.kind == OP_XPERM || d.kind == OP_U2 || d.kind == OP_SWAP) {
         d.la = pos[d.a];
         if (d.la < 0) fail(SV_EDEVICE, "internal: target bit outside tile");
@@ -664,15 +755,39 @@ inline void localise(DevOp<R> &d, const std::vector<int> &local_bits) {
 // Group the localised ops [ob, oe) of a tile (m local bits, m >= 3) into
 // stages: a mixing op joins the current stage while the union of targets
 // stays within three bits; diagonal ops always join; at most
-// STAGE_MAX_LADDERS ladders per stage.  Fills ra / rb / tslot of every op.
+// STAGE_MAX_LADDERS ladders per stage.  A run of single-control CNOTs and
+// X gates on local bits that would open a new stage after an earlier
+// stage of the tile is not run at all: it only changes the LDS layout map
+// Q of the following stages (Q <- Q o P for each op's index map P, an
+// involution), whose tables go to aux32.  If the tile ends on such a run a
+// stage without ops realises the layout (it must then write to global
+// memory: folding needs final_to_global).  Fills ra / rb / tslot of every
+// op that stays in a stage.
 template <typename R>
-inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, int m, std::vector<DevStage> &out) {
+inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, int m, std::vector<DevStage> &out,
+                         std::vector<uint32_t> &aux32, bool final_to_global) {
+    const bool can_fold = final_to_global && m <= 16;
     int start = ob;
     std::vector<int> regs;
     int nlad = 0;
     bool diag = false;
-    auto close = [&](int end) {
-        if (end <= start) return;
+    int closed = 0;  // stages of this tile so far
+    // layout map Q(j) = sum_i j_i col[i] ^ q over GF(2)
+    uint32_t col[32];
+    for (int i = 0; i < m; ++i) col[i] = 1u << i;
+    uint32_t q = 0;
+    bool ident = true;
+    auto img = [&](uint32_t v) {
+        uint32_t r = q;
+        for (int i = 0; i < m; ++i)
+            if ((v >> i) & 1) r ^= col[i];
+        return r;
+    };
+    auto foldable = [](const DevOp<R> &d) {
+        return d.kind == OP_XPERM && d.gcmask == 0 && __builtin_popcountll(d.lcmask) <= 1;
+    };
+    auto close = [&](int end, bool force) {
+        if (end <= start && !force) return;
         // fill with the highest unused local bits (keeps the low bits on the
         // lanes, so global loads of a group stay coalesced)
         for (int b = m - 1; b >= 0 && (int)regs.size() < 3; --b)
@@ -698,14 +813,48 @@ inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, int m, std:
                 const int sl = d.la >= 0 ? slot(d.la) : 3;
                 d.ra = sl < 3 ? sl : -1;
             }
+            if (d.kind == OP_DIAG) {
+                d.flags &= ~OPF_PLACEMENT;
+                const int sa = d.la >= 0 ? slot(d.la) : 3, sb = d.lb >= 0 ? slot(d.lb) : 3;
+                d.ra = sa < 3 ? sa : -1;
+                d.rb = sb < 3 ? sb : -1;
+                uint64_t regmask = 0;
+                for (int r : regs) regmask |= 1ull << r;
+                const bool ctrl_reg = (d.lcmask & regmask) != 0;
+                if (d.ra < 0 && d.rb < 0 && !ctrl_reg) {
+                    d.flags |= OPF_GRP;
+                    S.acc = 1;
+                } else if (d.b < 0 && d.cmask == 0 && d.ra >= 0) {
+                    d.flags |= OPF_REG1;
+                    S.acc = 1;
+                }
+            }
         }
         S.nlad = ls;
+        if (!ident) {
+            if (closed == 0) fail(SV_EDEVICE, "internal: layout map on the first stage of a tile");
+            S.perm = 1;
+            S.perm_tab = (int)aux32.size();
+            const uint32_t q0 = q;
+            q = 0;  // tables hold the linear part; pd[e] carries q
+            for (uint32_t v = 0; v < 128; ++v) aux32.push_back(img(v & ((1u << m) - 1)));
+            const uint32_t nh = m > 7 ? 1u << (m - 7) : 1u;
+            for (uint32_t v = 0; v < nh; ++v) aux32.push_back(img(v << 7));
+            q = q0;
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t lo = ((e & 1) ? 1u << regs[0] : 0u) | ((e & 2) ? 1u << regs[1] : 0u) |
+                                    ((e & 4) ? 1u << regs[2] : 0u);
+                S.pd[e] = (uint16_t)img(lo);
+            }
+        }
         out.push_back(S);
+        ++closed;
         start = end;
         regs.clear();
         nlad = 0;
         diag = false;
     };
+    bool pending = false;  // Q changed since the last closed stage
     for (int o = ob; o < oe; ++o) {
         const DevOp<R> &d = ops[o];
         std::vector<int> tg;
@@ -714,13 +863,34 @@ inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, int m, std:
         int add = 0;
         for (int t : tg)
             if (std::find(regs.begin(), regs.end(), t) == regs.end()) ++add;
-        if ((int)regs.size() + add > 3 || (d.kind == OP_LADDER && nlad == STAGE_MAX_LADDERS)) close(o);
+        const bool full = (int)regs.size() + add > 3 || (d.kind == OP_LADDER && nlad == STAGE_MAX_LADDERS);
+        if (can_fold && foldable(d) && (full || start == o) && (closed > 0 || o > start)) {
+            close(o, false);
+            start = o + 1;
+            // Q <- Q o P with P(j) = j ^ [control bit set] 2^t (no control: always)
+            const int t = d.la;
+            const uint32_t lc = (uint32_t)d.lcmask;
+            if (lc) {
+                const int cb = __builtin_ctz(lc);
+                col[cb] ^= col[t];
+            } else {
+                q ^= col[t];
+            }
+            ident = false;
+            for (int i = 0; i < m && ident; ++i) ident = col[i] == (1u << i);
+            ident = ident && q == 0;
+            pending = true;
+            continue;
+        }
+        if (full) close(o, false);
+        pending = false;
         for (int t : tg)
             if (std::find(regs.begin(), regs.end(), t) == regs.end()) regs.push_back(t);
         if (d.kind == OP_LADDER) ++nlad;
         if (d.kind == OP_DIAG || d.kind == OP_LADDER) diag = true;
     }
-    close(oe);
+    if (start < oe) close(oe, false);
+    else if (pending && !ident) close(oe, true);  // realise the final layout
 }
 
 struct DevTerms {

@@ -164,6 +164,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_tile(V2<R> *__restrict__ slab, uin
                                                    const DevStage *__restrict__ stages,
                                                    const DevOp<R> *__restrict__ ops,
                                                    const uint64_t *__restrict__ aux,
+                                                   const uint32_t *__restrict__ aux32,
                                                    const V2<R> *__restrict__ ltab, uint64_t ntiles, int from_zero) {
     extern __shared__ __align__(16) unsigned char smem[];
     const DevPass &P = passes[pidx];
@@ -173,6 +174,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_tile(V2<R> *__restrict__ slab, uin
     tc.lowm = (1u << P.l) - 1;
     tc.ident = false;
     tc.zero = from_zero != 0;
+    tc.paux = aux32;
     const uint32_t nhi = 1u << (P.m - P.l);
     uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem);
     tc.hi_off = hi_off;
@@ -549,7 +551,7 @@ DevPlanHost<R> build_dev_plan(const Plan &plan) {
         }
         DevPass dp = to_dev_pass(ps, b, (int)h.dops.size(), h.aux, h.aux32);
         dp.stage_begin = (int)h.dstages.size();
-        if (ps.kind == PASS_TILE) build_stages<R>(h.dops, b, (int)h.dops.size(), ps.m, h.dstages);
+        if (ps.kind == PASS_TILE) build_stages<R>(h.dops, b, (int)h.dops.size(), ps.m, h.dstages, h.aux32, true);
         dp.stage_end = (int)h.dstages.size();
         h.dpass.push_back(dp);
     }
@@ -619,7 +621,7 @@ void launch_plan(Ctx *ctx, const Plan &plan, const DevPlanHost<R> &h, const DevP
             set_lds_limit((const void *)k_tile<R>, lds);
             LaunchScope ls(ctx, "tile", 2.0 * S);
             hipLaunchKernelGGL(k_tile<R>, dim3(grid), dim3(TILE_TPB), lds, ctx->stream, slab, dim, nc, ovr_idx, ovr,
-                               d.pass, (int)i, d.stages, d.ops, d.aux, d.ltab, tiles,
+                               d.pass, (int)i, d.stages, d.ops, d.aux, d.aux32, d.ltab, tiles,
                                (from_zero && i == 0) ? 1 : 0);
         } else {
             if (from_zero && i == 0) fail(SV_EDEVICE, "internal: plan starts with a permutation");

@@ -88,7 +88,14 @@ enum {
     OPF_REAL = 1,  // 2x2 matrix with real entries (H, RY): cheaper butterfly
     OPF_PAT = 2,   // DIAG whose only factor != 1 is on the all-ones pattern
     OPF_NEG = 4,   // ... and that factor is exactly -1 (CZ)
+    // placement flags (set per stage by the stage builder):
+    OPF_GRP = 8,   // DIAG on bits outside the stage's registers: one factor
+                   // per register group, accumulated and applied once
+    OPF_REG1 = 16, // one-qubit DIAG without controls on register bit ra:
+                   // d0 goes to the group factor, the elements with the bit
+                   // set are multiplied by d1 / d0 (entry 4 of m)
 };
+constexpr int OPF_PLACEMENT = OPF_GRP | OPF_REG1;
 
 // Lower one validated gate (kind, qubits, effective angles, user matrix) to
 // its op.  mat = 8 or 32 doubles for MAT1 / MAT2.
@@ -140,13 +147,23 @@ Plan make_plan(int n, const std::vector<Op> &ops, const PlanOptions &opt);
 // applied to 8-amplitude groups held in registers, one LDS or HBM round
 // trip per stage.  Ladders get per-tile phase tables (slots 0..nlad-1).
 constexpr int STAGE_MAX_LADDERS = 4;
+// A stage: ops [op_begin, op_end) applied to 8-amplitude register groups
+// (register bits r0 < r1 < r2), then the group is stored.  With perm the
+// store goes through P(j) = A j ^ c, the composition of the single-control
+// CNOTs and X gates that follow the stage's ops (folded out of the op list):
+// P(j0 | loff_e) = tab_lo[j0 & 127] ^ tab_hi[j0 >> 7] ^ pd[e], tables at
+// perm_tab in the plan's 32-bit aux array.
 struct alignas(16) DevStage {
     int32_t r0, r1, r2;
     int32_t op_begin, op_end;
     int32_t nlad;
     int32_t has_diag;
-    int32_t pad;
+    int32_t perm;
     int32_t lad[STAGE_MAX_LADDERS];
+    int32_t perm_tab;
+    int32_t acc;      // some DIAG op uses the per-group factor
+    int32_t pad[2];
+    uint16_t pd[8];
 };
 
 // Device pass descriptor.  Per-pass tables live in an auxiliary array:
