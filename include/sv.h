@@ -146,10 +146,7 @@ typedef struct sv_queue sv_queue;
 /* Execution options for sv_apply_circuit_ex / sv_param_shift_grad_ex. */
 enum {
     SV_FLAG_UNFUSED = 1u << 0,    /* one kernel launch per gate (plain path) */
-    SV_FLAG_SEQUENTIAL = 1u << 1, /* gradient: one circuit at a time        */
-    SV_FLAG_PERGATE_BATCH = 1u << 2 /* gradient: one launch per pass over all
-                                       circuits instead of the persistent
-                                       work-queue kernel                     */
+    SV_FLAG_SEQUENTIAL = 1u << 1  /* gradient / batch: one circuit at a time */
 };
 
 /*

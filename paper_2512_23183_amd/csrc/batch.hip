@@ -72,6 +72,8 @@ __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
         tc.ident = true;
         tc.zero = false;
         tc.paux = paux;
+        tc.scale = (R)1;
+        tc.scaled = false;
         tc.base = 0;
         tc.hi_off = nullptr;
         tc.tabs = tabs;
@@ -172,6 +174,7 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
             std::vector<uint64_t> hoff;
             for (const Op &op : spec.op_sets[bc.op_set]) {
                 DevOp<R> d = to_dev<R>(op);
+                d.flags &= ~OPF_SCALED;  // no pass scale here: ops apply their full matrix
                 localise(d, loc);
                 if (op.kind == OP_LADDER) {
                     if (hoff.empty()) hoff = hi_offsets(loc, ladder_split(n_eff));
@@ -213,6 +216,7 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
             d.ovr_slot = (int)ovr.size();
             const DevOp<R> &basep = dops[d.ovr_index];
             DevOp<R> o = to_dev<R>(bc.ovr_op);
+            o.flags &= ~OPF_SCALED;
             // same gate and qubits as the base op: reuse its placement
             o.la = basep.la;
             o.lb = basep.lb;

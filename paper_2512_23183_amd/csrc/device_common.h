@@ -117,7 +117,9 @@ struct TileCtx {
     int lt;                   // table split: low table over local bits < lt
     int tstride;              // entries per table slot (2^lt + 2^(m-lt))
     bool zero;                // first global read synthesises |0...0>
-    const uint32_t *paux;     // stage store permutation tables
+    const uint32_t *paux;     // stage layout-map tables
+    R scale;                  // pass scale (OPF_SCALED factors), applied
+    bool scaled;              // by the store of the pass's last stage
 };
 
 // Low-part width of the ladder tables (local bits below it are global bits).
@@ -253,6 +255,21 @@ __device__ __forceinline__ void rg_u1(Grp<R> &g, uint32_t lc, const uint32_t (&L
                 nx.y = m0.x * x.y + m1.x * y.y;
                 ny.x = m2.x * x.x + m3.x * y.x;
                 ny.y = m2.x * x.y + m3.x * y.y;
+            } else if constexpr (K == 3) {  // OPF_HAD (unscaled)
+                nx.x = x.x + y.x;
+                nx.y = x.y + y.y;
+                ny.x = x.x - y.x;
+                ny.y = x.y - y.y;
+            } else if constexpr (K == 4) {  // OPF_ROTC, t in m0.x
+                nx.x = x.x - m0.x * y.x;
+                nx.y = x.y - m0.x * y.y;
+                ny.x = m0.x * x.x + y.x;
+                ny.y = m0.x * x.y + y.y;
+            } else if constexpr (K == 5) {  // OPF_ROTS, u in m0.x
+                nx.x = m0.x * x.x - y.x;
+                nx.y = m0.x * x.y - y.y;
+                ny.x = x.x + m0.x * y.x;
+                ny.y = x.y + m0.x * y.y;
             } else {
                 nx = cmac2(m0, x, m1, y);
                 ny = cmac2(m2, x, m3, y);
@@ -270,7 +287,9 @@ __device__ __forceinline__ void rg_u1(Grp<R> &g, uint32_t lc, const uint32_t (&L
 
 template <int K, bool CTRL, typename R>
 __device__ __forceinline__ void rg_u1_at(Grp<R> &g, uint32_t lc, const uint32_t (&L)[3], const DevOp<R> &op) {
-    const V2<R> m0 = mat_at(op, 0), m1 = mat_at(op, 1), m2 = mat_at(op, 2), m3 = mat_at(op, 3);
+    // K 4 / 5 (scaled rotations) take their one coefficient from entry 5
+    const V2<R> m0 = mat_at(op, (K == 4 || K == 5) ? 5 : 0), m1 = mat_at(op, 1), m2 = mat_at(op, 2),
+                m3 = mat_at(op, 3);
     if (op.ra == 0) rg_u1<0, K, CTRL>(g, lc, L, m0, m1, m2, m3);
     else if (op.ra == 1) rg_u1<1, K, CTRL>(g, lc, L, m0, m1, m2, m3);
     else rg_u1<2, K, CTRL>(g, lc, L, m0, m1, m2, m3);
@@ -463,6 +482,9 @@ __device__ __forceinline__ void stage_ops(Grp<R> &g, const TileCtx<R> &tc, const
         if (kind == OP_U1 || kind == OP_XPERM) {
             if ((tc.base & op.gcmask) != op.gcmask) continue;
             if (kind == OP_XPERM) rg_u1_dispatch<2>(g, L, op);
+            else if (op.flags & OPF_HAD) rg_u1_dispatch<3>(g, L, op);
+            else if (op.flags & OPF_ROTC) rg_u1_dispatch<4>(g, L, op);
+            else if (op.flags & OPF_ROTS) rg_u1_dispatch<5>(g, L, op);
             else if (op.flags & OPF_REAL) rg_u1_dispatch<1>(g, L, op);
             else rg_u1_dispatch<0>(g, L, op);
         } else if (kind == OP_U2 || kind == OP_SWAP) {
@@ -537,6 +559,15 @@ __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi,
             }
         });
         stage_ops<R>(g, tc, S, L, G, ops, ovr_index, ovr);
+        if constexpr (MODE & 2) {
+            if (tc.scaled) {
+                static_for<0, 8>([&](auto EC) {
+                    constexpr int e = decltype(EC)::value;
+                    el<e>(g).x *= tc.scale;
+                    el<e>(g).y *= tc.scale;
+                });
+            }
+        }
         static_for<0, 8>([&](auto EC) {
             constexpr int e = decltype(EC)::value;
             if constexpr (MODE & 2) gpsi[g.k0 | goff<e>(G)] = el<e>(g);
@@ -687,8 +718,24 @@ inline DevOp<R> to_dev(const Op &op) {
         d.m[2 * k + 1] = (R)op.m[k].imag();
     }
     if (op.kind == OP_U1 && op.m[0].imag() == 0.0 && op.m[1].imag() == 0.0 && op.m[2].imag() == 0.0 &&
-        op.m[3].imag() == 0.0)
+        op.m[3].imag() == 0.0) {
         d.flags |= OPF_REAL;
+        const double m0 = op.m[0].real(), m1 = op.m[1].real(), m2 = op.m[2].real(), m3 = op.m[3].real();
+        if (op.cmask == 0 && m0 != 0.0 && m0 == m1 && m0 == m2 && m3 == -m0) {
+            d.flags |= OPF_HAD;
+            d.sfac = m0;
+        } else if (op.cmask == 0 && m0 == m3 && m1 == -m2 && (m0 != 0.0 || m2 != 0.0)) {
+            if (std::fabs(m0) >= std::fabs(m2)) {
+                d.flags |= OPF_ROTC;
+                d.sfac = m0;
+                d.m[10] = (R)(m2 / m0);
+            } else {
+                d.flags |= OPF_ROTS;
+                d.sfac = m2;
+                d.m[10] = (R)(m0 / m2);
+            }
+        }
+    }
     if (op.kind == OP_DIAG && op.b < 0 && op.m[0] != cd(0.0)) {
         const cd r = op.m[1] / op.m[0];
         d.m[8] = (R)r.real();

@@ -157,7 +157,7 @@ constexpr int TILE_TPB = 512;
 // LDS layout: hi_off[2^(m-l)], ladder tables [STAGE_MAX_LADDERS][2^lt +
 // 2^(m-lt) + 1], then the tile (2^m amplitudes, only for multi-stage passes).
 template <typename R>
-__global__ __launch_bounds__(TILE_TPB) void k_tile(V2<R> *__restrict__ slab, uint64_t dim, int nc,
+__global__ __launch_bounds__(TILE_TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) void k_tile(V2<R> *__restrict__ slab, uint64_t dim, int nc,
                                                    const int *__restrict__ ovr_idx,
                                                    const DevOp<R> *__restrict__ ovr,
                                                    const DevPass *__restrict__ passes, int pidx,
@@ -191,6 +191,14 @@ __global__ __launch_bounds__(TILE_TPB) void k_tile(V2<R> *__restrict__ slab, uin
         const uint64_t c = w / ntiles, t = w - c * ntiles;
         tc.base = deposit(t, fmask);
         const int oi = ovr_idx ? ovr_idx[c] : -1;
+        // pass scale of this circuit: a shifted op of the pass brings its own factor
+        double sc = P.scale;
+        if (oi >= P.op_begin && oi < P.op_end) {
+            if (ops[oi].flags & OPF_SCALED) sc /= ops[oi].sfac;
+            if (ovr[c].flags & OPF_SCALED) sc *= ovr[c].sfac;
+        }
+        tc.scale = (R)sc;
+        tc.scaled = sc != 1.0;
         run_stages<R, TILE_TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, ltab, oi, ovr ? ovr + c : nullptr);
     }
 }
@@ -550,6 +558,9 @@ DevPlanHost<R> build_dev_plan(const Plan &plan) {
             h.dops.push_back(d);
         }
         DevPass dp = to_dev_pass(ps, b, (int)h.dops.size(), h.aux, h.aux32);
+        dp.scale = 1.0;
+        for (int i = b; i < (int)h.dops.size(); ++i)
+            if (h.dops[i].flags & OPF_SCALED) dp.scale *= h.dops[i].sfac;
         dp.stage_begin = (int)h.dstages.size();
         if (ps.kind == PASS_TILE) build_stages<R>(h.dops, b, (int)h.dops.size(), ps.m, h.dstages, h.aux32, true);
         dp.stage_end = (int)h.dstages.size();

@@ -82,6 +82,7 @@ struct alignas(16) DevOp {
     double turns;
     int32_t flags;    // OPF_* below
     int32_t tab;      // LADDER: offset of its host-built phase tables
+    double sfac;      // OPF_HAD / OPF_ROTC / OPF_ROTS: factor taken out
     R m[32];          // complex entries as (re, im)
 };
 enum {
@@ -94,7 +95,13 @@ enum {
     OPF_REG1 = 16, // one-qubit DIAG without controls on register bit ra:
                    // d0 goes to the group factor, the elements with the bit
                    // set are multiplied by d1 / d0 (entry 4 of m)
+    // uncontrolled real one-qubit ops with a factor sfac taken out, applied
+    // once per tile pass (the pass scale):
+    OPF_HAD = 32,  // s [[1, 1], [1, -1]]: sums and differences
+    OPF_ROTC = 64, // c [[1, -t], [t, 1]], t = s / c (|t| <= 1) in m[10]
+    OPF_ROTS = 128,// s [[u, -1], [1, u]], u = c / s (|u| < 1) in m[10]
 };
+constexpr int OPF_SCALED = OPF_HAD | OPF_ROTC | OPF_ROTS;
 constexpr int OPF_PLACEMENT = OPF_GRP | OPF_REG1;
 
 // Lower one validated gate (kind, qubits, effective angles, user matrix) to
@@ -178,6 +185,7 @@ struct alignas(16) DevPass {
     int32_t nfp;               // PERM: bit pairs outside the tile
     int32_t pad;
     int8_t fpa[24], fpb[24];   // PERM: those pairs
+    double scale;              // TILE: product of the deferred factors sfac
 };
 
 // ---------------------------------------------------------------------------

@@ -19,7 +19,6 @@ LIB_PATH = os.path.join(_HERE, "libsv.so")
 C64, C128 = 0, 1
 FLAG_UNFUSED = 1
 FLAG_SEQUENTIAL = 2
-FLAG_PERGATE_BATCH = 4
 
 STATUS = {0: "SV_OK", -1: "SV_EINVAL", -2: "SV_ENOMEM", -3: "SV_EDEVICE",
           -4: "SV_EBUSY", -5: "SV_ENUMERIC", -6: "SV_ECANCELED",
