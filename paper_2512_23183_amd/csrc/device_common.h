@@ -687,6 +687,28 @@ struct DevPlanDev {
     const uint32_t *aux32;
     const V2<R> *ltab;
 };
+// Tile-pass launch with TPB threads per workgroup (tile_t<TPB>.hip).
+template <typename R, int TPB>
+void launch_tile_tpb(Ctx *ctx, size_t lds, unsigned grid, V2<R> *slab, uint64_t dim, int nc, const int *ovr_idx,
+                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero);
+
+// Workgroup size of a tile pass of m local bits: two 8-amplitude groups per
+// thread per stage (measured fastest at every width: more independent
+// workgroups per CU overlap one workgroup's HBM waits with another's stages).
+inline int tile_tpb(int m) { return std::max(64, std::min(512, 1 << std::max(0, m - 4))); }
+
+template <typename R>
+inline void launch_tile(Ctx *ctx, int tpb, size_t lds, unsigned grid, V2<R> *slab, uint64_t dim, int nc,
+                        const int *ovr_idx, const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles,
+                        bool from_zero) {
+    switch (tpb) {
+    case 64: launch_tile_tpb<R, 64>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero); break;
+    case 128: launch_tile_tpb<R, 128>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero); break;
+    case 256: launch_tile_tpb<R, 256>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero); break;
+    default: launch_tile_tpb<R, 512>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero); break;
+    }
+}
+
 template <typename R> DevPlanHost<R> build_dev_plan(const Plan &plan);
 template <typename R> DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const char *slot);
 template <typename R>

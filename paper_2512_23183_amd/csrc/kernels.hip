@@ -149,60 +149,6 @@ __global__ __launch_bounds__(SWEEP_TPB) void k_scale(V2<R> *__restrict__ psi, ui
 
 constexpr int TILE_TPB = 512;
 
-// Tile passes over a slab of nc states of dim amplitudes each (one state:
-// nc = 1).  Each workgroup walks the work items w = blockIdx.x,
-// +gridDim.x, ... with w = circuit * ntiles + tile, so neighbouring
-// workgroups share a circuit.  Circuit c applies op ovr_idx[c] as ovr[c]
-// (parameter-shift copies); from_zero makes the reads synthesise |0...0>.
-// LDS layout: hi_off[2^(m-l)], ladder tables [STAGE_MAX_LADDERS][2^lt +
-// 2^(m-lt) + 1], then the tile (2^m amplitudes, only for multi-stage passes).
-template <typename R>
-__global__ __launch_bounds__(TILE_TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) void k_tile(V2<R> *__restrict__ slab, uint64_t dim, int nc,
-                                                   const int *__restrict__ ovr_idx,
-                                                   const DevOp<R> *__restrict__ ovr,
-                                                   const DevPass *__restrict__ passes, int pidx,
-                                                   const DevStage *__restrict__ stages,
-                                                   const DevOp<R> *__restrict__ ops,
-                                                   const uint64_t *__restrict__ aux,
-                                                   const uint32_t *__restrict__ aux32,
-                                                   const V2<R> *__restrict__ ltab, uint64_t ntiles, int from_zero) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const DevPass &P = passes[pidx];
-    TileCtx<R> tc;
-    tc.m = P.m;
-    tc.l = P.l;
-    tc.lowm = (1u << P.l) - 1;
-    tc.ident = false;
-    tc.zero = from_zero != 0;
-    tc.paux = aux32;
-    const uint32_t nhi = 1u << (P.m - P.l);
-    uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem);
-    tc.hi_off = hi_off;
-    tc.lt = ladder_split(P.m);
-    tc.tstride = (1 << tc.lt) + (1 << (P.m - tc.lt));
-    tc.tabs = reinterpret_cast<V2<R> *>(smem + ((8 * nhi + 15) & ~15u));
-    V2<R> *tile = tc.tabs + STAGE_MAX_LADDERS * (tc.tstride + 1);
-    for (uint32_t h = threadIdx.x; h < nhi; h += TILE_TPB) hi_off[h] = aux[P.hi_begin + h];
-    const uint64_t fmask = P.free_mask;
-    const int sb = P.stage_begin, se = P.stage_end;
-    __syncthreads();
-    const uint64_t nw = (uint64_t)nc * ntiles;
-    for (uint64_t w = blockIdx.x; w < nw; w += gridDim.x) {
-        const uint64_t c = w / ntiles, t = w - c * ntiles;
-        tc.base = deposit(t, fmask);
-        const int oi = ovr_idx ? ovr_idx[c] : -1;
-        // pass scale of this circuit: a shifted op of the pass brings its own factor
-        double sc = P.scale;
-        if (oi >= P.op_begin && oi < P.op_end) {
-            if (ops[oi].flags & OPF_SCALED) sc /= ops[oi].sfac;
-            if (ovr[c].flags & OPF_SCALED) sc *= ovr[c].sfac;
-        }
-        tc.scale = (R)sc;
-        tc.scaled = sc != 1.0;
-        run_stages<R, TILE_TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, ltab, oi, ovr ? ovr + c : nullptr);
-    }
-}
-
 // LDS position of tile element x: XOR-swizzled within rows of 256 bytes
 // (32 complex64 / 16 complex128) by two folds of the row index, so that the
 // permuted (e.g. bit-reversed) reads of a wave spread over the banks.
@@ -444,7 +390,7 @@ static DevPass to_dev_pass(const Pass &ps, int op_begin, int op_end, std::vector
 }
 
 static unsigned tile_grid(uint64_t tiles, int cu) {
-    const uint64_t cap = (uint64_t)cu * 8;
+    const uint64_t cap = (uint64_t)cu * 16;
     return (unsigned)std::max<uint64_t>(1, std::min(tiles, cap));
 }
 
@@ -629,11 +575,9 @@ void launch_plan(Ctx *ctx, const Plan &plan, const DevPlanHost<R> &h, const DevP
             const size_t tstride = (size_t)(1u << lt) + (1u << (ps.m - lt));
             size_t lds = ((8 * (size_t)nhi + 15) & ~(size_t)15) + STAGE_MAX_LADDERS * (tstride + 1) * sizeof(V2<R>);
             if (dp.stage_end - dp.stage_begin > 1) lds += sizeof(V2<R>) << ps.m;
-            set_lds_limit((const void *)k_tile<R>, lds);
             LaunchScope ls(ctx, "tile", 2.0 * S);
-            hipLaunchKernelGGL(k_tile<R>, dim3(grid), dim3(TILE_TPB), lds, ctx->stream, slab, dim, nc, ovr_idx, ovr,
-                               d.pass, (int)i, d.stages, d.ops, d.aux, d.aux32, d.ltab, tiles,
-                               (from_zero && i == 0) ? 1 : 0);
+            launch_tile<R>(ctx, tile_tpb(ps.m), lds, grid, slab, dim, nc, ovr_idx, ovr, d, (int)i, tiles,
+                           from_zero && i == 0);
         } else {
             if (from_zero && i == 0) fail(SV_EDEVICE, "internal: plan starts with a permutation");
             // k_perm moves at most 4 accesses per thread per tile

@@ -1,0 +1,79 @@
+// The tile-pass kernel, instantiated per workgroup size in tile_t*.hip.
+#pragma once
+#include "device_common.h"
+
+namespace sv {
+
+// Tile passes over a slab of nc states of dim amplitudes each (one state:
+// nc = 1).  Each workgroup walks the work items w = blockIdx.x,
+// +gridDim.x, ... with w = circuit * ntiles + tile, so neighbouring
+// workgroups share a circuit.  Circuit c applies op ovr_idx[c] as ovr[c]
+// (parameter-shift copies); from_zero makes the reads synthesise |0...0>.
+// LDS layout: hi_off[2^(m-l)], ladder tables [STAGE_MAX_LADDERS][2^lt +
+// 2^(m-lt) + 1], then the tile (2^m amplitudes, only for multi-stage passes).
+template <typename R, int TPB>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) void k_tile(V2<R> *__restrict__ slab, uint64_t dim, int nc,
+                                                   const int *__restrict__ ovr_idx,
+                                                   const DevOp<R> *__restrict__ ovr,
+                                                   const DevPass *__restrict__ passes, int pidx,
+                                                   const DevStage *__restrict__ stages,
+                                                   const DevOp<R> *__restrict__ ops,
+                                                   const uint64_t *__restrict__ aux,
+                                                   const uint32_t *__restrict__ aux32,
+                                                   const V2<R> *__restrict__ ltab, uint64_t ntiles, int from_zero) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const DevPass &P = passes[pidx];
+    TileCtx<R> tc;
+    tc.m = P.m;
+    tc.l = P.l;
+    tc.lowm = (1u << P.l) - 1;
+    tc.ident = false;
+    tc.zero = from_zero != 0;
+    tc.paux = aux32;
+    const uint32_t nhi = 1u << (P.m - P.l);
+    uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem);
+    tc.hi_off = hi_off;
+    tc.lt = ladder_split(P.m);
+    tc.tstride = (1 << tc.lt) + (1 << (P.m - tc.lt));
+    tc.tabs = reinterpret_cast<V2<R> *>(smem + ((8 * nhi + 15) & ~15u));
+    V2<R> *tile = tc.tabs + STAGE_MAX_LADDERS * (tc.tstride + 1);
+    for (uint32_t h = threadIdx.x; h < nhi; h += TPB) hi_off[h] = aux[P.hi_begin + h];
+    const uint64_t fmask = P.free_mask;
+    const int sb = P.stage_begin, se = P.stage_end;
+    __syncthreads();
+    const uint64_t nw = (uint64_t)nc * ntiles;
+    for (uint64_t w = blockIdx.x; w < nw; w += gridDim.x) {
+        const uint64_t c = w / ntiles, t = w - c * ntiles;
+        tc.base = deposit(t, fmask);
+        const int oi = ovr_idx ? ovr_idx[c] : -1;
+        // pass scale of this circuit: a shifted op of the pass brings its own factor
+        double sc = P.scale;
+        if (oi >= P.op_begin && oi < P.op_end) {
+            if (ops[oi].flags & OPF_SCALED) sc /= ops[oi].sfac;
+            if (ovr[c].flags & OPF_SCALED) sc *= ovr[c].sfac;
+        }
+        tc.scale = (R)sc;
+        tc.scaled = sc != 1.0;
+        run_stages<R, TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, ltab, oi, ovr ? ovr + c : nullptr);
+    }
+}
+
+
+template <typename R, int TPB>
+void launch_tile_tpb(Ctx *ctx, size_t lds, unsigned grid, V2<R> *slab, uint64_t dim, int nc, const int *ovr_idx,
+                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero) {
+    set_lds_limit((const void *)k_tile<R, TPB>, lds);
+    hipLaunchKernelGGL((k_tile<R, TPB>), dim3(grid), dim3(TPB), lds, ctx->stream, slab, dim, nc, ovr_idx, ovr, d.pass,
+                       pidx, d.stages, d.ops, d.aux, d.aux32, d.ltab, tiles, from_zero ? 1 : 0);
+    SV_HIP(hipGetLastError());
+}
+
+#define SV_TILE_INSTANTIATE(TPB)                                                                              \
+    template void launch_tile_tpb<float, TPB>(Ctx *, size_t, unsigned, V2<float> *, uint64_t, int, const int *, \
+                                              const DevOp<float> *, const DevPlanDev<float> &, int, uint64_t,   \
+                                              bool);                                                           \
+    template void launch_tile_tpb<double, TPB>(Ctx *, size_t, unsigned, V2<double> *, uint64_t, int,           \
+                                               const int *, const DevOp<double> *, const DevPlanDev<double> &,  \
+                                               int, uint64_t, bool);
+
+}  // namespace sv
