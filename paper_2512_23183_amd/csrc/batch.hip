@@ -35,7 +35,8 @@ __global__ void k_fill_u32(unsigned *p, unsigned v, int count) {
     if (i < count) p[i] = v;
 }
 
-// LDS: state[2^max_n], red[TPB/64], vals[max_T + 1], ladder tables.
+// LDS: state[2^max_n], red[TPB/64], vals[max_T + 1]; ladder tables are read
+// from global memory.
 template <typename R>
 __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
     const DevCirc *__restrict__ circ, int ncirc, unsigned *__restrict__ counter,
@@ -49,7 +50,6 @@ __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
     V2<R> *st = reinterpret_cast<V2<R> *>(smem);
     double *red = reinterpret_cast<double *>(smem + (sizeof(V2<R>) << max_n));
     double *vals = red + SMALL_TPB / 64;
-    V2<R> *tabs = reinterpret_cast<V2<R> *>(vals + ((max_T + 2) & ~1));
     for (;;) {
         if (threadIdx.x == 0) cur = (int)atomicAdd(counter, 1u);
         __syncthreads();
@@ -76,12 +76,12 @@ __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
         tc.scaled = false;
         tc.base = 0;
         tc.hi_off = nullptr;
-        tc.tabs = tabs;
-        tc.lt = ladder_split(n);
-        tc.tstride = (1 << tc.lt) + (1 << (n - tc.lt));
+        tc.ltabs = ltab;
+        tc.Gs = nullptr;
+        ladder_split(n, tc.lsa, tc.lsb);
         __syncthreads();
-        run_stages<R, SMALL_TPB>(st, nullptr, tc, stages, C.stage_begin, C.stage_end, ops, ltab,
-                                    C.ovr_index, ovr_ops + C.ovr_slot);
+        run_stages<R, SMALL_TPB>(st, nullptr, tc, stages, C.stage_begin, C.stage_end, ops, C.ovr_index,
+                                    ovr_ops + C.ovr_slot);
         for (int g = C.grp_begin; g < C.grp_end; ++g) {
             const uint64_t x = gx[g];
             const int hb = x ? 63 - __clzll(x) : -1;
@@ -171,20 +171,16 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
         if (set_begin[bc.op_set] < 0) {
             set_begin[bc.op_set] = (int)dops.size();
             std::vector<int> loc(all_local.begin(), all_local.begin() + n_eff);
-            std::vector<uint64_t> hoff;
             for (const Op &op : spec.op_sets[bc.op_set]) {
                 DevOp<R> d = to_dev<R>(op);
                 d.flags &= ~OPF_SCALED;  // no pass scale here: ops apply their full matrix
                 localise(d, loc);
-                if (op.kind == OP_LADDER) {
-                    if (hoff.empty()) hoff = hi_offsets(loc, ladder_split(n_eff));
-                    append_ladder_tables<R>(d, op, n_eff, hoff, ltab);
-                }
+                if (op.kind == OP_LADDER) append_ladder_tables<R>(d, op, loc, ltab);  // read from global memory
                 dops.push_back(d);
             }
             set_end[bc.op_set] = (int)dops.size();
             set_sb[bc.op_set] = (int)stages.size();
-            build_stages<R>(dops, set_begin[bc.op_set], set_end[bc.op_set], n_eff, stages, paux, false);
+            build_stages<R>(dops, set_begin[bc.op_set], set_end[bc.op_set], loc, stages, paux, false);
             set_se[bc.op_set] = (int)stages.size();
         }
         if (ham_gb[bc.ham] < 0) {
@@ -260,9 +256,7 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     upload(ctx, base, blob.host.data(), blob.host.size());
     unsigned *d_cnt = (unsigned *)(base + o_cnt);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, ctx->stream, d_cnt, 0u, 1);
-    const int lts = ladder_split(max_n);
-    const size_t lds = (sizeof(V2<R>) << max_n) + 8 * (SMALL_TPB / 64) + 8 * ((max_T + 2) & ~1) +
-                       STAGE_MAX_LADDERS * sizeof(V2<R>) * ((1u << lts) + (1u << (max_n - lts)) + 1);
+    const size_t lds = (sizeof(V2<R>) << max_n) + 8 * (SMALL_TPB / 64) + 8 * ((max_T + 2) & ~1);
     set_lds_limit((const void *)k_small_batch<R>, lds);
     const int nc = (int)circ.size();
     const int per_cu = lds <= 40 * 1024 ? 4 : lds <= 80 * 1024 ? 2 : 1;

@@ -113,17 +113,44 @@ struct TileCtx {
     bool ident;               // global index == local index
     uint64_t base;            // global bits fixed for this tile
     const uint64_t *hi_off;   // LDS: global offset of the high local bits
-    V2<R> *tabs;              // LDS: ladder phase tables
-    int lt;                   // table split: low table over local bits < lt
-    int tstride;              // entries per table slot (2^lt + 2^(m-lt))
+    const V2<R> *ltabs;       // ladder phase tables (LDS copy or global)
+    const V2<R> *Gs;          // per-tile ladder factors by op.tslot (LDS), null = 1
+    int lsa, lsb;             // ladder table split of the local bits
     bool zero;                // first global read synthesises |0...0>
     const uint32_t *paux;     // stage layout-map tables
     R scale;                  // pass scale (OPF_SCALED factors), applied
     bool scaled;              // by the store of the pass's last stage
 };
 
-// Low-part width of the ladder tables (local bits below it are global bits).
-__host__ __device__ constexpr int ladder_split(int m) { return m < 5 ? m : 5; }
+// Ladder tables split the m local bits into a low part of a bits, a middle
+// part of b bits and a high part of m - a - b bits.
+__host__ __device__ inline void ladder_split(int m, int &a, int &b) {
+    a = m < 5 ? m : 5;
+    b = (m - a + 1) / 2;
+}
+__host__ __device__ inline int ladder_entries(int m) {
+    int a, b;
+    ladder_split(m, a, b);
+    return (1 << a) + (1 << b) + (1 << (m - a - b));
+}
+
+// LDS layout of a tile pass (byte offsets, 16-byte aligned parts); the
+// host sizes the launch with the same function.
+constexpr int LTAB_LDS_CAP = 2048;  // ladder table entries kept in LDS
+struct LdsLayout {
+    uint32_t gs, tabs, tile, end;
+    bool tabs_in_lds;
+};
+__host__ __device__ inline LdsLayout tile_lds_layout(uint32_t nhi, int nlad, int ltab_count, uint32_t amp) {
+    auto al = [](uint32_t x) { return (x + 15u) & ~15u; };
+    LdsLayout L;
+    L.gs = al(8 * nhi);
+    L.tabs = L.gs + al(amp * (uint32_t)nlad);
+    L.tabs_in_lds = ltab_count <= LTAB_LDS_CAP;
+    L.tile = L.tabs + (L.tabs_in_lds ? al(amp * (uint32_t)ltab_count) : 0u);
+    L.end = L.tile;
+    return L;
+}
 
 template <typename R>
 __device__ __forceinline__ uint64_t gaddr(const TileCtx<R> &tc, uint32_t j) {
@@ -132,31 +159,6 @@ __device__ __forceinline__ uint64_t gaddr(const TileCtx<R> &tc, uint32_t j) {
 
 __device__ __forceinline__ uint32_t ins0(uint32_t x, int p) {
     return ((x >> p) << (p + 1)) | (x & ((1u << p) - 1));
-}
-
-// Ladder phase tables of a stage.  The host builds, per ladder, the
-// tile-independent tables TLc[v] = exp(2 pi i tau (v & M)) over the 2^lt
-// lowest local bits and THc[h] = exp(2 pi i tau (off(h << lt) & M)) over the
-// remaining local bits (off = global offset within the tile).  Per tile the
-// factor G = exp(2 pi i tau (base & M)) of the fixed bits is folded into TH;
-// the phase of local index j is then TL[j & (2^lt - 1)] * TH[j >> lt].
-template <typename R, int TPB>
-__device__ __forceinline__ void build_ladder_tables(const TileCtx<R> &tc, const DevStage &S,
-                                                    const DevOp<R> *ops, const V2<R> *__restrict__ ltab) {
-    V2<R> *Gs = tc.tabs + STAGE_MAX_LADDERS * tc.tstride;
-    if ((int)threadIdx.x < S.nlad) {
-        const DevOp<R> &op = ops[S.lad[threadIdx.x]];
-        Gs[threadIdx.x] = ladder_phase<R>(op.turns, tc.base & op.lmask);
-    }
-    __syncthreads();
-    const int nl = 1 << tc.lt;
-    for (int s = 0; s < S.nlad; ++s) {
-        const DevOp<R> &op = ops[S.lad[s]];
-        const V2<R> *src = ltab + op.tab;
-        const V2<R> G = Gs[s];
-        V2<R> *T = tc.tabs + s * tc.tstride;
-        for (int i = threadIdx.x; i < tc.tstride; i += TPB) T[i] = i < nl ? src[i] : cmul(G, src[i]);
-    }
 }
 
 // Global bit mask of local bit r.
@@ -442,22 +444,26 @@ __device__ __forceinline__ void rg_bit_scale(Grp<R> &g, const V2<R> r) {
     });
 }
 
-// Ladder: where bit a is set, multiply by TL[j & ltm] * TH[j >> lt].  When
-// a is register bit RA (template), exactly the elements with that bit set
-// are touched; otherwise (RA < 0) bit a is the same for the whole group.
+// Ladder: where bit a is set, multiply by exp(2 pi i turns (k & lmask)).
+// For k = base | off(j0) | off(e) (tile bits, the group's base index, its
+// register bits) the phase factors into G (per tile), the product of the
+// three tile-independent tables at j0's low / middle / high local bits, and
+// a constant K_e of the op's stage (m entries 8 + e).  When a is register
+// bit RA (template), exactly the elements with that bit set are touched;
+// otherwise (RA < 0) bit a is the same for the whole group.
 template <int RA, typename R>
-__device__ __forceinline__ void rg_ladder(Grp<R> &g, const uint32_t (&L)[3], const DevOp<R> &op,
-                                          const TileCtx<R> &tc) {
-    const V2<R> *T = tc.tabs + op.tslot * tc.tstride;
-    const V2<R> *TH = T + (1 << tc.lt);
-    const uint32_t ltm = (1u << tc.lt) - 1;
+__device__ __forceinline__ void rg_ladder(Grp<R> &g, const DevOp<R> &op, const TileCtx<R> &tc) {
     if (RA < 0 && !((g.k0 >> op.a) & 1)) return;
+    const V2<R> *T = tc.ltabs + op.tab;
+    const uint32_t j = g.j0;
+    V2<R> p = cmul(cmul(T[j & ((1u << tc.lsa) - 1)], T[(1 << tc.lsa) + ((j >> tc.lsa) & ((1u << tc.lsb) - 1))]),
+                   T[(1 << tc.lsa) + (1 << tc.lsb) + (j >> (tc.lsa + tc.lsb))]);
+    if (tc.Gs) p = cmul(p, tc.Gs[op.tslot]);
     static_for<0, 8>([&](auto EC) {
         constexpr int e = decltype(EC)::value;
         if constexpr (RA < 0 || (e & (1 << (RA < 0 ? 0 : RA)))) {
-            const uint32_t je = g.j0 | loff<e>(L);
             V2<R> &v = el<e>(g);
-            v = cmul(v, cmul(T[je & ltm], TH[je >> tc.lt]));
+            v = cmul(v, cmul(p, mat_at(op, 8 + e)));
         }
     });
 }
@@ -504,10 +510,10 @@ __device__ __forceinline__ void stage_ops(Grp<R> &g, const TileCtx<R> &tc, const
             else if (op.flags & OPF_PAT) rg_diag<true, false>(g, G, op);
             else rg_diag<false, false>(g, G, op);
         } else if (kind == OP_LADDER) {
-            if (op.ra == 0) rg_ladder<0>(g, L, op, tc);
-            else if (op.ra == 1) rg_ladder<1>(g, L, op, tc);
-            else if (op.ra == 2) rg_ladder<2>(g, L, op, tc);
-            else rg_ladder<-1>(g, L, op, tc);
+            if (op.ra == 0) rg_ladder<0>(g, op, tc);
+            else if (op.ra == 1) rg_ladder<1>(g, op, tc);
+            else if (op.ra == 2) rg_ladder<2>(g, op, tc);
+            else rg_ladder<-1>(g, op, tc);
         }
     }
     if (S.acc) {
@@ -590,14 +596,10 @@ __device__ __forceinline__ float4 pack_pair(float2 a, float2 b) { return make_fl
 template <typename R, int TPB>
 __device__ __forceinline__ void run_stages(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
                                            const DevStage *__restrict__ stages, int sb, int se,
-                                           const DevOp<R> *__restrict__ ops, const V2<R> *__restrict__ ltab,
-                                           int ovr_index = -1, const DevOp<R> *ovr = nullptr) {
+                                           const DevOp<R> *__restrict__ ops, int ovr_index = -1,
+                                           const DevOp<R> *ovr = nullptr) {
     for (int s = sb; s < se; ++s) {
         const DevStage &S = stages[s];
-        if (S.nlad) {
-            build_ladder_tables<R, TPB>(tc, S, ops, ltab);
-            __syncthreads();
-        }
         const bool first = gpsi && s == sb, last = gpsi && s == se - 1;
         if (first && last) run_stage<R, TPB, 3>(tile, gpsi, tc, S, ops, ovr_index, ovr);
         else if (first) run_stage<R, TPB, 1>(tile, gpsi, tc, S, ops, ovr_index, ovr);
@@ -607,23 +609,40 @@ __device__ __forceinline__ void run_stages(V2<R> *tile, V2<R> *__restrict__ gpsi
     }
 }
 
-// Host: the tile-independent ladder tables of op d in a tile of m local bits
-// whose local index j has in-tile global offset off(j) (FP64, rounded once).
+// Host: exp(2 pi i turns (v & lmask)) in FP64, rounded once.
 template <typename R>
-inline void append_ladder_tables(DevOp<R> &d, const Op &op, int m, const std::vector<uint64_t> &off_of_hi,
+inline V2<R> host_phase(double turns, uint64_t v) {
+    double t = turns * (double)v;
+    t -= std::floor(t);
+    V2<R> z;
+    z.x = (R)std::cos(2.0 * M_PI * t);
+    z.y = (R)std::sin(2.0 * M_PI * t);
+    return z;
+}
+
+// In-tile global offset of a pattern of local bits.
+inline uint64_t local_offset(uint32_t pattern, const std::vector<int> &local_bits) {
+    uint64_t o = 0;
+    for (size_t i = 0; i < local_bits.size(); ++i)
+        if ((pattern >> i) & 1) o |= 1ull << local_bits[i];
+    return o;
+}
+
+// Host: the tile-independent ladder tables of op d for a tile whose local
+// bit i is global bit local_bits[i]: the phase of the in-tile offset of each
+// pattern of the low a, middle b and high m - a - b local bits.
+template <typename R>
+inline void append_ladder_tables(DevOp<R> &d, const Op &op, const std::vector<int> &local_bits,
                                  std::vector<V2<R>> &ltab) {
-    const int lt = ladder_split(m);
+    const int m = (int)local_bits.size();
+    int a, b;
+    ladder_split(m, a, b);
     d.tab = (int)ltab.size();
-    auto ph = [&](uint64_t v) {
-        double t = op.turns * (double)v;
-        t -= std::floor(t);
-        V2<R> z;
-        z.x = (R)std::cos(2.0 * M_PI * t);
-        z.y = (R)std::sin(2.0 * M_PI * t);
-        return z;
-    };
-    for (uint32_t v = 0; v < (1u << lt); ++v) ltab.push_back(ph(v & op.lmask));
-    for (uint32_t h = 0; h < (1u << (m - lt)); ++h) ltab.push_back(ph(off_of_hi[h] & op.lmask));
+    for (uint32_t v = 0; v < (1u << a); ++v) ltab.push_back(host_phase<R>(op.turns, local_offset(v, local_bits) & op.lmask));
+    for (uint32_t v = 0; v < (1u << b); ++v)
+        ltab.push_back(host_phase<R>(op.turns, local_offset(v << a, local_bits) & op.lmask));
+    for (uint32_t v = 0; v < (1u << (m - a - b)); ++v)
+        ltab.push_back(host_phase<R>(op.turns, local_offset(v << (a + b), local_bits) & op.lmask));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -823,8 +842,8 @@ inline void localise(DevOp<R> &d, const std::vector<int> &local_bits) {
 
 // Group the localised ops [ob, oe) of a tile (m local bits, m >= 3) into
 // stages: a mixing op joins the current stage while the union of targets
-// stays within three bits; diagonal ops always join; at most
-// STAGE_MAX_LADDERS ladders per stage.  A run of single-control CNOTs and
+// stays within three bits; diagonal ops always join.  A run of
+// single-control CNOTs and
 // X gates on local bits that would open a new stage after an earlier
 // stage of the tile is not run at all: it only changes the LDS layout map
 // Q of the following stages (Q <- Q o P for each op's index map P, an
@@ -833,12 +852,12 @@ inline void localise(DevOp<R> &d, const std::vector<int> &local_bits) {
 // memory: folding needs final_to_global).  Fills ra / rb / tslot of every
 // op that stays in a stage.
 template <typename R>
-inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, int m, std::vector<DevStage> &out,
-                         std::vector<uint32_t> &aux32, bool final_to_global) {
+inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, const std::vector<int> &local_bits,
+                         std::vector<DevStage> &out, std::vector<uint32_t> &aux32, bool final_to_global) {
+    const int m = (int)local_bits.size();
     const bool can_fold = final_to_global && m <= 16;
     int start = ob;
     std::vector<int> regs;
-    int nlad = 0;
     bool diag = false;
     int closed = 0;  // stages of this tile so far
     // layout map Q(j) = sum_i j_i col[i] ^ q over GF(2)
@@ -870,17 +889,22 @@ inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, int m, std:
         S.op_begin = start;
         S.op_end = end;
         S.has_diag = diag ? 1 : 0;
-        int ls = 0;
         for (int o = start; o < end; ++o) {
             DevOp<R> &d = ops[o];
             auto slot = [&](int lb) { return (int)(std::find(regs.begin(), regs.end(), lb) - regs.begin()); };
             if (d.kind == OP_U1 || d.kind == OP_XPERM || d.kind == OP_U2 || d.kind == OP_SWAP) d.ra = slot(d.la);
             if (d.kind == OP_U2 || d.kind == OP_SWAP) d.rb = slot(d.lb);
             if (d.kind == OP_LADDER) {
-                d.tslot = ls;
-                S.lad[ls++] = o;
                 const int sl = d.la >= 0 ? slot(d.la) : 3;
                 d.ra = sl < 3 ? sl : -1;
+                // K_e: phase of the register bits' in-tile offset
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t lo = ((e & 1) ? 1u << regs[0] : 0u) | ((e & 2) ? 1u << regs[1] : 0u) |
+                                        ((e & 4) ? 1u << regs[2] : 0u);
+                    const V2<R> k = host_phase<R>(d.turns, local_offset(lo, local_bits) & d.lmask);
+                    d.m[2 * (8 + e)] = k.x;
+                    d.m[2 * (8 + e) + 1] = k.y;
+                }
             }
             if (d.kind == OP_DIAG) {
                 d.flags &= ~OPF_PLACEMENT;
@@ -899,7 +923,6 @@ inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, int m, std:
                 }
             }
         }
-        S.nlad = ls;
         if (!ident) {
             if (closed == 0) fail(SV_EDEVICE, "internal: layout map on the first stage of a tile");
             S.perm = 1;
@@ -920,7 +943,6 @@ inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, int m, std:
         ++closed;
         start = end;
         regs.clear();
-        nlad = 0;
         diag = false;
     };
     bool pending = false;  // Q changed since the last closed stage
@@ -932,7 +954,7 @@ inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, int m, std:
         int add = 0;
         for (int t : tg)
             if (std::find(regs.begin(), regs.end(), t) == regs.end()) ++add;
-        const bool full = (int)regs.size() + add > 3 || (d.kind == OP_LADDER && nlad == STAGE_MAX_LADDERS);
+        const bool full = (int)regs.size() + add > 3;
         if (can_fold && foldable(d) && (full || start == o) && (closed > 0 || o > start)) {
             close(o, false);
             start = o + 1;
@@ -955,7 +977,6 @@ inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, int m, std:
         pending = false;
         for (int t : tg)
             if (std::find(regs.begin(), regs.end(), t) == regs.end()) regs.push_back(t);
-        if (d.kind == OP_LADDER) ++nlad;
         if (d.kind == OP_DIAG || d.kind == OP_LADDER) diag = true;
     }
     if (start < oe) close(oe, false);

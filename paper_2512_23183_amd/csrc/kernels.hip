@@ -492,23 +492,31 @@ DevPlanHost<R> build_dev_plan(const Plan &plan) {
             continue;
         }
         const int b = (int)h.dops.size();
-        std::vector<uint64_t> hoff;
+        const int ltab_begin = (int)h.ltab.size();
+        std::vector<int> ladders;
         for (const Op &op : ps.ops) {
             DevOp<R> d = to_dev<R>(op);
             localise(d, ps.local_bits);
-            if (op.kind == OP_LADDER) {
-                if (hoff.empty()) hoff = hi_offsets(ps.local_bits, ladder_split(ps.m));
-                append_ladder_tables<R>(d, op, ps.m, hoff, h.ltab);
+            if (op.kind == OP_LADDER && ps.kind == PASS_TILE) {
+                append_ladder_tables<R>(d, op, ps.local_bits, h.ltab);
+                d.tab -= ltab_begin;  // tables are addressed from the pass's first one
+                d.tslot = (int)ladders.size();
+                ladders.push_back((int)h.dops.size());
             }
             h.gate.push_back(op.gate);
             h.dops.push_back(d);
         }
         DevPass dp = to_dev_pass(ps, b, (int)h.dops.size(), h.aux, h.aux32);
+        dp.ltab_begin = ltab_begin;
+        dp.ltab_count = (int)h.ltab.size() - ltab_begin;
+        dp.nlad = (int)ladders.size();
+        dp.lad_list = (int)h.aux32.size();
+        for (int o : ladders) h.aux32.push_back((uint32_t)o);
         dp.scale = 1.0;
         for (int i = b; i < (int)h.dops.size(); ++i)
             if (h.dops[i].flags & OPF_SCALED) dp.scale *= h.dops[i].sfac;
         dp.stage_begin = (int)h.dstages.size();
-        if (ps.kind == PASS_TILE) build_stages<R>(h.dops, b, (int)h.dops.size(), ps.m, h.dstages, h.aux32, true);
+        if (ps.kind == PASS_TILE) build_stages<R>(h.dops, b, (int)h.dops.size(), ps.local_bits, h.dstages, h.aux32, true);
         dp.stage_end = (int)h.dstages.size();
         h.dpass.push_back(dp);
     }
@@ -571,9 +579,7 @@ void launch_plan(Ctx *ctx, const Plan &plan, const DevPlanHost<R> &h, const DevP
         const unsigned grid = tile_grid(tiles * (uint64_t)nc, ctx->cu_count);
         if (ps.kind == PASS_TILE) {
             const DevPass &dp = h.dpass[i];
-            const int lt = ladder_split(ps.m);
-            const size_t tstride = (size_t)(1u << lt) + (1u << (ps.m - lt));
-            size_t lds = ((8 * (size_t)nhi + 15) & ~(size_t)15) + STAGE_MAX_LADDERS * (tstride + 1) * sizeof(V2<R>);
+            size_t lds = tile_lds_layout(nhi, dp.nlad, dp.ltab_count, sizeof(V2<R>)).end;
             if (dp.stage_end - dp.stage_begin > 1) lds += sizeof(V2<R>) << ps.m;
             LaunchScope ls(ctx, "tile", 2.0 * S);
             launch_tile<R>(ctx, tile_tpb(ps.m), lds, grid, slab, dim, nc, ovr_idx, ovr, d, (int)i, tiles,

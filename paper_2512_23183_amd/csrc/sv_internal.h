@@ -150,10 +150,6 @@ struct Plan {
 // the final layout is restored by PERM passes.
 Plan make_plan(int n, const std::vector<Op> &ops, const PlanOptions &opt);
 
-// A stage: ops whose mixing targets lie in three local bits (r0 < r1 < r2),
-// applied to 8-amplitude groups held in registers, one LDS or HBM round
-// trip per stage.  Ladders get per-tile phase tables (slots 0..nlad-1).
-constexpr int STAGE_MAX_LADDERS = 4;
 // A stage: ops [op_begin, op_end) applied to 8-amplitude register groups
 // (register bits r0 < r1 < r2), then the group is stored.  With perm the
 // store goes through P(j) = A j ^ c, the composition of the single-control
@@ -163,10 +159,8 @@ constexpr int STAGE_MAX_LADDERS = 4;
 struct alignas(16) DevStage {
     int32_t r0, r1, r2;
     int32_t op_begin, op_end;
-    int32_t nlad;
     int32_t has_diag;
     int32_t perm;
-    int32_t lad[STAGE_MAX_LADDERS];
     int32_t perm_tab;
     int32_t acc;      // some DIAG op uses the per-group factor
     int32_t pad[2];
@@ -186,6 +180,8 @@ struct alignas(16) DevPass {
     int32_t pad;
     int8_t fpa[24], fpb[24];   // PERM: those pairs
     double scale;              // TILE: product of the deferred factors sfac
+    int32_t lad_list, nlad;    // TILE: ladder ops (indices in the 32-bit aux array)
+    int32_t ltab_begin, ltab_count;  // TILE: their phase tables in the plan's table array
 };
 
 // ---------------------------------------------------------------------------

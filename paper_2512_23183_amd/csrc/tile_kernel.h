@@ -9,8 +9,10 @@ namespace sv {
 // +gridDim.x, ... with w = circuit * ntiles + tile, so neighbouring
 // workgroups share a circuit.  Circuit c applies op ovr_idx[c] as ovr[c]
 // (parameter-shift copies); from_zero makes the reads synthesise |0...0>.
-// LDS layout: hi_off[2^(m-l)], ladder tables [STAGE_MAX_LADDERS][2^lt +
-// 2^(m-lt) + 1], then the tile (2^m amplitudes, only for multi-stage passes).
+// LDS layout (16-byte aligned parts): hi_off[2^(m-l)], the per-tile ladder
+// factors Gs[nlad], the pass's ladder tables when they fit
+// (ltab_count <= LTAB_LDS_CAP; else they are read from global memory), then
+// the tile (2^m amplitudes, only for multi-stage passes).
 template <typename R, int TPB>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) void k_tile(V2<R> *__restrict__ slab, uint64_t dim, int nc,
                                                    const int *__restrict__ ovr_idx,
@@ -33,11 +35,16 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
     const uint32_t nhi = 1u << (P.m - P.l);
     uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem);
     tc.hi_off = hi_off;
-    tc.lt = ladder_split(P.m);
-    tc.tstride = (1 << tc.lt) + (1 << (P.m - tc.lt));
-    tc.tabs = reinterpret_cast<V2<R> *>(smem + ((8 * nhi + 15) & ~15u));
-    V2<R> *tile = tc.tabs + STAGE_MAX_LADDERS * (tc.tstride + 1);
+    ladder_split(P.m, tc.lsa, tc.lsb);
+    const LdsLayout lay = tile_lds_layout(nhi, P.nlad, P.ltab_count, sizeof(V2<R>));
+    V2<R> *Gs = reinterpret_cast<V2<R> *>(smem + lay.gs);
+    V2<R> *ltl = reinterpret_cast<V2<R> *>(smem + lay.tabs);
+    V2<R> *tile = reinterpret_cast<V2<R> *>(smem + lay.tile);
+    tc.Gs = Gs;
+    tc.ltabs = lay.tabs_in_lds ? ltl : ltab + P.ltab_begin;
     for (uint32_t h = threadIdx.x; h < nhi; h += TPB) hi_off[h] = aux[P.hi_begin + h];
+    if (lay.tabs_in_lds)
+        for (int i = threadIdx.x; i < P.ltab_count; i += TPB) ltl[i] = ltab[P.ltab_begin + i];
     const uint64_t fmask = P.free_mask;
     const int sb = P.stage_begin, se = P.stage_end;
     __syncthreads();
@@ -45,6 +52,14 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
     for (uint64_t w = blockIdx.x; w < nw; w += gridDim.x) {
         const uint64_t c = w / ntiles, t = w - c * ntiles;
         tc.base = deposit(t, fmask);
+        if (P.nlad) {
+            // the tile's factor of every ladder: the phase of its fixed bits
+            for (int i = threadIdx.x; i < P.nlad; i += TPB) {
+                const DevOp<R> &op = ops[aux32[P.lad_list + i]];
+                Gs[i] = ladder_phase<R>(op.turns, tc.base & op.lmask);
+            }
+            __syncthreads();
+        }
         const int oi = ovr_idx ? ovr_idx[c] : -1;
         // pass scale of this circuit: a shifted op of the pass brings its own factor
         double sc = P.scale;
@@ -54,7 +69,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
         }
         tc.scale = (R)sc;
         tc.scaled = sc != 1.0;
-        run_stages<R, TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, ltab, oi, ovr ? ovr + c : nullptr);
+        run_stages<R, TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
     }
 }
 
