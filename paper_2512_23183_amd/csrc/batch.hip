@@ -22,8 +22,22 @@ namespace sv {
 
 struct alignas(16) DevCirc {
     int32_t n, op_begin, op_end, ovr_index;  // ovr_index: absolute op index or -1
-    int32_t ovr_slot, grp_begin, grp_end, T;
+    int32_t ovr_slot, ch_begin, ch_end, T;   // term chunks [ch_begin, ch_end)
     int32_t coeff_begin, out_slot, stage_begin, stage_end;
+};
+
+// Pauli terms of the small-circuit path in chunks of <= ESUM_CHUNK terms
+// that share an X/Y support x (local = global bits) and the part (Re / Im)
+// of conj(psi[k ^ x]) psi[k] they use: mode 0 diagonal, 1 Re, 2 Im.
+struct alignas(16) SChunk {
+    uint32_t x;
+    int32_t mode, tbeg, tend;
+};
+struct alignas(16) STerm {
+    uint32_t z;
+    int32_t idx;   // value slot (term index; T = norm)
+    int32_t neg;   // i^ny sign: ny mod 4 in {1, 2}
+    int32_t diag;  // x = 0: no pair factor 2
 };
 
 constexpr int SMALL_TPB = 256;
@@ -42,9 +56,8 @@ __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
     const DevCirc *__restrict__ circ, int ncirc, unsigned *__restrict__ counter,
     const DevOp<R> *__restrict__ ops, const DevStage *__restrict__ stages, const V2<R> *__restrict__ ltab,
     const uint32_t *__restrict__ paux, const DevOp<R> *__restrict__ ovr_ops,
-    const DevTerm *__restrict__ terms, const int *__restrict__ gbeg, const int *__restrict__ gend,
-    const uint64_t *__restrict__ gx, const double *__restrict__ coeffs, double *__restrict__ energies,
-    int max_n, int max_T) {
+    const SChunk *__restrict__ chunks, const STerm *__restrict__ sterms, const double *__restrict__ coeffs,
+    double *__restrict__ energies, int max_n, int max_T) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cur;
     V2<R> *st = reinterpret_cast<V2<R> *>(smem);
@@ -82,29 +95,30 @@ __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
         __syncthreads();
         run_stages<R, SMALL_TPB>(st, nullptr, tc, stages, C.stage_begin, C.stage_end, ops, C.ovr_index,
                                     ovr_ops + C.ovr_slot);
-        for (int g = C.grp_begin; g < C.grp_end; ++g) {
-            const uint64_t x = gx[g];
-            const int hb = x ? 63 - __clzll(x) : -1;
-            const uint32_t items = x ? N / 2 : N;
-            for (int t = gbeg[g]; t < gend[g]; ++t) {
-                const uint64_t z = terms[t].z;
-                const int ny = terms[t].ny;
-                double acc = 0.0;
-                for (uint32_t it = threadIdx.x; it < items; it += SMALL_TPB) {
-                    if (x == 0) {
-                        const V2<R> a = st[it];
-                        const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
-                        acc += (__popcll(it & z) & 1) ? -p : p;
-                    } else {
-                        const uint32_t k = ((it >> hb) << (hb + 1)) | (it & ((1u << hb) - 1));
-                        const uint32_t k2 = k ^ (uint32_t)x;
-                        const V2<R> a = st[k], b = st[k2];
-                        const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
-                        acc += pair_contrib(bx * ax + by * ay, bx * ay - by * ax, k, k2, z, ny);
+        // one wave per chunk of terms; each term's value has one writer
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const uint32_t lane = threadIdx.x & 63;
+        for (int ch = C.ch_begin + wave; ch < C.ch_end; ch += SMALL_TPB / 64) {
+            const SChunk K = chunks[ch];
+            const int cnt = K.tend - K.tbeg;
+            uint32_t zl[ESUM_CHUNK];
+            double acc[ESUM_CHUNK];
+#pragma unroll
+            for (int q = 0; q < ESUM_CHUNK; ++q) {
+                zl[q] = q < cnt ? sterms[K.tbeg + q].z : 0u;
+                acc[q] = 0.0;
+            }
+            esum_dispatch<R>(st, N, K.x, K.mode, cnt, zl, acc, lane);
+#pragma unroll
+            for (int q = 0; q < ESUM_CHUNK; ++q) {
+                if (q < cnt) {
+                    const double sum = wave_sum(acc[q]);
+                    if (lane == 0) {
+                        const STerm &tm = sterms[K.tbeg + q];
+                        const double v = tm.diag ? sum : 2.0 * sum;
+                        vals[tm.idx] = tm.neg ? -v : v;
                     }
                 }
-                const double s = block_sum<SMALL_TPB>(acc, red);
-                if (threadIdx.x == 0) vals[terms[t].idx] = s;
             }
         }
         __syncthreads();
@@ -152,9 +166,8 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     std::iota(all_local.begin(), all_local.end(), 0);
     std::vector<int> ham_gb(spec.hams.size(), -1), ham_ge(spec.hams.size(), -1),
         ham_cb(spec.hams.size(), -1), ham_T(spec.hams.size(), 0);
-    std::vector<DevTerm> terms;
-    std::vector<int> gbeg, gend;
-    std::vector<uint64_t> gx;
+    std::vector<SChunk> chunks;
+    std::vector<STerm> sterms;
     std::vector<double> coeffs;
     std::vector<DevCirc> circ;
     std::vector<DevOp<R>> ovr;
@@ -185,15 +198,33 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
         }
         if (ham_gb[bc.ham] < 0) {
             DevTerms dt = build_dev_terms(spec.hams[bc.ham]);
-            const int tb = (int)terms.size();
-            ham_gb[bc.ham] = (int)gx.size();
+            ham_gb[bc.ham] = (int)chunks.size();
             for (size_t g = 0; g < dt.gx.size(); ++g) {
-                gx.push_back(dt.gx[g]);
-                gbeg.push_back(tb + dt.gbeg[g]);
-                gend.push_back(tb + dt.gend[g]);
+                const uint32_t x = (uint32_t)dt.gx[g];
+                for (int pim = 0; pim < 2; ++pim) {
+                    std::vector<int> ts;
+                    for (int t = dt.gbeg[g]; t < dt.gend[g]; ++t)
+                        if (x != 0 ? (dt.terms[t].ny & 1) == pim : pim == 0) ts.push_back(t);
+                    for (size_t i = 0; i < ts.size(); i += ESUM_CHUNK) {
+                        SChunk K;
+                        K.x = x;
+                        K.mode = x == 0 ? 0 : (pim ? 2 : 1);
+                        K.tbeg = (int)sterms.size();
+                        for (size_t k = i; k < std::min(ts.size(), i + ESUM_CHUNK); ++k) {
+                            const DevTerm &d = dt.terms[ts[k]];
+                            STerm st;
+                            st.z = (uint32_t)d.z;
+                            st.idx = d.idx;
+                            st.neg = x != 0 && (d.ny == 1 || d.ny == 2);
+                            st.diag = x == 0;
+                            sterms.push_back(st);
+                        }
+                        K.tend = (int)sterms.size();
+                        chunks.push_back(K);
+                    }
+                }
             }
-            ham_ge[bc.ham] = (int)gx.size();
-            terms.insert(terms.end(), dt.terms.begin(), dt.terms.end());
+            ham_ge[bc.ham] = (int)chunks.size();
             ham_cb[bc.ham] = (int)coeffs.size();
             coeffs.insert(coeffs.end(), dt.coeffs.begin(), dt.coeffs.end());
             ham_T[bc.ham] = dt.T;
@@ -224,8 +255,8 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
             o.flags = (o.flags & ~OPF_PLACEMENT) | (basep.flags & OPF_PLACEMENT);
             ovr.push_back(o);
         }
-        d.grp_begin = ham_gb[bc.ham];
-        d.grp_end = ham_ge[bc.ham];
+        d.ch_begin = ham_gb[bc.ham];
+        d.ch_end = ham_ge[bc.ham];
         d.T = ham_T[bc.ham];
         d.coeff_begin = ham_cb[bc.ham];
         d.out_slot = bc.out_slot >= 0 ? bc.out_slot : c;
@@ -246,10 +277,8 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     const size_t o_lt = blob.add(ltab.data(), ltab.size() * sizeof(V2<R>));
     const size_t o_pa = blob.add(paux.data(), paux.size() * 4);
     const size_t o_ovr = blob.add(ovr.data(), ovr.size() * sizeof(DevOp<R>));
-    const size_t o_t = blob.add(terms.data(), terms.size() * sizeof(DevTerm));
-    const size_t o_gb = blob.add(gbeg.data(), gbeg.size() * 4);
-    const size_t o_ge = blob.add(gend.data(), gend.size() * 4);
-    const size_t o_gx = blob.add(gx.data(), gx.size() * 8);
+    const size_t o_ch = blob.add(chunks.data(), chunks.size() * sizeof(SChunk));
+    const size_t o_st = blob.add(sterms.data(), sterms.size() * sizeof(STerm));
     const size_t o_cf = blob.add(coeffs.data(), coeffs.size() * 8);
     const size_t o_cnt = blob.add(nullptr, 16);
     char *base = (char *)scratch(ctx, "batch_small", blob.host.size());
@@ -268,8 +297,8 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
                        (const DevCirc *)(base + o_c), nc, d_cnt, (const DevOp<R> *)(base + o_ops),
                        (const DevStage *)(base + o_stg), (const V2<R> *)(base + o_lt),
                        (const uint32_t *)(base + o_pa), (const DevOp<R> *)(base + o_ovr),
-                       (const DevTerm *)(base + o_t), (const int *)(base + o_gb), (const int *)(base + o_ge),
-                       (const uint64_t *)(base + o_gx), (const double *)(base + o_cf), d_E, max_n, max_T);
+                       (const SChunk *)(base + o_ch), (const STerm *)(base + o_st), (const double *)(base + o_cf),
+                       d_E, max_n, max_T);
     SV_HIP(hipGetLastError());
 }
 

@@ -651,6 +651,85 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Per-term FP64 sums of Pauli expectations over a tile in LDS (one wave per
+// chunk of terms sharing an X/Y support).
+constexpr int ESUM_CHUNK = 8;
+
+// +1.0 or -1.0 by the parity of popcount(j & z)
+__device__ __forceinline__ double parity_sign(uint32_t j, uint32_t z) {
+    return __hiloint2double((int)((__popc(j & z) << 31) | 0x3ff00000u), 0);
+}
+
+__device__ __forceinline__ uint32_t below_of(uint32_t xl) { return (1u << (31 - __clz(xl))) - 1; }
+
+// One wave's sums over a tile in LDS for CNT terms of one group chunk.
+// MODE 0: diagonal, items = amplitudes j, value |psi_j|^2.  MODE 1/2: items
+// = pairs (j, j ^ xl) with j's top bit of xl clear, value Re/Im conj(b) a.
+// acc[q] += (-1)^popcount(j & zl[q]) value (an exact product); loads of U items are issued
+// before their arithmetic.
+template <typename R, int CNT, int MODE>
+__device__ __forceinline__ void esum(const V2<R> *__restrict__ tile, uint32_t items, uint32_t xl, uint32_t below,
+                                     const uint32_t (&zl)[ESUM_CHUNK], double (&acc)[ESUM_CHUNK], uint32_t lane) {
+    constexpr int U = 4;
+    auto item = [&](uint32_t it) { return MODE == 0 ? it : (((it & ~below) << 1) | (it & below)); };
+    auto value = [&](const V2<R> &a, const V2<R> &b) {
+        const double ax = a.x, ay = a.y;
+        if (MODE == 0) return ax * ax + ay * ay;
+        const double bx = b.x, by = b.y;
+        return MODE == 1 ? bx * ax + by * ay : bx * ay - by * ax;
+    };
+    uint32_t it = lane;
+    for (; it + 64 * (U - 1) < items; it += 64 * U) {
+        uint32_t j[U];
+        V2<R> a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            j[u] = item(it + 64 * u);
+            a[u] = tile[j[u]];
+            if (MODE != 0) b[u] = tile[j[u] ^ xl];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double v = value(a[u], MODE != 0 ? b[u] : a[u]);
+#pragma unroll
+            for (int q = 0; q < CNT; ++q) acc[q] = fma(parity_sign(j[u], zl[q]), v, acc[q]);
+        }
+    }
+    for (; it < items; it += 64) {
+        const uint32_t jj = item(it);
+        const V2<R> a = tile[jj];
+        const double v = value(a, MODE != 0 ? tile[jj ^ xl] : a);
+#pragma unroll
+        for (int q = 0; q < CNT; ++q) acc[q] = fma(parity_sign(jj, zl[q]), v, acc[q]);
+    }
+}
+
+
+// esum for a chunk of cnt (1..ESUM_CHUNK) terms over a tile of T amplitudes:
+// mode 0 diagonal, 1 / 2 pairs on X/Y support xl using Re / Im.
+template <typename R>
+__device__ __forceinline__ void esum_dispatch(const V2<R> *__restrict__ tile, uint32_t T, uint32_t xl, int mode,
+                                              int cnt, const uint32_t (&zl)[ESUM_CHUNK],
+                                              double (&acc)[ESUM_CHUNK], uint32_t lane) {
+    switch (cnt * 3 + mode) {
+#define SV_ESUM_CASE(C)                                                                            \
+    case C * 3 + 0: esum<R, C, 0>(tile, T, 0u, 0u, zl, acc, lane); break;                          \
+    case C * 3 + 1: esum<R, C, 1>(tile, T / 2, xl, below_of(xl), zl, acc, lane); break;            \
+    case C * 3 + 2: esum<R, C, 2>(tile, T / 2, xl, below_of(xl), zl, acc, lane); break;
+        SV_ESUM_CASE(1)
+        SV_ESUM_CASE(2)
+        SV_ESUM_CASE(3)
+        SV_ESUM_CASE(4)
+        SV_ESUM_CASE(5)
+        SV_ESUM_CASE(6)
+        SV_ESUM_CASE(7)
+        SV_ESUM_CASE(8)
+#undef SV_ESUM_CASE
+    default: break;
+    }
+}
+
+
 // Block-wide sum in a fixed order; result valid in thread 0.
 template <int TPB>
 __device__ __forceinline__ double block_sum(double v, double *red) {

@@ -37,60 +37,11 @@ namespace {
 
 constexpr int EXPT_TPB = 256;
 constexpr int EXPT_WAVES = EXPT_TPB / 64;
-constexpr int EXPT_CHUNK = 8;        // terms per register block
+constexpr int EXPT_CHUNK = ESUM_CHUNK;  // terms per register block
 constexpr int EXPT_SLOT_CAP = 1024;  // terms per pass (LDS accumulators)
 constexpr uint64_t EXPT_VB_MAX = 2048;
 
 }  // namespace
-
-// +1.0 or -1.0 by the parity of popcount(j & z)
-__device__ __forceinline__ double parity_sign(uint32_t j, uint32_t z) {
-    return __hiloint2double((int)((__popc(j & z) << 31) | 0x3ff00000u), 0);
-}
-
-__device__ __forceinline__ uint32_t below_of(uint32_t xl) { return (1u << (31 - __clz(xl))) - 1; }
-
-// One wave's sums over a tile in LDS for CNT terms of one group chunk.
-// MODE 0: diagonal, items = amplitudes j, value |psi_j|^2.  MODE 1/2: items
-// = pairs (j, j ^ xl) with j's top bit of xl clear, value Re/Im conj(b) a.
-// acc[q] += (-1)^popcount(j & zl[q]) value (an exact product); loads of U items are issued
-// before their arithmetic.
-template <typename R, int CNT, int MODE>
-__device__ __forceinline__ void esum(const V2<R> *__restrict__ tile, uint32_t items, uint32_t xl, uint32_t below,
-                                     const uint32_t (&zl)[EXPT_CHUNK], double (&acc)[EXPT_CHUNK], uint32_t lane) {
-    constexpr int U = 4;
-    auto item = [&](uint32_t it) { return MODE == 0 ? it : (((it & ~below) << 1) | (it & below)); };
-    auto value = [&](const V2<R> &a, const V2<R> &b) {
-        const double ax = a.x, ay = a.y;
-        if (MODE == 0) return ax * ax + ay * ay;
-        const double bx = b.x, by = b.y;
-        return MODE == 1 ? bx * ax + by * ay : bx * ay - by * ax;
-    };
-    uint32_t it = lane;
-    for (; it + 64 * (U - 1) < items; it += 64 * U) {
-        uint32_t j[U];
-        V2<R> a[U], b[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            j[u] = item(it + 64 * u);
-            a[u] = tile[j[u]];
-            if (MODE != 0) b[u] = tile[j[u] ^ xl];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double v = value(a[u], MODE != 0 ? b[u] : a[u]);
-#pragma unroll
-            for (int q = 0; q < CNT; ++q) acc[q] = fma(parity_sign(j[u], zl[q]), v, acc[q]);
-        }
-    }
-    for (; it < items; it += 64) {
-        const uint32_t jj = item(it);
-        const V2<R> a = tile[jj];
-        const double v = value(a, MODE != 0 ? tile[jj ^ xl] : a);
-#pragma unroll
-        for (int q = 0; q < CNT; ++q) acc[q] = fma(parity_sign(jj, zl[q]), v, acc[q]);
-    }
-}
 
 // Stage 1: grid = nc * vb workgroups of EXPT_TPB threads.
 template <typename R>
@@ -132,23 +83,7 @@ __global__ __launch_bounds__(EXPT_TPB) void k_expect_tile(const V2<R> *__restric
             double acc[EXPT_CHUNK];
 #pragma unroll
             for (int q = 0; q < EXPT_CHUNK; ++q) acc[q] = 0.0;
-            const int mode = G.xl == 0 ? 0 : (G.pim ? 2 : 1);
-            switch (cnt * 3 + mode) {
-#define SV_ESUM_CASE(C)                                                              \
-    case C * 3 + 0: esum<R, C, 0>(tile, T, 0u, 0u, zl, acc, lane); break;            \
-    case C * 3 + 1: esum<R, C, 1>(tile, T / 2, G.xl, below_of(G.xl), zl, acc, lane); break; \
-    case C * 3 + 2: esum<R, C, 2>(tile, T / 2, G.xl, below_of(G.xl), zl, acc, lane); break;
-                SV_ESUM_CASE(1)
-                SV_ESUM_CASE(2)
-                SV_ESUM_CASE(3)
-                SV_ESUM_CASE(4)
-                SV_ESUM_CASE(5)
-                SV_ESUM_CASE(6)
-                SV_ESUM_CASE(7)
-                SV_ESUM_CASE(8)
-#undef SV_ESUM_CASE
-            default: break;
-            }
+            esum_dispatch<R>(tile, T, G.xl, G.xl == 0 ? 0 : (G.pim ? 2 : 1), cnt, zl, acc, lane);
 #pragma unroll
             for (int q = 0; q < EXPT_CHUNK; ++q) {
                 if (q < cnt) {
