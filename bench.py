@@ -188,9 +188,13 @@ def bench_deep30(ctx, sv, inputs, n=30, depth=40):
     return rec
 
 
+SERVE_N = (8, 24)
+SERVE_DEPTH = (2, 10)
+
+
 def bench_serving(ctx, sv, inputs, count, seed=5):
     # serial baseline rate first (same request list, one at a time, plain path)
-    reqs = inputs.serving_requests(count, seed, rate_per_s=0.0, n_range=(8, 20), depth_range=(2, 6))
+    reqs = inputs.serving_requests(count, seed, rate_per_s=0.0, n_range=SERVE_N, depth_range=SERVE_DEPTH)
     t0 = time.perf_counter()
     for r in reqs[: max(4, count // 8)]:
         if r.grad:
@@ -202,10 +206,11 @@ def bench_serving(ctx, sv, inputs, count, seed=5):
             st.free()
     serial_dt = (time.perf_counter() - t0) / max(4, count // 8)
     mu = 1.0 / serial_dt
-    out = {"requests": count, "serial_req_per_s": mu, "n_range": [8, 20], "depth_range": [2, 6]}
-    for load in (0.8, 2.0):
-        lam = load * mu
-        reqs = inputs.serving_requests(count, seed, rate_per_s=lam, n_range=(8, 20), depth_range=(2, 6))
+    out = {"requests": count, "serial_req_per_s": mu, "n_range": list(SERVE_N), "depth_range": list(SERVE_DEPTH)}
+    for load in (0.8, 2.0, "burst"):
+        # burst: every request arrives at once (peak queue throughput)
+        lam = 0.0 if load == "burst" else load * mu
+        reqs = inputs.serving_requests(count, seed, rate_per_s=lam, n_range=SERVE_N, depth_range=SERVE_DEPTH)
         q = ctx.queue(64 << 30)
         tickets = []
         t_start = time.perf_counter()
@@ -233,8 +238,9 @@ def bench_serving(ctx, sv, inputs, count, seed=5):
 # Sources that decide what the headline tile kernel reads and writes; the
 # recorded counter traffic is reported only while they are unchanged.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_qft28_c64_traffic.md")
-TRAFFIC_SOURCES = ["paper_2512_23183_amd/csrc/kernels.hip", "paper_2512_23183_amd/csrc/device_common.h",
-                   "paper_2512_23183_amd/csrc/plan.cpp", "paper_2512_23183_amd/csrc/lower.cpp"]
+TRAFFIC_SOURCES = ["paper_2512_23183_amd/csrc/kernels.hip", "paper_2512_23183_amd/csrc/tile_kernel.h",
+                   "paper_2512_23183_amd/csrc/device_common.h", "paper_2512_23183_amd/csrc/plan.cpp",
+                   "paper_2512_23183_amd/csrc/lower.cpp"]
 
 
 def traffic_sources_sha():

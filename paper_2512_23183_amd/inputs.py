@@ -321,7 +321,10 @@ def serving_requests(count: int, seed: int, rate_per_s: float,
     t = 0.0
     out = []
     for rid in range(count):
-        t += rng.exponential(1.0 / rate_per_s) if rate_per_s > 0 else 0.0
+        # one Exp(1) draw per request whatever the rate, so the request list
+        # is the same at every arrival rate (rate 0: all at t = 0)
+        gap = rng.exponential(1.0)
+        t += gap / rate_per_s if rate_per_s > 0 else 0.0
         n = int(rng.integers(n_range[0], n_range[1] + 1))
         depth = int(rng.integers(depth_range[0], depth_range[1] + 1))
         nt = int(rng.integers(terms_range[0], terms_range[1] + 1))
