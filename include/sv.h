@@ -161,7 +161,10 @@ typedef struct sv_config {
     int32_t expect_bits_c128;  /* same for complex128: 6..13, 0 = default 12 */
     int32_t perm_bits_c64;     /* permutation pass tile width, complex64: 6..12, 0 = default 12 */
     int32_t perm_bits_c128;    /* same for complex128: 6..11, 0 = default 11 */
-    int32_t reserved[2];       /* must be 0 */
+    int32_t dense_fuse;        /* complex64 apply: runs of fixed gates on four qubits become
+                                  one dense 16x16 block applied with MFMA; 0 = default (on),
+                                  1 = on, -1 = off */
+    int32_t reserved;          /* must be 0 */
 } sv_config;
 
 int sv_init(sv_ctx **out, int device, const sv_config *cfg);

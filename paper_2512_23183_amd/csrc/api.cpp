@@ -70,6 +70,7 @@ void apply_ops(State *st, const std::vector<Op> &ops, uint32_t flags) {
         PlanOptions po;
         po.tile_bits = ctx->tile_bits[st->dtype];
         po.perm_bits = ctx->perm_bits[st->dtype];
+        po.dense4 = st->dtype == SV_C64 && ctx->dense4;
         run_plan(ctx, st, make_plan(st->n, ops, po));
     }
     if (ctx->profile) {
@@ -203,6 +204,7 @@ int sv_init(sv_ctx **out, int device, const sv_config *cfg) {
             pick(cfg->expect_bits_c128, 6, EXPECT_MAX[SV_C128], ctx->expect_bits[SV_C128]);
             pick(cfg->perm_bits_c64, 6, PERM_MAX[SV_C64], ctx->perm_bits[SV_C64]);
             pick(cfg->perm_bits_c128, 6, PERM_MAX[SV_C128], ctx->perm_bits[SV_C128]);
+            if (cfg->dense_fuse != 0) ctx->dense4 = cfg->dense_fuse > 0;
         }
         *out = ctx;
     });

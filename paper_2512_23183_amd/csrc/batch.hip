@@ -85,6 +85,7 @@ __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
         tc.ident = true;
         tc.zero = false;
         tc.paux = paux;
+        tc.mtab = nullptr;
         tc.scale = (R)1;
         tc.scaled = false;
         tc.base = 0;

@@ -118,6 +118,7 @@ struct TileCtx {
     int lsa, lsb;             // ladder table split of the local bits
     bool zero;                // first global read synthesises |0...0>
     const uint32_t *paux;     // stage layout-map tables
+    const float *mtab;        // MFMA stage matrices
     R scale;                  // pass scale (OPF_SCALED factors), applied
     bool scaled;              // by the store of the pass's last stage
 };
@@ -532,10 +533,106 @@ __device__ __forceinline__ void stage_ops(Grp<R> &g, const TileCtx<R> &tc, const
 // tab_hi[j >> 7] ^ q (the layout left by CNOT runs folded out of earlier
 // stages); loads and stores of a group use the same positions, so no
 // thread writes where another has yet to read.
+typedef float mfma_f32x16 __attribute__((ext_vector_type(16)));
+
+// MFMA stage (complex64 only): the stage's 16 x 16 complex matrix U on
+// register bits r0 < r1 < r2 < r3 as the real 32 x 32 matrix
+// W = [[Re U, -Im U], [Im U, Re U]] (row-major at tc.mtab + S.wtab).  A wave
+// takes 32 groups g of 16 amplitudes at a time: Y = W X with column g of X =
+// (Re x_g, Im x_g), as 16 v_mfma_f32_32x32x2f32 steps (K = 2 each).  Lane
+// l = j + 32 h (group j, half h) supplies operand A = W[j][2s + h] and B =
+// component 2s + h of group j, i.e. Re / Im of amplitudes h, h + 2, ...,
+// h + 14, so it loads those 8 amplitudes; its 16 results are rows (r / 4) 8
+// + 4 h + r % 4 of column j: Re (r < 8) and Im (r + 8) of amplitudes
+// 4 h .. 4 h + 3 and 8 + 4 h .. 11 + 4 h, which it stores.  Every load of a
+// wave feeds the MFMAs before any of its stores, and waves own disjoint
+// groups, so the stage runs in place.
+template <typename R, int TPB, int MODE>
+__device__ __forceinline__ void mfma_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
+                                           const DevStage &S) {
+    if constexpr (sizeof(R) == 4) {
+        const int r[4] = {S.r0, S.r1, S.r2, S.r3};
+        uint32_t L4[4];
+        uint64_t G4[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            L4[i] = 1u << r[i];
+            G4[i] = gbit(tc, r[i]);
+        }
+        const uint32_t lane = threadIdx.x & 63, j = lane & 31, h = lane >> 5;
+        const uint32_t wave = threadIdx.x >> 6;
+        float w[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) w[s] = tc.mtab[S.wtab + 32 * j + 2 * s + h];
+        auto loff = [&](uint32_t a) {
+            return ((a & 1) ? L4[0] : 0u) | ((a & 2) ? L4[1] : 0u) | ((a & 4) ? L4[2] : 0u) | ((a & 8) ? L4[3] : 0u);
+        };
+        auto goff = [&](uint32_t a) {
+            return ((a & 1) ? G4[0] : 0ull) | ((a & 2) ? G4[1] : 0ull) | ((a & 4) ? G4[2] : 0ull) |
+                   ((a & 8) ? G4[3] : 0ull);
+        };
+        const uint32_t ngroups = 1u << (tc.m - 4);
+        for (uint32_t g0 = wave * 32; g0 < ngroups; g0 += (TPB / 64) * 32) {
+            const uint32_t gi = g0 + j;
+            const bool live = gi < ngroups;
+            const uint32_t j0 = ins0(ins0(ins0(ins0(live ? gi : 0u, r[0]), r[1]), r[2]), r[3]);
+            const uint64_t k0 = gaddr(tc, j0);
+            float bre[8], bim[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const uint32_t a = 2 * s + h;
+                V2<R> v;
+                v.x = 0;
+                v.y = 0;
+                if (live) {
+                    if constexpr (MODE & 1) {
+                        if (tc.zero) v.x = (k0 | goff(a)) == 0 ? (R)1 : (R)0;
+                        else v = gpsi[k0 | goff(a)];
+                    } else {
+                        v = tile[j0 | loff(a)];
+                    }
+                }
+                bre[s] = v.x;
+                bim[s] = v.y;
+            }
+            mfma_f32x16 acc;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w[s], s < 8 ? bre[s] : bim[s - 8], acc, 0, 0, 0);
+            if (live) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const uint32_t a = (q / 4) * 8 + 4 * h + (q % 4);
+                    V2<R> v;
+                    v.x = acc[q];
+                    v.y = acc[q + 8];
+                    if constexpr (MODE & 2) {
+                        if (tc.scaled) {
+                            v.x *= tc.scale;
+                            v.y *= tc.scale;
+                        }
+                        gpsi[k0 | goff(a)] = v;
+                    } else {
+                        tile[j0 | loff(a)] = v;
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <typename R, int TPB, int MODE>
 __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
                                           const DevStage &S, const DevOp<R> *__restrict__ ops,
                                           int ovr_index, const DevOp<R> *ovr) {
+    if constexpr (sizeof(R) == 4) {
+        if (S.mfma) {
+            mfma_stage<R, TPB, MODE>(tile, gpsi, tc, S);
+            return;
+        }
+    }
     const uint32_t nitems = (1u << tc.m) >> 3;
     const int r0 = S.r0, r1 = S.r1, r2 = S.r2;
     const uint32_t L[3] = {1u << r0, 1u << r1, 1u << r2};
@@ -775,6 +872,7 @@ struct DevPlanHost {
     std::vector<uint64_t> aux;
     std::vector<uint32_t> aux32;
     std::vector<V2<R>> ltab;
+    std::vector<float> mtab;      // 32x32 real matrices of MFMA stages
 };
 template <typename R>
 struct DevPlanDev {
@@ -784,6 +882,7 @@ struct DevPlanDev {
     const uint64_t *aux;
     const uint32_t *aux32;
     const V2<R> *ltab;
+    const float *mtab;
 };
 // Tile-pass launch with TPB threads per workgroup (tile_t<TPB>.hip).
 template <typename R, int TPB>
@@ -1027,6 +1126,30 @@ inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, const std::
     bool pending = false;  // Q changed since the last closed stage
     for (int o = ob; o < oe; ++o) {
         const DevOp<R> &d = ops[o];
+        if (d.kind == OP_DENSE4) {
+            // a stage of its own on its four bits (layout maps are not folded
+            // in passes that hold dense ops)
+            if (!ident) fail(SV_EDEVICE, "internal: dense op after a folded permutation");
+            close(o, false);
+            DevStage S;
+            std::memset(&S, 0, sizeof S);
+            int r[4], k = 0;
+            for (int b = 0; b < m && k < 4; ++b)
+                if ((d.lcmask >> b) & 1) r[k++] = b;
+            if (k != 4) fail(SV_EDEVICE, "internal: dense op without four local bits");
+            S.r0 = r[0];
+            S.r1 = r[1];
+            S.r2 = r[2];
+            S.r3 = r[3];
+            S.op_begin = o;
+            S.op_end = o + 1;
+            S.mfma = 1;
+            S.wtab = d.tab;
+            out.push_back(S);
+            ++closed;
+            start = o + 1;
+            continue;
+        }
         std::vector<int> tg;
         if (d.kind == OP_U1 || d.kind == OP_XPERM) tg = {d.la};
         else if (d.kind == OP_U2 || d.kind == OP_SWAP) tg = {d.la, d.lb};

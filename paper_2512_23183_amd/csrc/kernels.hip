@@ -497,6 +497,20 @@ DevPlanHost<R> build_dev_plan(const Plan &plan) {
         for (const Op &op : ps.ops) {
             DevOp<R> d = to_dev<R>(op);
             localise(d, ps.local_bits);
+            if (op.kind == OP_DENSE4) {
+                // local positions of its four bits; W = [[Re U, -Im U], [Im U, Re U]]
+                d.lcmask = 0;
+                for (size_t i = 0; i < ps.local_bits.size(); ++i)
+                    if ((op.lmask >> ps.local_bits[i]) & 1) d.lcmask |= 1ull << i;
+                d.tab = (int)h.mtab.size();
+                const std::vector<cd> &U = plan.dense[op.dense];
+                for (int rr = 0; rr < 32; ++rr)
+                    for (int cc = 0; cc < 32; ++cc) {
+                        const cd u = U[16 * (rr % 16) + (cc % 16)];
+                        const double v = rr < 16 ? (cc < 16 ? u.real() : -u.imag()) : (cc < 16 ? u.imag() : u.real());
+                        h.mtab.push_back((float)v);
+                    }
+            }
             if (op.kind == OP_LADDER && ps.kind == PASS_TILE) {
                 append_ladder_tables<R>(d, op, ps.local_bits, h.ltab);
                 d.tab -= ltab_begin;  // tables are addressed from the pass's first one
@@ -531,7 +545,8 @@ DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const char *slo
     const size_t s_ops = al(h.dops.size() * sizeof(DevOp<R>) + 16), s_pass = al(h.dpass.size() * sizeof(DevPass) + 16);
     const size_t s_st = al(h.dstages.size() * sizeof(DevStage) + 16), s_aux = al(h.aux.size() * 8 + 16);
     const size_t s_aux32 = al(h.aux32.size() * 4 + 16), s_lt = al(h.ltab.size() * sizeof(V2<R>) + 16);
-    std::vector<unsigned char> host(s_ops + s_pass + s_st + s_aux + s_aux32 + s_lt, 0);
+    const size_t s_mt = al(h.mtab.size() * 4 + 16);
+    std::vector<unsigned char> host(s_ops + s_pass + s_st + s_aux + s_aux32 + s_lt + s_mt, 0);
     size_t off = 0;
     auto put = [&](const void *src, size_t bytes, size_t sz) {
         if (bytes) std::memcpy(host.data() + off, src, bytes);
@@ -545,6 +560,7 @@ DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const char *slo
     const size_t o_aux = put(h.aux.data(), h.aux.size() * 8, s_aux);
     const size_t o_aux32 = put(h.aux32.data(), h.aux32.size() * 4, s_aux32);
     const size_t o_lt = put(h.ltab.data(), h.ltab.size() * sizeof(V2<R>), s_lt);
+    const size_t o_mt = put(h.mtab.data(), h.mtab.size() * 4, s_mt);
     char *dbase = (char *)scratch(ctx, slot, host.size());
     upload(ctx, dbase, host.data(), host.size());
     DevPlanDev<R> d;
@@ -554,6 +570,7 @@ DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const char *slo
     d.aux = (const uint64_t *)(dbase + o_aux);
     d.aux32 = (const uint32_t *)(dbase + o_aux32);
     d.ltab = (const V2<R> *)(dbase + o_lt);
+    d.mtab = (const float *)(dbase + o_mt);
     return d;
 }
 template DevPlanDev<float> upload_dev_plan<float>(Ctx *, const DevPlanHost<float> &, const char *);

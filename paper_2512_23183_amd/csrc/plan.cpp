@@ -153,6 +153,155 @@ void finish_tile_pass(int n, Pass &ps, uint64_t S) {
     ps.l = run;
 }
 
+// ---------------------------------------------------------------------------
+// Dense four-bit blocks.  A run of consecutive fixed (parameter-free) ops
+// of a tile pass whose bits all lie in one set of at most four local bits
+// is multiplied out into one 16 x 16 matrix (OP_DENSE4), applied by one
+// MFMA stage (a 32 x 32 real GEMM per 32 groups of 16 amplitudes) instead
+// of several register stages.  Only passes without CNOT-like ops are fused
+// (their runs may instead be folded into LDS layout maps).
+// ---------------------------------------------------------------------------
+
+std::vector<int> mask_bits(uint64_t m) {
+    std::vector<int> r;
+    for (int b = 0; b < 64; ++b)
+        if ((m >> b) & 1) r.push_back(b);
+    return r;
+}
+
+// Register-engine VALU operations per amplitude of an op (the fusion model).
+double op_cost(const Op &o) {
+    switch (o.kind) {
+    case OP_U1: {
+        bool real = true;
+        for (int k = 0; k < 4; ++k) real &= o.m[k].imag() == 0.0;
+        return real ? 4.0 : 8.0;
+    }
+    case OP_U2: return 32.0;
+    case OP_DIAG: return 2.0;
+    default: return 1.0;
+    }
+}
+
+uint64_t op_bits(const Op &o) {
+    uint64_t b = o.cmask;
+    if (o.a >= 0) b |= bit(o.a);
+    if (o.b >= 0) b |= bit(o.b);
+    return b;
+}
+
+// Apply op to a vector over the block bits (index bit k = global bit pos[k]).
+void apply_op16(const Op &op, const int (&pos)[64], cd *v) {
+    auto has = [&](int i, uint64_t mask) {
+        for (int b : mask_bits(mask))
+            if (!((i >> pos[b]) & 1)) return false;
+        return true;
+    };
+    const int A = op.a >= 0 ? 1 << pos[op.a] : 0, B = op.b >= 0 ? 1 << pos[op.b] : 0;
+    switch (op.kind) {
+    case OP_U1:
+        for (int i = 0; i < 16; ++i)
+            if (!(i & A) && has(i, op.cmask)) {
+                const cd x = v[i], y = v[i | A];
+                v[i] = op.m[0] * x + op.m[1] * y;
+                v[i | A] = op.m[2] * x + op.m[3] * y;
+            }
+        break;
+    case OP_XPERM:
+        for (int i = 0; i < 16; ++i)
+            if (!(i & A) && has(i, op.cmask)) std::swap(v[i], v[i | A]);
+        break;
+    case OP_SWAP:
+        for (int i = 0; i < 16; ++i)
+            if ((i & A) && !(i & B) && has(i, op.cmask)) std::swap(v[i], v[i ^ A ^ B]);
+        break;
+    case OP_DIAG:
+        for (int i = 0; i < 16; ++i)
+            if (has(i, op.cmask)) {
+                const int ba = (i & A) ? 1 : 0, bb = (B && (i & B)) ? 1 : 0;
+                v[i] *= op.b >= 0 ? op.m[2 * ba + bb] : op.m[ba];
+            }
+        break;
+    case OP_U2:
+        for (int i = 0; i < 16; ++i)
+            if (!(i & A) && !(i & B) && has(i, op.cmask)) {
+                const int idx[4] = {i, i | B, i | A, i | A | B};  // 2 bit_a + bit_b
+                cd x[4], y[4];
+                for (int r = 0; r < 4; ++r) x[r] = v[idx[r]];
+                for (int r = 0; r < 4; ++r) {
+                    y[r] = 0.0;
+                    for (int c = 0; c < 4; ++c) y[r] += op.m[4 * r + c] * x[c];
+                }
+                for (int r = 0; r < 4; ++r) v[idx[r]] = y[r];
+            }
+        break;
+    default: fail(SV_EDEVICE, "internal: op kind cannot join a dense block");
+    }
+}
+
+// Least total op cost for which a block is replaced by a dense op.
+constexpr double DENSE4_MIN_COST = 24.0;
+
+void fuse_dense4(Pass &ps, Plan &plan) {
+    uint64_t local = 0;
+    for (int b : ps.local_bits) local |= bit(b);
+    for (const Op &o : ps.ops)
+        if (o.kind == OP_XPERM || o.kind == OP_SWAP) return;
+    auto fusible = [&](const Op &o) {
+        return !o.param && (o.kind == OP_U1 || o.kind == OP_U2 || o.kind == OP_DIAG) &&
+               (op_bits(o) & ~local) == 0;
+    };
+    std::vector<Op> out, blk;
+    uint64_t B = 0;
+    auto flush = [&]() {
+        double cost = 0;
+        for (const Op &o : blk) cost += op_cost(o);
+        if (blk.size() >= 2 && cost >= DENSE4_MIN_COST) {
+            // pad to four bits with the lowest local bits not in the block
+            for (int b : ps.local_bits)
+                if (__builtin_popcountll(B) < 4 && !(B & bit(b))) B |= bit(b);
+            int pos[64];
+            int k = 0;
+            for (int b : mask_bits(B)) pos[b] = k++;
+            std::vector<cd> U(256);
+            for (int c = 0; c < 16; ++c) {
+                cd v[16];
+                for (int i = 0; i < 16; ++i) v[i] = i == c ? 1.0 : 0.0;
+                for (const Op &o : blk) apply_op16(o, pos, v);
+                for (int r = 0; r < 16; ++r) U[16 * r + c] = v[r];
+            }
+            Op d;
+            d.kind = OP_DENSE4;
+            d.lmask = B;
+            d.dense = (int)plan.dense.size();
+            plan.dense.push_back(std::move(U));
+            out.push_back(d);
+        } else {
+            out.insert(out.end(), blk.begin(), blk.end());
+        }
+        blk.clear();
+        B = 0;
+    };
+    for (const Op &o : ps.ops) {
+        if (fusible(o)) {
+            const uint64_t nb = B | op_bits(o);
+            if (__builtin_popcountll(nb) <= 4) {
+                blk.push_back(o);
+                B = nb;
+                continue;
+            }
+            flush();
+            blk.push_back(o);
+            B = op_bits(o);
+            continue;
+        }
+        flush();
+        out.push_back(o);
+    }
+    flush();
+    ps.ops.swap(out);
+}
+
 }  // namespace
 
 Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
@@ -294,6 +443,7 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
             if (!(S & bit(b))) { S |= bit(b); ++nS; }
         finish_tile_pass(n, ps, S);
         if (ps.ops.empty()) fail(SV_EDEVICE, "internal: planner made no progress");
+        if (opt.dense4 && ps.m >= 4) fuse_dense4(ps, plan);
         plan.passes.push_back(std::move(ps));
         rest.swap(deferred);
         rsets.swap(dsets);

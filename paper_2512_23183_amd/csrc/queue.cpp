@@ -334,6 +334,7 @@ int sv_queue_create(sv_ctx *ctx_, size_t hbm_budget_bytes, sv_queue **out) {
             q->ctx->expect_bits[d] = ctx->expect_bits[d];
             q->ctx->perm_bits[d] = ctx->perm_bits[d];
         }
+        q->ctx->dense4 = ctx->dense4;
         if (hipStreamCreateWithFlags(&q->ctx->own_stream, hipStreamNonBlocking) != hipSuccess) {
             delete q->ctx;
             delete q;

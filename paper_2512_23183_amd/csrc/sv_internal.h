@@ -51,6 +51,9 @@ enum OpKind : int32_t {
     OP_LADDER = 3,  // if bit a set: amplitude *= exp(2 pi i turns (k & lmask))
     OP_SWAP = 4,    // exchange bits a and b, where all cmask bits set
     OP_XPERM = 5,   // CNOT-like: swap pair on bit a where all cmask bits set
+    OP_DENSE4 = 6,  // dense 16x16 matrix (Plan::dense[dense]) on the four bits
+                    // of lmask, pattern bit k = the k-th lowest of them; made
+                    // by the planner from runs of fixed gates (MFMA stages)
 };
 
 struct Op {
@@ -62,6 +65,7 @@ struct Op {
     double ang = 0.0;      // CP: its angle (kept exact for ladder merging)
     cd m[16];
     int32_t gate = -1;     // source gate index (-1 = synthesised)
+    int32_t dense = -1;    // OP_DENSE4: index of its matrix in Plan::dense
     bool param = false;    // angle depends on the parameter vector
     bool diagonal() const { return kind == OP_DIAG || kind == OP_LADDER; }
 };
@@ -138,12 +142,14 @@ struct PlanOptions {
     int low_bits = 5;      // l
     int perm_bits = 11;    // tile width of permutation passes
     bool fuse = true;      // false: one sweep op per gate
+    bool dense4 = false;   // fuse runs of fixed gates on four bits into OP_DENSE4
 };
 
 struct Plan {
     int n = 0;
     std::vector<Pass> passes;
     int n_gate_ops = 0;
+    std::vector<std::vector<cd>> dense;  // 16x16 row-major matrices of OP_DENSE4 ops
 };
 
 // Build passes from ops.  SWAP ops are absorbed into a bit relabelling and
@@ -163,7 +169,10 @@ struct alignas(16) DevStage {
     int32_t perm;
     int32_t perm_tab;
     int32_t acc;      // some DIAG op uses the per-group factor
-    int32_t pad[2];
+    int32_t mfma;     // 1: the stage is one OP_DENSE4 op on bits r0 < r1 < r2 < r3
+    int32_t r3;
+    int32_t wtab;     // MFMA stage: its 32x32 real matrix in the plan's float table
+    int32_t pad[3];
     uint16_t pd[8];
 };
 
@@ -242,6 +251,7 @@ struct Ctx {
     int tile_bits[2] = {13, 12};
     int expect_bits[2] = {13, 12};
     int perm_bits[2] = {12, 11};
+    bool dense4 = true;  // complex64 circuits: MFMA stages for dense four-qubit runs
     std::mutex mu;
     // scratch buffers reused across calls (grown on demand)
     std::map<std::string, DeviceBuffer> scratch;

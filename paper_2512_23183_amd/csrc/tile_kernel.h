@@ -22,7 +22,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
                                                    const DevOp<R> *__restrict__ ops,
                                                    const uint64_t *__restrict__ aux,
                                                    const uint32_t *__restrict__ aux32,
-                                                   const V2<R> *__restrict__ ltab, uint64_t ntiles, int from_zero) {
+                                                   const V2<R> *__restrict__ ltab,
+                                                   const float *__restrict__ mtab, uint64_t ntiles, int from_zero) {
     extern __shared__ __align__(16) unsigned char smem[];
     const DevPass &P = passes[pidx];
     TileCtx<R> tc;
@@ -32,6 +33,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
     tc.ident = false;
     tc.zero = from_zero != 0;
     tc.paux = aux32;
+    tc.mtab = mtab;
     const uint32_t nhi = 1u << (P.m - P.l);
     uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem);
     tc.hi_off = hi_off;
@@ -79,7 +81,7 @@ void launch_tile_tpb(Ctx *ctx, size_t lds, unsigned grid, V2<R> *slab, uint64_t 
                      const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero) {
     set_lds_limit((const void *)k_tile<R, TPB>, lds);
     hipLaunchKernelGGL((k_tile<R, TPB>), dim3(grid), dim3(TPB), lds, ctx->stream, slab, dim, nc, ovr_idx, ovr, d.pass,
-                       pidx, d.stages, d.ops, d.aux, d.aux32, d.ltab, tiles, from_zero ? 1 : 0);
+                       pidx, d.stages, d.ops, d.aux, d.aux32, d.ltab, d.mtab, tiles, from_zero ? 1 : 0);
     SV_HIP(hipGetLastError());
 }
 

@@ -47,7 +47,7 @@ class _Config(ctypes.Structure):
     _fields_ = [("tile_bits_c64", ctypes.c_int32), ("tile_bits_c128", ctypes.c_int32),
                 ("expect_bits_c64", ctypes.c_int32), ("expect_bits_c128", ctypes.c_int32),
                 ("perm_bits_c64", ctypes.c_int32), ("perm_bits_c128", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("dense_fuse", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Request(ctypes.Structure):
@@ -192,9 +192,9 @@ def _np_dtype(dtype: int):
 class Context:
     def __init__(self, device: int = 0, tile_bits_c64: int = 0, tile_bits_c128: int = 0,
                  expect_bits_c64: int = 0, expect_bits_c128: int = 0,
-                 perm_bits_c64: int = 0, perm_bits_c128: int = 0):
+                 perm_bits_c64: int = 0, perm_bits_c128: int = 0, dense_fuse: int = 0):
         cfg = _Config(tile_bits_c64, tile_bits_c128, expect_bits_c64, expect_bits_c128,
-                      perm_bits_c64, perm_bits_c128)
+                      perm_bits_c64, perm_bits_c128, dense_fuse)
         h = _vp()
         _check(lib().sv_init(ctypes.byref(h), device, ctypes.byref(cfg)))
         self.h = h
@@ -222,7 +222,7 @@ class Context:
         cfg = _Config()
         _check(lib().sv_autotune(self.h, dtype, n_qubits,
                                  cache_path.encode() if cache_path else None, ctypes.byref(cfg)))
-        return {k: getattr(cfg, k) for k, _ in _Config._fields_ if k != "reserved"}
+        return {k: getattr(cfg, k) for k, _ in _Config._fields_ if k not in ("reserved", "dense_fuse")}
 
     def profile(self, on: bool = True):
         _check(lib().sv_profile_enable(self.h, 1 if on else 0))

@@ -410,3 +410,20 @@ def test_autotune_picks_valid_widths_and_caches(sv, tmp_path):
             assert ok, (dtype, err)
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("n,depth", [(9, 4), (14, 3), (17, 2)])
+def test_dense_mfma_blocks_match_oracle(sv, n, depth):
+    # deep random layers (U3 on every qubit, CZ matching): complex64 runs of
+    # fixed gates on four qubits become dense 16x16 blocks on MFMA
+    circ = I.deep_random_circuit(n, depth, 40 + n)
+    psi0 = I.gaussian_state(n, 41 + n)
+    want = oracle.run_circuit(circ, None, psi0)
+    for fuse in (1, -1):
+        c = sv.Context(0, dense_fuse=fuse)
+        try:
+            got = run_gpu(c, circ, None, psi0, C64)
+        finally:
+            c.close()
+        ok, err = amp_tol_ok(got, want, C64, circ.n_gates)
+        assert ok, (fuse, err)
