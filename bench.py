@@ -134,18 +134,30 @@ def bench_qft_table(ctx, sv, inputs, oracle_mod):
     return out
 
 
-def bench_grad(ctx, sv, inputs, n, layers, dtype, ham, reps, seq_reps=1, seq_flags=None):
+def bench_grad(ctx, sv, inputs, n, layers, dtype, ham, reps, seq_reps=1, seq_flags=None, direct_ctx=None):
     c = inputs.hea_circuit(n, layers)
     params = inputs.uniform_params(c.n_params, 1 if n == 10 else 3)
     circuits = 2 * c.n_params + 1
     ctx.param_shift_grad(c, params, ham, dtype)  # warm-up
+    l0, i0 = ctx.graph_stats()
     t0 = time.perf_counter()
     for _ in range(reps):
         e, g = ctx.param_shift_grad(c, params, ham, dtype)
     dt = (time.perf_counter() - t0) / reps
+    l1, i1 = ctx.graph_stats()
     rec = {"n": n, "params": c.n_params, "circuits": circuits, "gates_per_circuit": c.n_gates,
            "batched_ms": dt * 1e3, "batched_grads_per_s": 1.0 / dt,
-           "au_per_s": circuits * c.n_gates * float(1 << n) / dt}
+           "au_per_s": circuits * c.n_gates * float(1 << n) / dt,
+           "graph_launches": l1 - l0, "graph_instantiations": i1 - i0}
+    if direct_ctx is not None:
+        # the same batch launched kernel by kernel (no graph)
+        direct_ctx.param_shift_grad(c, params, ham, dtype)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            e3, g3 = direct_ctx.param_shift_grad(c, params, ham, dtype)
+        dt3 = (time.perf_counter() - t0) / reps
+        rec["batched_direct_launch_ms"] = dt3 * 1e3
+        rec["batched_direct_launch_bitwise_equal"] = bool(e3 == e and np.array_equal(g3, g))
     for name, fl in (seq_flags or {}).items():
         t0 = time.perf_counter()
         for _ in range(seq_reps):
@@ -329,15 +341,19 @@ def main():
     extras = {}
     if not args.quick:
         extras["qft"] = bench_qft_table(ctx, sv, inputs, oracle)
+        direct = sv.Context(0, graph_batch=-1, **tuned)
         rec10, _ = bench_grad(ctx, sv, inputs, 10, 4, sv.C128, inputs.xyz_chain(10), 20, 3,
                               {"sequential": sv.FLAG_SEQUENTIAL,
-                               "sequential_unfused": sv.FLAG_SEQUENTIAL | sv.FLAG_UNFUSED})
+                               "sequential_unfused": sv.FLAG_SEQUENTIAL | sv.FLAG_UNFUSED}, direct)
         extras["grad10_c128"] = rec10
-        log(f"[bench] grad10: {rec10['batched_ms']:.2f} ms")
-        rec20, _ = bench_grad(ctx, sv, inputs, 20, 8, sv.C64, inputs.random_2local(20, 200, 3), 1, 1,
-                              {"sequential": sv.FLAG_SEQUENTIAL})
+        log(f"[bench] grad10: {rec10['batched_ms']:.3f} ms (direct launches "
+            f"{rec10['batched_direct_launch_ms']:.3f} ms)")
+        rec20, _ = bench_grad(ctx, sv, inputs, 20, 8, sv.C64, inputs.random_2local(20, 200, 3), 2, 1,
+                              {"sequential": sv.FLAG_SEQUENTIAL}, direct)
         extras["grad20_c64"] = rec20
-        log(f"[bench] grad20: {rec20['batched_ms']:.2f} ms")
+        log(f"[bench] grad20: {rec20['batched_ms']:.2f} ms (direct launches "
+            f"{rec20['batched_direct_launch_ms']:.2f} ms)")
+        direct.close()
         extras["deep30_c64"] = bench_deep30(ctx, sv, inputs)
         if args.serving > 0:
             extras["serving"] = bench_serving(ctx, sv, inputs, args.serving)

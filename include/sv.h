@@ -164,7 +164,10 @@ typedef struct sv_config {
     int32_t dense_fuse;        /* complex64 apply: runs of fixed gates on four qubits become
                                   one dense 16x16 block applied with MFMA; 0 = default (on),
                                   1 = on, -1 = off */
-    int32_t reserved;          /* must be 0 */
+    int32_t graph_batch;       /* gradients, batch energies and queue ticks: record the batch's
+                                  launches and replay them as one hipGraph launch (the
+                                  instantiated graph is reused while the batch keeps its
+                                  shape); 0 = default (on), 1 = on, -1 = off */
 } sv_config;
 
 int sv_init(sv_ctx **out, int device, const sv_config *cfg);
@@ -319,6 +322,13 @@ const char *sv_last_error(void);
  * state of the clamped size in HBM; takes about a second at 28 qubits.
  */
 int sv_autotune(sv_ctx *ctx, int dtype, int n_qubits, const char *cache_path, sv_config *chosen);
+
+/*
+ * Counters of the context's batch graphs (nullable outputs): hipGraph
+ * launches, and instantiations among them (the others reused the previous
+ * executable graph, updated in place).  For the caller's diagnostics.
+ */
+int sv_graph_stats(sv_ctx *ctx, uint64_t *launches, uint64_t *instantiations);
 
 const char *sv_version(void);
 

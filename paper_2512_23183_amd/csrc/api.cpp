@@ -205,6 +205,7 @@ int sv_init(sv_ctx **out, int device, const sv_config *cfg) {
             pick(cfg->perm_bits_c64, 6, PERM_MAX[SV_C64], ctx->perm_bits[SV_C64]);
             pick(cfg->perm_bits_c128, 6, PERM_MAX[SV_C128], ctx->perm_bits[SV_C128]);
             if (cfg->dense_fuse != 0) ctx->dense4 = cfg->dense_fuse > 0;
+            if (cfg->graph_batch != 0) ctx->graphs = cfg->graph_batch > 0;
         }
         *out = ctx;
     });
@@ -216,6 +217,7 @@ int sv_shutdown(sv_ctx *ctx) {
         use_device(ctx);
         queue_shutdown_all(ctx);
         (void)hipStreamSynchronize(ctx->stream);
+        release_graph(ctx);
         for (auto &kv : ctx->scratch)
             if (kv.second.ptr) (void)hipFree(kv.second.ptr);
         for (auto &p : ctx->pending) {
@@ -225,6 +227,14 @@ int sv_shutdown(sv_ctx *ctx) {
         for (hipEvent_t e : ctx->free_events) (void)hipEventDestroy(e);
         if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
         delete ctx;
+    });
+}
+
+int sv_graph_stats(sv_ctx *ctx, uint64_t *launches, uint64_t *instantiations) {
+    return guard([&] {
+        need(ctx != nullptr, "ctx is NULL");
+        if (launches) *launches = ctx->graph_launches;
+        if (instantiations) *instantiations = ctx->graph_instantiations;
     });
 }
 

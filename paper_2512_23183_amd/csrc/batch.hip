@@ -285,7 +285,6 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     char *base = (char *)scratch(ctx, "batch_small", blob.host.size());
     upload(ctx, base, blob.host.data(), blob.host.size());
     unsigned *d_cnt = (unsigned *)(base + o_cnt);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, ctx->stream, d_cnt, 0u, 1);
     const size_t lds = (sizeof(V2<R>) << max_n) + 8 * (SMALL_TPB / 64) + 8 * ((max_T + 2) & ~1);
     set_lds_limit((const void *)k_small_batch<R>, lds);
     const int nc = (int)circ.size();
@@ -293,14 +292,18 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     const int grid = std::max(1, std::min(nc, ctx->cu_count * per_cu));
     double bytes = 0;
     for (const DevCirc &d : circ) bytes += (double)(sizeof(V2<R>) << d.n);
-    LaunchScope ls(ctx, "small_batch", bytes);
-    hipLaunchKernelGGL(k_small_batch<R>, dim3(grid), dim3(SMALL_TPB), lds, ctx->stream,
-                       (const DevCirc *)(base + o_c), nc, d_cnt, (const DevOp<R> *)(base + o_ops),
-                       (const DevStage *)(base + o_stg), (const V2<R> *)(base + o_lt),
-                       (const uint32_t *)(base + o_pa), (const DevOp<R> *)(base + o_ovr),
-                       (const SChunk *)(base + o_ch), (const STerm *)(base + o_st), (const double *)(base + o_cf),
-                       d_E, max_n, max_T);
-    SV_HIP(hipGetLastError());
+    launch_or_record(ctx, [=] {
+        // the work counter is cleared by a kernel (graph-safe, no memset node)
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, ctx->stream, d_cnt, 0u, 1);
+        LaunchScope ls(ctx, "small_batch", bytes);
+        hipLaunchKernelGGL(k_small_batch<R>, dim3(grid), dim3(SMALL_TPB), lds, ctx->stream,
+                           (const DevCirc *)(base + o_c), nc, d_cnt, (const DevOp<R> *)(base + o_ops),
+                           (const DevStage *)(base + o_stg), (const V2<R> *)(base + o_lt),
+                           (const uint32_t *)(base + o_pa), (const DevOp<R> *)(base + o_ovr),
+                           (const SChunk *)(base + o_ch), (const STerm *)(base + o_st),
+                           (const double *)(base + o_cf), d_E, max_n, max_T);
+        SV_HIP(hipGetLastError());
+    });
 }
 
 namespace {
@@ -308,42 +311,66 @@ namespace {
 // Circuits too large for one workgroup, batched: one plan per (op set,
 // Hamiltonian); per pass one launch over all (circuit, tile) items of a
 // chunk of circuits held in a slab; then the batched expectation passes.
+// Everything is planned and uploaded first (one scratch slot per group and
+// chunk, the slab and the partial sums sized once for the largest group),
+// so the launches can be recorded and replayed as one graph.
+template <typename R>
+struct LargeGroup {
+    std::vector<int> cs;
+    Plan plan;
+    EPlanHost E;
+    DevPlanHost<R> h;
+    int chunk = 1;
+};
+
 template <typename R>
 void run_large_batched(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, double *d_E,
                        std::vector<int> &fallback) {
-    std::map<std::pair<int, int>, std::vector<int>> groups;
-    for (int c : idx) groups[{spec.circuits[c].op_set, spec.circuits[c].ham}].push_back(c);
-    for (auto &kv : groups) {
-        const std::vector<int> &cs = kv.second;
-        const int n = spec.circuits[cs[0]].n;
+    std::map<std::pair<int, int>, std::vector<int>> by_key;
+    for (int c : idx) by_key[{spec.circuits[c].op_set, spec.circuits[c].ham}].push_back(c);
+    std::vector<std::shared_ptr<LargeGroup<R>>> groups;
+    size_t slab_bytes = 0, part_bytes = 0;
+    for (auto &kv : by_key) {
+        auto G = std::make_shared<LargeGroup<R>>();
+        G->cs = kv.second;
+        const int n = spec.circuits[G->cs[0]].n;
         PlanOptions po;
         po.tile_bits = ctx->tile_bits[spec.dtype];
         po.perm_bits = ctx->perm_bits[spec.dtype];
-        const std::vector<Op> &ops = spec.op_sets[kv.first.first];
-        Plan plan = make_plan(n, ops, po);
-        EPlanHost E = make_eplan(n, expect_tile_bits(ctx, spec.dtype), build_dev_terms(spec.hams[kv.first.second]));
-        bool plan_ok = !plan.passes.empty() && plan.passes[0].kind == PASS_TILE;
-        for (const Pass &ps : plan.passes) plan_ok = plan_ok && ps.kind != PASS_SWEEP;
-        if (!E.ok || !plan_ok) {
-            fallback.insert(fallback.end(), cs.begin(), cs.end());
+        G->plan = make_plan(n, spec.op_sets[kv.first.first], po);
+        G->E = make_eplan(n, expect_tile_bits(ctx, spec.dtype), build_dev_terms(spec.hams[kv.first.second]));
+        bool plan_ok = !G->plan.passes.empty() && G->plan.passes[0].kind == PASS_TILE;
+        for (const Pass &ps : G->plan.passes) plan_ok = plan_ok && ps.kind != PASS_SWEEP;
+        if (!G->E.ok || !plan_ok) {
+            fallback.insert(fallback.end(), G->cs.begin(), G->cs.end());
             continue;
         }
-        DevPlanHost<R> h = build_dev_plan<R>(plan);
-        DevPlanDev<R> d = upload_dev_plan<R>(ctx, h, "mp_plan");
-        std::map<int, int> dop_of_gate;
-        for (size_t i = 0; i < h.gate.size(); ++i)
-            if (h.gate[i] >= 0) dop_of_gate[h.gate[i]] = (int)i;
-        EPlanDev ed = upload_eplan(ctx, E, "mp_eplan");
+        G->h = build_dev_plan<R>(G->plan);
         // chunks of circuits whose states fit the slab budget
-        const uint64_t dim = 1ull << n;
-        const size_t sbytes = sizeof(V2<R>) * dim;
+        const size_t sbytes = sizeof(V2<R>) << n;
         const size_t budget = (size_t)16 << 30, pbudget = (size_t)2 << 30;
-        const size_t pbytes = 8 * E.part_stride;
-        const int chunk = (int)std::max<size_t>(
-            1, std::min<size_t>(cs.size(), std::min(budget / sbytes, pbudget / std::max<size_t>(pbytes, 1))));
-        V2<R> *slab = (V2<R> *)scratch(ctx, "mp_slab", sbytes * chunk);
-        for (size_t c0 = 0; c0 < cs.size(); c0 += chunk) {
-            const int nc = (int)std::min<size_t>(chunk, cs.size() - c0);
+        const size_t pbytes = 8 * std::max<uint64_t>(1, G->E.part_stride);
+        G->chunk = (int)std::max<size_t>(
+            1, std::min<size_t>(G->cs.size(), std::min(budget / sbytes, pbudget / pbytes)));
+        slab_bytes = std::max(slab_bytes, sbytes * G->chunk);
+        part_bytes = std::max(part_bytes, pbytes * G->chunk);
+        groups.push_back(G);
+    }
+    if (groups.empty()) return;
+    V2<R> *slab = (V2<R> *)scratch(ctx, "mp_slab", slab_bytes);
+    double *part = (double *)scratch(ctx, "mp_partial", part_bytes);
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        std::shared_ptr<LargeGroup<R>> G = groups[gi];
+        const std::string tag = "#" + std::to_string(gi);
+        const DevPlanDev<R> d = upload_dev_plan<R>(ctx, G->h, "mp_plan" + tag);
+        const EPlanDev ed = upload_eplan(ctx, G->E, "mp_eplan" + tag);
+        std::map<int, int> dop_of_gate;
+        for (size_t i = 0; i < G->h.gate.size(); ++i)
+            if (G->h.gate[i] >= 0) dop_of_gate[G->h.gate[i]] = (int)i;
+        const std::vector<int> &cs = G->cs;
+        const uint64_t dim = 1ull << G->plan.n;
+        for (size_t c0 = 0; c0 < cs.size(); c0 += G->chunk) {
+            const int nc = (int)std::min<size_t>(G->chunk, cs.size() - c0);
             std::vector<int> oidx(nc, -1), oslot(nc);
             std::vector<DevOp<R>> ovr(nc);
             for (int c = 0; c < nc; ++c) {
@@ -353,7 +380,7 @@ void run_large_batched(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &
                 if (bc.ovr_index < 0) continue;
                 auto it = dop_of_gate.find(bc.ovr_index);
                 if (it == dop_of_gate.end()) fail(SV_EDEVICE, "internal: shifted gate not found in the plan");
-                const DevOp<R> &bp = h.dops[it->second];
+                const DevOp<R> &bp = G->h.dops[it->second];
                 DevOp<R> o = to_dev<R>(bc.ovr_op);
                 // same gate and qubits: keep the base op's placement in the plan
                 o.kind = bp.kind;
@@ -377,11 +404,13 @@ void run_large_batched(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &
             const size_t o_oi = ob.add(oidx.data(), nc * 4);
             const size_t o_ov = ob.add(ovr.data(), nc * sizeof(DevOp<R>));
             const size_t o_os = ob.add(oslot.data(), nc * 4);
-            char *obase = (char *)scratch(ctx, "mp_ovr", ob.host.size());
+            char *obase = (char *)scratch(ctx, "mp_ovr" + tag + "." + std::to_string(c0), ob.host.size());
             upload(ctx, obase, ob.host.data(), ob.host.size());
-            launch_plan<R>(ctx, plan, h, d, slab, dim, nc, (const int *)(obase + o_oi),
-                           (const DevOp<R> *)(obase + o_ov), true);
-            launch_expect<R>(ctx, E, ed, slab, dim, nc, (const int *)(obase + o_os), d_E, nullptr);
+            launch_or_record(ctx, [=] {
+                launch_plan<R>(ctx, G->plan, G->h, d, slab, dim, nc, (const int *)(obase + o_oi),
+                               (const DevOp<R> *)(obase + o_ov), true);
+                launch_expect<R>(ctx, G->E, ed, slab, dim, nc, part, (const int *)(obase + o_os), d_E, nullptr);
+            });
         }
     }
 }
@@ -428,7 +457,7 @@ void run_large_sequential(Ctx *ctx, const BatchSpec &spec, const std::vector<int
 
 }  // namespace
 
-void run_batch_dev(Ctx *ctx, const BatchSpec &spec, uint32_t flags, double *d_E) {
+void run_batch_dev(Ctx *ctx, const BatchSpec &spec, uint32_t flags, double *d_E, double *d_grad) {
     const int nc = (int)spec.circuits.size();
     std::vector<int> small, large;
     const int smax = small_batch_max_qubits(spec.dtype);
@@ -439,16 +468,38 @@ void run_batch_dev(Ctx *ctx, const BatchSpec &spec, uint32_t flags, double *d_E)
         if (!sequential && bc.n <= smax && vals <= SMALL_VALS_MAX) small.push_back(c);
         else large.push_back(c);
     }
-    if (spec.dtype == SV_C64) launch_small<float>(ctx, spec, small, d_E);
-    else launch_small<double>(ctx, spec, small, d_E);
+    const bool comb = d_grad && spec.comb_begin.size() > 1;
     if (sequential) {
+        if (spec.dtype == SV_C64) launch_small<float>(ctx, spec, small, d_E);
+        else launch_small<double>(ctx, spec, small, d_E);
         run_large_sequential(ctx, spec, large, flags, d_E);
-    } else {
-        std::vector<int> fallback;
+        if (comb) combine_dev(ctx, d_E, spec.comb_begin, spec.comb_circ, spec.comb_w, d_grad);
+        return;
+    }
+    // batched: uploads are enqueued now, launches are recorded and then run
+    // as one graph (or directly when graphs are off or launches are timed)
+    std::vector<std::function<void()>> work;
+    const bool graph = ctx->graphs && !ctx->profile;
+    if (graph) {
+        ctx->record = &work;
+        ctx->record_slots.clear();
+    }
+    std::vector<int> fallback;
+    try {
+        if (spec.dtype == SV_C64) launch_small<float>(ctx, spec, small, d_E);
+        else launch_small<double>(ctx, spec, small, d_E);
         if (spec.dtype == SV_C64) run_large_batched<float>(ctx, spec, large, d_E, fallback);
         else run_large_batched<double>(ctx, spec, large, d_E, fallback);
-        run_large_sequential(ctx, spec, fallback, flags, d_E);
+        if (comb && fallback.empty()) combine_dev(ctx, d_E, spec.comb_begin, spec.comb_circ, spec.comb_w, d_grad);
+    } catch (...) {
+        ctx->record = nullptr;
+        throw;
     }
+    ctx->record = nullptr;
+    if (graph) launch_recorded(ctx, work);
+    // circuits the batched plan cannot take run one at a time afterwards
+    run_large_sequential(ctx, spec, fallback, flags, d_E);
+    if (comb && !fallback.empty()) combine_dev(ctx, d_E, spec.comb_begin, spec.comb_circ, spec.comb_w, d_grad);
 }
 
 void combine_dev(Ctx *ctx, const double *d_E, const std::vector<int> &beg, const std::vector<int> &circ,
@@ -461,10 +512,12 @@ void combine_dev(Ctx *ctx, const double *d_E, const std::vector<int> &beg, const
     const size_t o_w = blob.add(w.data(), w.size() * 8);
     char *base = (char *)scratch(ctx, "comb", blob.host.size());
     upload(ctx, base, blob.host.data(), blob.host.size());
-    hipLaunchKernelGGL(k_combine, dim3((np + 255) / 256), dim3(256), 0, ctx->stream, d_E,
-                       (const int *)(base + o_b), (const int *)(base + o_c), (const double *)(base + o_w), np,
-                       d_grad);
-    SV_HIP(hipGetLastError());
+    launch_or_record(ctx, [=] {
+        hipLaunchKernelGGL(k_combine, dim3((np + 255) / 256), dim3(256), 0, ctx->stream, d_E,
+                           (const int *)(base + o_b), (const int *)(base + o_c), (const double *)(base + o_w), np,
+                           d_grad);
+        SV_HIP(hipGetLastError());
+    });
 }
 
 void run_batch(Ctx *ctx, const BatchSpec &spec, uint32_t flags, std::vector<double> &E,
@@ -472,12 +525,9 @@ void run_batch(Ctx *ctx, const BatchSpec &spec, uint32_t flags, std::vector<doub
     const int nc = (int)spec.circuits.size();
     const int np = spec.comb_begin.empty() ? 0 : (int)spec.comb_begin.size() - 1;
     double *d_E = (double *)scratch(ctx, "batch_E", (size_t)(std::max(nc, 1) + np) * 8);
-    run_batch_dev(ctx, spec, flags, d_E);
+    run_batch_dev(ctx, spec, flags, d_E, np > 0 ? d_E + nc : nullptr);
     grad.assign(np, 0.0);
-    if (np > 0) {
-        combine_dev(ctx, d_E, spec.comb_begin, spec.comb_circ, spec.comb_w, d_E + nc);
-        SV_HIP(hipMemcpyAsync(grad.data(), d_E + nc, (size_t)np * 8, hipMemcpyDeviceToHost, ctx->stream));
-    }
+    if (np > 0) SV_HIP(hipMemcpyAsync(grad.data(), d_E + nc, (size_t)np * 8, hipMemcpyDeviceToHost, ctx->stream));
     E.assign(nc, 0.0);
     if (nc) SV_HIP(hipMemcpyAsync(E.data(), d_E, (size_t)nc * 8, hipMemcpyDeviceToHost, ctx->stream));
     SV_HIP(hipStreamSynchronize(ctx->stream));

@@ -469,9 +469,6 @@ __device__ __forceinline__ void rg_ladder(Grp<R> &g, const DevOp<R> &op, const T
     });
 }
 
-// MODE bit 0: read the group from global memory (else from the LDS tile);
-// MODE bit 1: write it to global memory (else to the LDS tile).  Each
-// thread handles groups threadIdx.x, +TPB, ... one at a time.
 // Apply the ops [op_begin, op_end) of stage S to one register group.
 template <typename R>
 __device__ __forceinline__ void stage_ops(Grp<R> &g, const TileCtx<R> &tc, const DevStage &S,
@@ -623,6 +620,10 @@ __device__ __forceinline__ void mfma_stage(V2<R> *tile, V2<R> *__restrict__ gpsi
     }
 }
 
+// One 3-bit stage over the tile.  MODE bit 0: read the groups from global
+// memory (else from the LDS tile); MODE bit 1: write them to global memory
+// (else to the LDS tile).  Each thread handles groups threadIdx.x, +TPB, ...
+// one at a time (holding two at once spills registers).
 template <typename R, int TPB, int MODE>
 __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
                                           const DevStage &S, const DevOp<R> *__restrict__ ops,
@@ -907,7 +908,7 @@ inline void launch_tile(Ctx *ctx, int tpb, size_t lds, unsigned grid, V2<R> *sla
 }
 
 template <typename R> DevPlanHost<R> build_dev_plan(const Plan &plan);
-template <typename R> DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const char *slot);
+template <typename R> DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const std::string &slot);
 template <typename R>
 void launch_plan(Ctx *ctx, const Plan &plan, const DevPlanHost<R> &h, const DevPlanDev<R> &d, V2<R> *slab,
                  uint64_t dim, int nc, const int *ovr_idx, const DevOp<R> *ovr, bool from_zero);
@@ -1288,10 +1289,13 @@ struct EPlanDev {
 };
 
 EPlanHost make_eplan(int n, int m_max, const DevTerms &dt);
-EPlanDev upload_eplan(Ctx *ctx, const EPlanHost &E, const char *slot);
+EPlanDev upload_eplan(Ctx *ctx, const EPlanHost &E, const std::string &slot);
 int expect_tile_bits(const Ctx *ctx, int dtype);
+// FP64 partial-sum buffer for nc states of plan E (scratch slot `slot`).
+double *expect_partials(Ctx *ctx, const EPlanHost &E, int nc, const std::string &slot);
+// Launches only (no allocation or upload): part comes from expect_partials.
 template <typename R>
 void launch_expect(Ctx *ctx, const EPlanHost &E, const EPlanDev &d, const V2<R> *slab, uint64_t dim, int nc,
-                   const int *d_out_slot, double *d_E, double *d_vals);
+                   double *part, const int *d_out_slot, double *d_E, double *d_vals);
 
 }  // namespace sv

@@ -375,7 +375,7 @@ EPlanHost make_eplan(int n, int m_max, const DevTerms &dt) {
     return E;
 }
 
-EPlanDev upload_eplan(Ctx *ctx, const EPlanHost &E, const char *slot) {
+EPlanDev upload_eplan(Ctx *ctx, const EPlanHost &E, const std::string &slot) {
     std::vector<unsigned char> host;
     auto put = [&](const void *p, size_t bytes) {
         const size_t off = (host.size() + 255) & ~(size_t)255;
@@ -405,11 +405,14 @@ size_t eplan_lds_bytes(const EPass &p, size_t amp_bytes) {
     return (amp_bytes << p.m) + 8 * ((size_t)1 << (p.m - p.l)) + 8 * (size_t)p.nslots;
 }
 
+double *expect_partials(Ctx *ctx, const EPlanHost &E, int nc, const std::string &slot) {
+    return (double *)scratch(ctx, slot, 8 * std::max<uint64_t>(1, E.part_stride) * std::max(nc, 1));
+}
+
 template <typename R>
 void launch_expect(Ctx *ctx, const EPlanHost &E, const EPlanDev &d, const V2<R> *slab, uint64_t dim, int nc,
-                   const int *d_out_slot, double *d_E, double *d_vals) {
+                   double *part, const int *d_out_slot, double *d_E, double *d_vals) {
     if (!E.ok) fail(SV_EINVAL, E.why);
-    double *part = (double *)scratch(ctx, "exp_partial", 8 * std::max<uint64_t>(1, E.part_stride) * nc);
     for (size_t e = 0; e < E.passes.size(); ++e) {
         const EPass &p = E.passes[e];
         const uint64_t blocks = (uint64_t)p.vb * nc;
@@ -441,9 +444,9 @@ void launch_expect(Ctx *ctx, const EPlanHost &E, const EPlanDev &d, const V2<R> 
     SV_HIP(hipGetLastError());
 }
 template void launch_expect<float>(Ctx *, const EPlanHost &, const EPlanDev &, const V2<float> *, uint64_t, int,
-                                   const int *, double *, double *);
+                                   double *, const int *, double *, double *);
 template void launch_expect<double>(Ctx *, const EPlanHost &, const EPlanDev &, const V2<double> *, uint64_t, int,
-                                    const int *, double *, double *);
+                                    double *, const int *, double *, double *);
 
 int expect_tile_bits(const Ctx *ctx, int dtype) {
     return ctx->expect_bits[dtype];
@@ -455,8 +458,10 @@ void expectation_dev(Ctx *ctx, const void *psi, int n, int dtype, const DevTerms
                      double *d_vals) {
     EPlanHost E = make_eplan(n, expect_tile_bits(ctx, dtype), dt);
     EPlanDev d = upload_eplan(ctx, E, "exp_meta");
-    if (dtype == SV_C64) launch_expect<float>(ctx, E, d, (const V2<float> *)psi, 1ull << n, 1, nullptr, d_energy, d_vals);
-    else launch_expect<double>(ctx, E, d, (const V2<double> *)psi, 1ull << n, 1, nullptr, d_energy, d_vals);
+    double *part = expect_partials(ctx, E, 1, "exp_partial");
+    if (dtype == SV_C64)
+        launch_expect<float>(ctx, E, d, (const V2<float> *)psi, 1ull << n, 1, part, nullptr, d_energy, d_vals);
+    else launch_expect<double>(ctx, E, d, (const V2<double> *)psi, 1ull << n, 1, part, nullptr, d_energy, d_vals);
 }
 
 void device_expectation(Ctx *ctx, const void *psi, int n, int dtype, const TermGroups &tg, double *energy,

@@ -254,6 +254,13 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uin
 
 void *scratch(Ctx *ctx, const std::string &name, size_t bytes) {
     DeviceBuffer &b = ctx->scratch[name];
+    if (ctx->record) {
+        // a recorded launch holds this pointer until the graph runs: a slot
+        // may be handed out once per recording
+        for (const std::string &s : ctx->record_slots)
+            if (s == name) fail(SV_EDEVICE, "internal: scratch slot " + name + " reused while recording");
+        ctx->record_slots.push_back(name);
+    }
     if (b.bytes < bytes) {
         if (b.ptr) {
             SV_HIP(hipStreamSynchronize(ctx->stream));
@@ -273,6 +280,61 @@ void *scratch(Ctx *ctx, const std::string &name, size_t bytes) {
 
 void upload(Ctx *ctx, void *dst, const void *src, size_t bytes) {
     if (bytes) SV_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+}
+
+void launch_or_record(Ctx *ctx, std::function<void()> f) {
+    if (ctx->record) ctx->record->push_back(std::move(f));
+    else f();
+}
+
+void release_graph(Ctx *ctx) {
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    ctx->graph_exec = nullptr;
+}
+
+// The uploads of a batch have been enqueued while it was recorded; the
+// launches are captured from ctx->stream into a graph and run as one
+// launch.  The instantiated graph is kept and updated in place while the
+// next batch has the same shape (same kernels and grid; pointers and
+// arguments may change), which skips the instantiation.
+void launch_recorded(Ctx *ctx, std::vector<std::function<void()>> &work) {
+    if (work.empty()) return;
+    hipGraph_t g = nullptr;
+    SV_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+    try {
+        for (auto &f : work) f();
+    } catch (...) {
+        (void)hipStreamEndCapture(ctx->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        throw;
+    }
+    SV_HIP(hipStreamEndCapture(ctx->stream, &g));
+    bool updated = false;
+    if (ctx->graph_exec) {
+        // the previous replay must be over before its node arguments change
+        SV_HIP(hipStreamSynchronize(ctx->stream));
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        updated = hipGraphExecUpdate(ctx->graph_exec, g, &bad, &res) == hipSuccess &&
+                  res == hipGraphExecUpdateSuccess;
+        if (!updated) {
+            (void)hipGetLastError();
+            release_graph(ctx);
+        }
+    }
+    if (!updated) {
+        const hipError_t e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            ctx->graph_exec = nullptr;
+            (void)hipGraphDestroy(g);
+            fail(SV_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        ++ctx->graph_instantiations;
+    }
+    (void)hipGraphDestroy(g);
+    SV_HIP(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    ++ctx->graph_launches;
 }
 
 LaunchScope::LaunchScope(Ctx *c, const char *nm, double b) : ctx(c), name(nm), bytes(b) {
@@ -540,7 +602,7 @@ template DevPlanHost<float> build_dev_plan<float>(const Plan &);
 template DevPlanHost<double> build_dev_plan<double>(const Plan &);
 
 template <typename R>
-DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const char *slot) {
+DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const std::string &slot) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t s_ops = al(h.dops.size() * sizeof(DevOp<R>) + 16), s_pass = al(h.dpass.size() * sizeof(DevPass) + 16);
     const size_t s_st = al(h.dstages.size() * sizeof(DevStage) + 16), s_aux = al(h.aux.size() * 8 + 16);
@@ -573,8 +635,8 @@ DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const char *slo
     d.mtab = (const float *)(dbase + o_mt);
     return d;
 }
-template DevPlanDev<float> upload_dev_plan<float>(Ctx *, const DevPlanHost<float> &, const char *);
-template DevPlanDev<double> upload_dev_plan<double>(Ctx *, const DevPlanHost<double> &, const char *);
+template DevPlanDev<float> upload_dev_plan<float>(Ctx *, const DevPlanHost<float> &, const std::string &);
+template DevPlanDev<double> upload_dev_plan<double>(Ctx *, const DevPlanHost<double> &, const std::string &);
 
 // Launch every pass of a plan over a slab of nc states (dim amplitudes
 // each).  Sweep passes (the plain path) only exist for nc == 1.  With

@@ -271,6 +271,7 @@ void queue_destroy_impl(QueueImpl *q) {
     q->cv_done.notify_all();
     (void)hipSetDevice(q->ctx->device);
     (void)hipStreamSynchronize(q->ctx->stream);
+    release_graph(q->ctx);
     if (q->d_pool) (void)hipFree(q->d_pool);
     for (auto &kv : q->ctx->scratch)
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
@@ -335,6 +336,7 @@ int sv_queue_create(sv_ctx *ctx_, size_t hbm_budget_bytes, sv_queue **out) {
             q->ctx->perm_bits[d] = ctx->perm_bits[d];
         }
         q->ctx->dense4 = ctx->dense4;
+        q->ctx->graphs = ctx->graphs;
         if (hipStreamCreateWithFlags(&q->ctx->own_stream, hipStreamNonBlocking) != hipSuccess) {
             delete q->ctx;
             delete q;

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <complex>
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -255,6 +256,14 @@ struct Ctx {
     std::mutex mu;
     // scratch buffers reused across calls (grown on demand)
     std::map<std::string, DeviceBuffer> scratch;
+    // batched executor: the launches of one batch call are recorded and
+    // replayed as one hipGraph launch (graph_exec is reused through
+    // hipGraphExecUpdate while the launch sequence keeps its shape)
+    bool graphs = true;
+    std::vector<std::function<void()>> *record = nullptr;  // non-null while recording
+    std::vector<std::string> record_slots;                  // scratch slots touched while recording
+    hipGraphExec_t graph_exec = nullptr;
+    uint64_t graph_launches = 0, graph_instantiations = 0;
     // profiling
     bool profile = false;
     std::map<std::string, ProfileEntry> prof;
@@ -274,6 +283,12 @@ struct State {
 };
 
 void *scratch(Ctx *ctx, const std::string &name, size_t bytes);
+// Kernel launches of the batched executor go through here: run now, or
+// appended to ctx->record (no allocation or upload may happen inside f).
+void launch_or_record(Ctx *ctx, std::function<void()> f);
+// Launch the recorded work as one hipGraph on ctx->stream.
+void launch_recorded(Ctx *ctx, std::vector<std::function<void()>> &work);
+void release_graph(Ctx *ctx);
 
 // Profiling hooks around a launch.
 struct LaunchScope {
@@ -331,9 +346,9 @@ struct BatchSpec {
 // Energies of all circuits (and the combined gradient when requested).
 void run_batch(Ctx *ctx, const BatchSpec &spec, uint32_t flags,
                std::vector<double> &energies, std::vector<double> &grad);
-// Device-resident variant: energies go to d_E[out_slot]; nothing is
-// synchronised.
-void run_batch_dev(Ctx *ctx, const BatchSpec &spec, uint32_t flags, double *d_E);
+// Device-resident variant: energies go to d_E[out_slot] and, when d_grad is
+// non-null, the combined gradient to d_grad; nothing is synchronised.
+void run_batch_dev(Ctx *ctx, const BatchSpec &spec, uint32_t flags, double *d_E, double *d_grad = nullptr);
 // grad[i] = sum_j w[j] * E[circ[j]] on the device (fixed order).
 void combine_dev(Ctx *ctx, const double *d_E, const std::vector<int> &beg,
                  const std::vector<int> &circ, const std::vector<double> &w,

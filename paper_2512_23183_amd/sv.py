@@ -47,7 +47,7 @@ class _Config(ctypes.Structure):
     _fields_ = [("tile_bits_c64", ctypes.c_int32), ("tile_bits_c128", ctypes.c_int32),
                 ("expect_bits_c64", ctypes.c_int32), ("expect_bits_c128", ctypes.c_int32),
                 ("perm_bits_c64", ctypes.c_int32), ("perm_bits_c128", ctypes.c_int32),
-                ("dense_fuse", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("dense_fuse", ctypes.c_int32), ("graph_batch", ctypes.c_int32)]
 
 
 class _Request(ctypes.Structure):
@@ -123,6 +123,7 @@ def lib():
             "sv_profile_get": [_vp, ctypes.c_char_p, _dp, ctypes.POINTER(ctypes.c_uint64), _dp],
             "sv_profile_reset": [_vp],
             "sv_autotune": [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(_Config)],
+            "sv_graph_stats": [_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -192,9 +193,10 @@ def _np_dtype(dtype: int):
 class Context:
     def __init__(self, device: int = 0, tile_bits_c64: int = 0, tile_bits_c128: int = 0,
                  expect_bits_c64: int = 0, expect_bits_c128: int = 0,
-                 perm_bits_c64: int = 0, perm_bits_c128: int = 0, dense_fuse: int = 0):
+                 perm_bits_c64: int = 0, perm_bits_c128: int = 0, dense_fuse: int = 0,
+                 graph_batch: int = 0):
         cfg = _Config(tile_bits_c64, tile_bits_c128, expect_bits_c64, expect_bits_c128,
-                      perm_bits_c64, perm_bits_c128, dense_fuse)
+                      perm_bits_c64, perm_bits_c128, dense_fuse, graph_batch)
         h = _vp()
         _check(lib().sv_init(ctypes.byref(h), device, ctypes.byref(cfg)))
         self.h = h
@@ -222,7 +224,13 @@ class Context:
         cfg = _Config()
         _check(lib().sv_autotune(self.h, dtype, n_qubits,
                                  cache_path.encode() if cache_path else None, ctypes.byref(cfg)))
-        return {k: getattr(cfg, k) for k, _ in _Config._fields_ if k not in ("reserved", "dense_fuse")}
+        return {k: getattr(cfg, k) for k, _ in _Config._fields_ if k not in ("graph_batch", "dense_fuse")}
+
+    def graph_stats(self) -> Tuple[int, int]:
+        """(hipGraph launches, instantiations) of this context's batches."""
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().sv_graph_stats(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def profile(self, on: bool = True):
         _check(lib().sv_profile_enable(self.h, 1 if on else 0))
