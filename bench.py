@@ -200,6 +200,42 @@ def bench_deep30(ctx, sv, inputs, n=30, depth=40):
     return rec
 
 
+def bench_sweeps(ctx, sv, inputs):
+    """GB/s of single-gate sweeps (the plain path: one launch per gate) on an
+    8 GiB state, per gate and target position: algorithmic bytes (the
+    amplitudes the gate reads and writes) over the kernel's own time."""
+    out = {}
+    I = inputs
+    for n, dtype, dname in ((30, sv.C64, "c64"), (29, sv.C128, "c128")):
+        st = ctx.alloc(n, dtype)
+        cases = []
+        for q in (0, n // 2, n - 5, n - 2, n - 1):
+            cases.append((f"u3_q{q}", I.U3, [q], [0.3, 0.7, 1.1], "sweep_u1"))
+        cases += [("cnot_q0_q%d" % (n - 1), I.CNOT, [0, n - 1], [], "sweep_xperm"),
+                  ("cz_q0_q%d" % (n // 2), I.CZ, [0, n // 2], [], "sweep_phase"),
+                  ("swap_q1_q%d" % (n - 3), I.SWAP, [1, n - 3], [], "sweep_swap")]
+        rec = {}
+        for name, kind, qs, ang, kname in cases:
+            b = I.CircuitBuilder(n)
+            b.add(kind, qs, angles=ang)
+            c = b.build()
+            st.apply(c, None, sv.FLAG_UNFUSED)  # warm-up
+            ctx.synchronize()
+            ctx.profile_reset()
+            ctx.profile(True)
+            for _ in range(5):
+                st.apply(c, None, sv.FLAG_UNFUSED)
+            ctx.synchronize()
+            ms, cnt, by = ctx.profile_get(kname)
+            ctx.profile(False)
+            rec[name] = {"kernel": kname, "ms": ms / cnt, "gbs": by / (ms / 1e3) / 1e9,
+                         "frac_of_8tbs": by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+        st.free()
+        out[f"n{n}_{dname}"] = rec
+        log("[bench] sweeps n=%d %s: %s" % (n, dname, ", ".join(f"{k} {v['gbs']:.0f}" for k, v in rec.items())))
+    return out
+
+
 SERVE_N = (8, 24)
 SERVE_DEPTH = (2, 10)
 
@@ -354,6 +390,7 @@ def main():
         log(f"[bench] grad20: {rec20['batched_ms']:.2f} ms (direct launches "
             f"{rec20['batched_direct_launch_ms']:.2f} ms)")
         direct.close()
+        extras["sweeps"] = bench_sweeps(ctx, sv, inputs)
         extras["deep30_c64"] = bench_deep30(ctx, sv, inputs)
         if args.serving > 0:
             extras["serving"] = bench_serving(ctx, sv, inputs, args.serving)

@@ -28,100 +28,183 @@ namespace sv {
 
 constexpr int SWEEP_TPB = 256;
 
-template <typename R>
-__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_u1(V2<R> *__restrict__ psi, uint64_t items,
-                                                        Ins in, int a, DevOp<R> op) {
-    const V2<R> m0 = mat_at(op, 0), m1 = mat_at(op, 1), m2 = mat_at(op, 2), m3 = mat_at(op, 3);
-    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
-    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
-        const uint64_t k0 = expand(r, in), k1 = k0 | (1ull << a);
-        const V2<R> x = psi[k0], y = psi[k1];
-        psi[k0] = cmac2(m0, x, m1, y);
-        psi[k1] = cmac2(m2, x, m3, y);
-    }
-}
+enum SweepKind { SW_U1, SW_XPERM, SW_U2, SW_SWAP, SW_PHASE, SW_DIAG, SW_LADDER };
+// How a thread reaches its amplitudes:
+//  SWM_ONE   one amplitude per index (8 B complex64, 16 B complex128);
+//  SWM_VEC2  complex64 with index bit 0 free: the thread takes reduced
+//            indices 2t and 2t+1, whose amplitudes sit next to each other,
+//            so every access is 16 bytes (two lanes' worth per load);
+//  SWM_PAIR  complex64 one-qubit gate on bit 0: the pair (k, k+1) is one
+//            16-byte access.
+enum SweepMode { SWM_ONE, SWM_VEC2, SWM_PAIR };
 
 template <typename R>
-__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_xperm(V2<R> *__restrict__ psi, uint64_t items,
-                                                           Ins in, int a) {
-    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
-    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
-        const uint64_t k0 = expand(r, in), k1 = k0 | (1ull << a);
-        const V2<R> x = psi[k0], y = psi[k1];
-        psi[k0] = y;
-        psi[k1] = x;
-    }
+struct SweepArgs {
+    DevOp<R> op;  // matrix entries (U1, U2, DIAG)
+    V2<R> f;      // PHASE factor
+    uint64_t flip, lmask;
+    double turns;
+    int a, b;
+};
+
+constexpr int sweep_nidx(int kind) {
+    return kind == SW_U2 ? 4 : (kind == SW_U1 || kind == SW_XPERM || kind == SW_SWAP) ? 2 : 1;
 }
 
-template <typename R>
-__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_u2(V2<R> *__restrict__ psi, uint64_t items,
-                                                        Ins in, int a, int b, DevOp<R> op) {
-    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
-    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
-        const uint64_t k = expand(r, in);
-        const uint64_t idx[4] = {k, k | (1ull << b), k | (1ull << a), k | (1ull << a) | (1ull << b)};
-        V2<R> v[4], w[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = psi[idx[i]];
+// Loads and stores of one amplitude (V2<R>) or of two adjacent complex64
+// amplitudes; NT marks streaming accesses (data touched once per sweep).
+template <bool NT, typename R>
+__device__ __forceinline__ V2<R> sw_ld1(const V2<R> *p) {
+    typedef R vec __attribute__((ext_vector_type(2)));
+    const vec v = NT ? __builtin_nontemporal_load(reinterpret_cast<const vec *>(p)) : *reinterpret_cast<const vec *>(p);
+    V2<R> r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+template <bool NT, typename R>
+__device__ __forceinline__ void sw_st1(V2<R> *p, V2<R> x) {
+    typedef R vec __attribute__((ext_vector_type(2)));
+    const vec v = {x.x, x.y};
+    if (NT) __builtin_nontemporal_store(v, reinterpret_cast<vec *>(p));
+    else *reinterpret_cast<vec *>(p) = v;
+}
+template <bool NT>
+__device__ __forceinline__ void sw_ld2(const V2<float> *p, V2<float> &a, V2<float> &b) {
+    typedef float vec __attribute__((ext_vector_type(4)));
+    const vec v = NT ? __builtin_nontemporal_load(reinterpret_cast<const vec *>(p)) : *reinterpret_cast<const vec *>(p);
+    a.x = v.x;
+    a.y = v.y;
+    b.x = v.z;
+    b.y = v.w;
+}
+template <bool NT>
+__device__ __forceinline__ void sw_st2(V2<float> *p, V2<float> a, V2<float> b) {
+    typedef float vec __attribute__((ext_vector_type(4)));
+    const vec v = {a.x, a.y, b.x, b.y};
+    if (NT) __builtin_nontemporal_store(v, reinterpret_cast<vec *>(p));
+    else *reinterpret_cast<vec *>(p) = v;
+}
+
+// The gate on the amplitudes of one index set (k = index of v[0]).
+template <int KIND, typename R>
+__device__ __forceinline__ void sweep_apply(V2<R> (&v)[sweep_nidx(KIND)], uint64_t k, const SweepArgs<R> &A) {
+    if constexpr (KIND == SW_U1) {
+        const V2<R> x = v[0], y = v[1];
+        v[0] = cmac2(mat_at(A.op, 0), x, mat_at(A.op, 1), y);
+        v[1] = cmac2(mat_at(A.op, 2), x, mat_at(A.op, 3), y);
+    } else if constexpr (KIND == SW_XPERM || KIND == SW_SWAP) {
+        const V2<R> x = v[0];
+        v[0] = v[1];
+        v[1] = x;
+    } else if constexpr (KIND == SW_U2) {
+        V2<R> w[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            V2<R> acc = cmul(mat_at(op, 4 * i), v[0]);
+            V2<R> acc = cmul(mat_at(A.op, 4 * i), v[0]);
 #pragma unroll
             for (int j = 1; j < 4; ++j) {
-                V2<R> t = cmul(mat_at(op, 4 * i + j), v[j]);
+                const V2<R> t = cmul(mat_at(A.op, 4 * i + j), v[j]);
                 acc.x += t.x;
                 acc.y += t.y;
             }
             w[i] = acc;
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) psi[idx[i]] = w[i];
+        for (int i = 0; i < 4; ++i) v[i] = w[i];
+    } else if constexpr (KIND == SW_PHASE) {
+        v[0] = cmul(v[0], A.f);
+    } else if constexpr (KIND == SW_DIAG) {
+        int idx = (int)((k >> A.a) & 1);
+        if (A.b >= 0) idx = 2 * idx + (int)((k >> A.b) & 1);
+        v[0] = cmul(v[0], mat_at(A.op, idx));
+    } else {
+        v[0] = cmul(v[0], ladder_phase<R>(A.turns, k & A.lmask));
     }
 }
 
-// Phase on the amplitudes selected by `in` (every fixed bit set): factor f.
-template <typename R>
-__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_phase(V2<R> *__restrict__ psi, uint64_t items,
-                                                           Ins in, V2<R> f) {
-    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
-    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
-        const uint64_t k = expand(r, in);
-        psi[k] = cmul(psi[k], f);
+// Index set of one gate application from the smallest index k.
+template <int KIND, typename R>
+__device__ __forceinline__ void sweep_index(uint64_t (&idx)[sweep_nidx(KIND)], uint64_t k, const SweepArgs<R> &A) {
+    idx[0] = k;
+    if constexpr (KIND == SW_U1 || KIND == SW_XPERM) {
+        idx[1] = k | (1ull << A.a);
+    } else if constexpr (KIND == SW_SWAP) {
+        idx[1] = k ^ A.flip;
+    } else if constexpr (KIND == SW_U2) {
+        idx[1] = k | (1ull << A.b);
+        idx[2] = k | (1ull << A.a);
+        idx[3] = k | (1ull << A.a) | (1ull << A.b);
     }
 }
 
-// General diagonal: amplitudes with all control bits set get m[idx(bits a, b)].
-template <typename R>
-__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_diag(V2<R> *__restrict__ psi, uint64_t items,
-                                                          Ins in, int a, int b, DevOp<R> op) {
-    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
-    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
-        const uint64_t k = expand(r, in);
-        int idx = (int)((k >> a) & 1);
-        if (b >= 0) idx = 2 * idx + (int)((k >> b) & 1);
-        psi[k] = cmul(psi[k], mat_at(op, idx));
+// One gate over the whole state: thread t handles reduced index t (two
+// adjacent ones in SWM_VEC2), expanded by `in` to the indices of the
+// amplitudes the gate touches.  One thread per work item (exact grid): a
+// grid-stride loop measured slower on these streaming sweeps.  With U > 1
+// (index sets far apart) a thread takes U work items, 256 * W apart, so
+// each stream of a wavefront has U accesses in flight; the grid then covers
+// the items exactly (items a multiple of 256 * W * U).
+template <typename R, int KIND, int MODE, bool NT, int U>
+__global__ __launch_bounds__(SWEEP_TPB) void k_sweep(V2<R> *__restrict__ psi, uint64_t threads, Ins in,
+                                                     SweepArgs<R> A) {
+    constexpr int NI = sweep_nidx(KIND);
+    if constexpr (U > 1) {
+        static_assert(MODE != SWM_PAIR, "pair mode takes one item per thread");
+        constexpr int W = MODE == SWM_VEC2 ? 2 : 1;
+        const uint64_t rb = (uint64_t)blockIdx.x * (SWEEP_TPB * W * U) + W * threadIdx.x;
+        uint64_t idx[U][NI];
+        V2<R> v0[U][NI], v1[U][NI];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            sweep_index<KIND, R>(idx[u], expand(rb + (uint64_t)(SWEEP_TPB * W) * u, in), A);
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                if constexpr (W == 2) sw_ld2<NT>(psi + idx[u][i], v0[u][i], v1[u][i]);
+                else v0[u][i] = sw_ld1<NT, R>(psi + idx[u][i]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            sweep_apply<KIND, R>(v0[u], idx[u][0], A);
+            if constexpr (W == 2) sweep_apply<KIND, R>(v1[u], idx[u][0] + 1, A);
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                if constexpr (W == 2) sw_st2<NT>(psi + idx[u][i], v0[u][i], v1[u][i]);
+                else sw_st1<NT, R>(psi + idx[u][i], v0[u][i]);
+            }
+        }
+        return;
     }
-}
-
-template <typename R>
-__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_ladder(V2<R> *__restrict__ psi, uint64_t items,
-                                                            Ins in, uint64_t lmask, double turns) {
-    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
-    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
-        const uint64_t k = expand(r, in);
-        psi[k] = cmul(psi[k], ladder_phase<R>(turns, k & lmask));
-    }
-}
-
-template <typename R>
-__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_swap(V2<R> *__restrict__ psi, uint64_t items,
-                                                          Ins in, uint64_t flip) {
-    const uint64_t stride = (uint64_t)gridDim.x * SWEEP_TPB;
-    for (uint64_t r = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x; r < items; r += stride) {
-        const uint64_t k = expand(r, in), k2 = k ^ flip;
-        const V2<R> x = psi[k], y = psi[k2];
-        psi[k] = y;
-        psi[k2] = x;
+    const uint64_t t = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x;
+    if (t >= threads) return;
+    if constexpr (MODE == SWM_PAIR) {
+        const uint64_t k = expand(t, in);  // bit 0 inserted as 0: the pair is (k, k + 1)
+        V2<R> v[2];
+        sw_ld2<NT>(psi + k, v[0], v[1]);
+        sweep_apply<KIND, R>(v, k, A);
+        sw_st2<NT>(psi + k, v[0], v[1]);
+    } else if constexpr (MODE == SWM_VEC2) {
+        const uint64_t k = expand(2 * t, in);  // bit 0 free: expand(2t + 1) = k + 1
+        uint64_t idx[NI];
+        sweep_index<KIND, R>(idx, k, A);
+        V2<R> v0[NI], v1[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) sw_ld2<NT>(psi + idx[i], v0[i], v1[i]);
+        sweep_apply<KIND, R>(v0, k, A);
+        sweep_apply<KIND, R>(v1, k + 1, A);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) sw_st2<NT>(psi + idx[i], v0[i], v1[i]);
+    } else {
+        const uint64_t k = expand(t, in);
+        uint64_t idx[NI];
+        sweep_index<KIND, R>(idx, k, A);
+        V2<R> v[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) v[i] = sw_ld1<NT, R>(psi + idx[i]);
+        sweep_apply<KIND, R>(v, k, A);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) sw_st1<NT, R>(psi + idx[i], v[i]);
     }
 }
 
@@ -456,48 +539,164 @@ static unsigned tile_grid(uint64_t tiles, int cu) {
     return (unsigned)std::max<uint64_t>(1, std::min(tiles, cap));
 }
 
+// One-qubit gate (U1 or X) on a low bit a whose partner sits in another
+// lane of the same wavefront: each lane loads 16 contiguous bytes (two
+// complex64 / one complex128 amplitude), so a wavefront reads and writes one
+// contiguous kilobyte, and the partner amplitudes come from lane t ^ d by a
+// cross-lane permute.  `in` inserts the control bits only; they all lie above
+// the wavefront's span, and the thread count is a multiple of 64.
+template <typename R, int KIND>
+__global__ __launch_bounds__(SWEEP_TPB) void k_sweep_shfl(V2<R> *__restrict__ psi, uint64_t threads, Ins in,
+                                                          SweepArgs<R> A, int d) {
+    const uint64_t t = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x;
+    if (t >= threads) return;  // whole wavefronts only
+    constexpr int W = sizeof(R) == 4 ? 2 : 1;
+    const uint64_t k = expand(t * W, in);
+    V2<R> own[W], par[W];
+    if constexpr (W == 2) sw_ld2<true>(psi + k, own[0], own[1]);
+    else own[0] = sw_ld1<true, R>(psi + k);
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        par[i].x = __shfl_xor(own[i].x, d);
+        par[i].y = __shfl_xor(own[i].y, d);
+    }
+    if constexpr (KIND == SW_XPERM) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) own[i] = par[i];
+    } else {
+        // own amplitude has bit a = b: new = m[b][b] * own + m[b][1-b] * partner
+        const bool b = (k >> A.a) & 1;
+        const V2<R> co = b ? mat_at(A.op, 3) : mat_at(A.op, 0), cp = b ? mat_at(A.op, 2) : mat_at(A.op, 1);
+#pragma unroll
+        for (int i = 0; i < W; ++i) own[i] = cmac2(co, own[i], cp, par[i]);
+    }
+    if constexpr (W == 2) sw_st2<true>(psi + k, own[0], own[1]);
+    else sw_st1<true, R>(psi + k, own[0]);
+}
+
+// Launch one sweep: `pos` are the index bits inserted by `in` (controls and
+// the bits a gate acts on), `low` the smallest distance in bytes between
+// two amplitudes of one index set (0 when a set has one amplitude).
+template <typename R, int KIND>
+static void launch_sweep(Ctx *ctx, V2<R> *psi, int n, const std::vector<int> &pos, uint64_t ones,
+                         const SweepArgs<R> &A, size_t low, const char *name, double bytes) {
+    if constexpr (KIND == SW_U1 || KIND == SW_XPERM) {
+        // partner in another lane of the wavefront (a below its span of 2^span
+        // amplitudes; complex64 bit 0 is the 16-byte pair), controls above it
+        constexpr int W = sizeof(R) == 4 ? 2 : 1, span = sizeof(R) == 4 ? 7 : 6;
+        int cmin = 64;
+        for (int p : pos)
+            if (p != A.a) cmin = std::min(cmin, p);
+        const int nc = (int)pos.size() - 1;
+        if (A.a < span && (W == 1 || A.a >= 1) && cmin >= span && n - nc >= span) {
+            std::vector<int> cpos;
+            for (int p : pos)
+                if (p != A.a) cpos.push_back(p);
+            const Ins cin = make_ins(cpos, ones);
+            const uint64_t threads = (1ull << (n - nc)) / W;
+            const uint64_t blocks = (threads + SWEEP_TPB - 1) / SWEEP_TPB;
+            if (blocks > 0x7fffffffull) fail(SV_EINVAL, "sweep launch too large");
+            LaunchScope ls(ctx, name, bytes);
+            hipLaunchKernelGGL((k_sweep_shfl<R, KIND>), dim3((unsigned)blocks), dim3(SWEEP_TPB), 0, ctx->stream, psi,
+                               threads, cin, A, (1 << A.a) / W);
+            return;
+        }
+    }
+    const Ins in = make_ins(pos, ones);
+    const uint64_t items = 1ull << (n - pos.size());
+    bool bit0 = false;
+    for (int p : pos) bit0 |= p == 0;
+    int mode = SWM_ONE;
+    if constexpr (sizeof(R) == 4) {
+        if (!bit0 && items >= 2) mode = SWM_VEC2;
+        else if ((KIND == SW_U1 || KIND == SW_XPERM) && A.a == 0 && !(ones & 1)) mode = SWM_PAIR;
+    }
+    // streaming (non-temporal) accesses unless the index set shares a cache
+    // line (then the second access of a lane reuses the line of the first);
+    // single amplitudes of complex64 stay plain (sparse patterns)
+    const bool nt = (low == 0 || low >= 128) && (mode != SWM_ONE || sizeof(R) == 16);
+    // index sets spread over 32 MiB and more: four items per thread
+    const int W = mode == SWM_VEC2 ? 2 : 1;
+    const bool wide = low >= ((size_t)32 << 20) && mode != SWM_PAIR && (mode != SWM_ONE || sizeof(R) == 16) &&
+                      items % (uint64_t)(SWEEP_TPB * W * 4) == 0;
+    const uint64_t threads = items / W;
+    const uint64_t blocks = wide ? items / (SWEEP_TPB * W * 4) : (threads + SWEEP_TPB - 1) / SWEEP_TPB;
+    if (blocks > 0x7fffffffull) fail(SV_EINVAL, "sweep launch too large");
+    LaunchScope ls(ctx, name, bytes);
+    auto go = [&](auto MODE_C, auto NT_C, auto U_C) {
+        constexpr int M = decltype(MODE_C)::value;
+        constexpr bool T = decltype(NT_C)::value;
+        constexpr int UU = decltype(U_C)::value;
+        hipLaunchKernelGGL((k_sweep<R, KIND, M, T, UU>), dim3((unsigned)blocks), dim3(SWEEP_TPB), 0, ctx->stream,
+                           psi, threads, in, A);
+    };
+    using I0 = std::integral_constant<int, SWM_ONE>;
+    using IT = std::true_type;
+    using IF = std::false_type;
+    using U1c = std::integral_constant<int, 1>;
+    using U4c = std::integral_constant<int, 4>;
+    if constexpr (sizeof(R) == 4) {
+        using IV = std::integral_constant<int, SWM_VEC2>;
+        if (mode == SWM_VEC2) {
+            if (wide) go(IV{}, IT{}, U4c{});
+            else if (nt) go(IV{}, IT{}, U1c{});
+            else go(IV{}, IF{}, U1c{});
+            return;
+        }
+        if constexpr (KIND == SW_U1 || KIND == SW_XPERM) {
+            using IP = std::integral_constant<int, SWM_PAIR>;
+            if (mode == SWM_PAIR) {
+                go(IP{}, IT{}, U1c{});
+                return;
+            }
+        }
+        if (nt) go(I0{}, IT{}, U1c{});
+        else go(I0{}, IF{}, U1c{});
+    } else {
+        if (wide) go(I0{}, IT{}, U4c{});
+        else if (nt) go(I0{}, IT{}, U1c{});
+        else go(I0{}, IF{}, U1c{});
+    }
+}
+
 template <typename R>
 void sweep_one(Ctx *ctx, V2<R> *psi, int n, const Op &op) {
-    const int cu = ctx->cu_count;
-    const double amp = (double)sizeof(V2<R>);
-    DevOp<R> d = to_dev<R>(op);
+    const size_t amp = sizeof(V2<R>);
+    SweepArgs<R> A;
+    std::memset(&A, 0, sizeof A);
+    A.op = to_dev<R>(op);
+    A.a = op.a;
+    A.b = op.b;
     std::vector<int> cb = bits_of(op.cmask);
     switch (op.kind) {
     case OP_U1:
     case OP_XPERM: {
         std::vector<int> pos = cb;
         pos.push_back(op.a);
-        const Ins in = make_ins(pos, op.cmask);
-        const uint64_t items = 1ull << (n - pos.size());
-        LaunchScope ls(ctx, op.kind == OP_U1 ? "sweep_u1" : "sweep_xperm", 4.0 * amp * items);
+        const double bytes = 2.0 * amp * (double)(1ull << (n - cb.size()));
         if (op.kind == OP_U1)
-            hipLaunchKernelGGL(k_sweep_u1<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
-                               ctx->stream, psi, items, in, op.a, d);
+            launch_sweep<R, SW_U1>(ctx, psi, n, pos, op.cmask, A, amp << op.a, "sweep_u1", bytes);
         else
-            hipLaunchKernelGGL(k_sweep_xperm<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
-                               ctx->stream, psi, items, in, op.a);
+            launch_sweep<R, SW_XPERM>(ctx, psi, n, pos, op.cmask, A, amp << op.a, "sweep_xperm", bytes);
         break;
     }
     case OP_U2: {
         std::vector<int> pos = cb;
         pos.push_back(op.a);
         pos.push_back(op.b);
-        const Ins in = make_ins(pos, op.cmask);
-        const uint64_t items = 1ull << (n - pos.size());
-        LaunchScope ls(ctx, "sweep_u2", 8.0 * amp * items);
-        hipLaunchKernelGGL(k_sweep_u2<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
-                           ctx->stream, psi, items, in, op.a, op.b, d);
+        const double bytes = 2.0 * amp * (double)(1ull << (n - cb.size()));
+        launch_sweep<R, SW_U2>(ctx, psi, n, pos, op.cmask, A, amp << std::min(op.a, op.b), "sweep_u2", bytes);
         break;
     }
     case OP_SWAP: {
         std::vector<int> pos = cb;
         pos.push_back(op.a);
         pos.push_back(op.b);
-        const Ins in = make_ins(pos, op.cmask | (1ull << op.a));
-        const uint64_t items = 1ull << (n - pos.size());
-        LaunchScope ls(ctx, "sweep_swap", 4.0 * amp * items);
-        hipLaunchKernelGGL(k_sweep_swap<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
-                           ctx->stream, psi, items, in, (1ull << op.a) | (1ull << op.b));
+        A.flip = (1ull << op.a) | (1ull << op.b);
+        // pairs (k, k ^ flip) with bit a set and bit b clear: half the state moves
+        const double bytes = 2.0 * amp * (double)(1ull << (n - cb.size() - 1));
+        launch_sweep<R, SW_SWAP>(ctx, psi, n, pos, op.cmask | (1ull << op.a), A, amp << std::min(op.a, op.b),
+                                 "sweep_swap", bytes);
         break;
     }
     case OP_DIAG: {
@@ -514,29 +713,21 @@ void sweep_one(Ctx *ctx, V2<R> *psi, int n, const Op &op) {
                 if (!(ones & (1ull << op.b))) pos.push_back(op.b);
                 ones |= 1ull << op.b;
             }
-            const Ins in = make_ins(pos, ones);
-            const uint64_t items = 1ull << (n - pos.size());
-            V2<R> f;
-            f.x = (R)op.m[last].real();
-            f.y = (R)op.m[last].imag();
-            LaunchScope ls(ctx, "sweep_phase", 2.0 * amp * items);
-            hipLaunchKernelGGL(k_sweep_phase<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
-                               ctx->stream, psi, items, in, f);
+            A.f.x = (R)op.m[last].real();
+            A.f.y = (R)op.m[last].imag();
+            const double bytes = 2.0 * amp * (double)(1ull << (n - pos.size()));
+            launch_sweep<R, SW_PHASE>(ctx, psi, n, pos, ones, A, 0, "sweep_phase", bytes);
         } else {
-            const Ins in = make_ins(cb, op.cmask);
-            const uint64_t items = 1ull << (n - cb.size());
-            LaunchScope ls(ctx, "sweep_diag", 2.0 * amp * items);
-            hipLaunchKernelGGL(k_sweep_diag<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
-                               ctx->stream, psi, items, in, op.a, op.b, d);
+            const double bytes = 2.0 * amp * (double)(1ull << (n - cb.size()));
+            launch_sweep<R, SW_DIAG>(ctx, psi, n, cb, op.cmask, A, 0, "sweep_diag", bytes);
         }
         break;
     }
     case OP_LADDER: {
-        const Ins in = make_ins({op.a}, 1ull << op.a);
-        const uint64_t items = 1ull << (n - 1);
-        LaunchScope ls(ctx, "sweep_ladder", 2.0 * amp * items);
-        hipLaunchKernelGGL(k_sweep_ladder<R>, dim3(grid_for(items, SWEEP_TPB, cu)), dim3(SWEEP_TPB), 0,
-                           ctx->stream, psi, items, in, op.lmask, op.turns);
+        A.lmask = op.lmask;
+        A.turns = op.turns;
+        const double bytes = 2.0 * amp * (double)(1ull << (n - 1));
+        launch_sweep<R, SW_LADDER>(ctx, psi, n, {op.a}, 1ull << op.a, A, 0, "sweep_ladder", bytes);
         break;
     }
     default:

@@ -94,6 +94,29 @@ def test_each_kind_every_position(ctx, kind, n, dtype):
 
 
 @pytest.mark.parametrize("dtype", [C128, C64])
+def test_sweeps_on_far_apart_bits(ctx, dtype):
+    # one launch per gate on a 24-qubit state: index sets 32 MiB and more
+    # apart (several work items per thread), in-wavefront partners (lane
+    # shuffles), bit 0 pairs, controls above and below the wavefront span
+    n = 24
+    psi0 = I.gaussian_state(n, 77)
+    rng = np.random.default_rng(5)
+    z = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    m2, _ = np.linalg.qr(z)
+    cases = [(I.U3, [0], [0.3, 1.2, 2.1]), (I.U3, [1], [0.5, 0.1, 0.9]), (I.H, [2], []),
+             (I.CNOT, [0, 1], []), (I.CNOT, [1, 0], []), (I.CNOT, [0, n - 1], []), (I.CNOT, [0, n - 3], []),
+             (I.CRY, [n - 1, 0], [0.7]), (I.X, [n - 5], []), (I.RY, [n - 7], [1.3]),
+             (I.SWAP, [0, 2], []), (I.SWAP, [1, n - 1], []), (I.CZ, [0, 1], []), (I.CP, [0, n - 2], [0.4]),
+             (I.RZZ, [0, 1], [0.8]), (I.MAT2, [1, 0], None)]
+    for kind, qs, ang in cases:
+        c = single_gate(n, kind, qs, ang, m2 if kind == I.MAT2 else None)
+        want = oracle.run_circuit(c, None, psi0)
+        got = run_gpu(ctx, c, None, psi0, dtype, 1)
+        ok, err = amp_tol_ok(got, want, dtype, 1)
+        assert ok, (I.KIND_NAMES[kind], qs, err)
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
 @pytest.mark.parametrize("n,G,seed", [(1, 20, 1), (2, 40, 2), (8, 300, 3), (13, 300, 4),
                                       (14, 300, 5), (17, 300, 6), (20, 200, 7)])
 def test_random_circuits(ctx, n, G, seed, dtype):
