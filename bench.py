@@ -10,8 +10,11 @@ Extras in the same JSON line (each bounded in time):
              launch per gate, GB/s per pass
   grad10     10-qubit complex128 VQE gradient (161 circuits): batched vs one
              circuit at a time
+  vqe10      the same ansatz and Hamiltonian minimised by Adam (lr 1e-2, at
+             most 350 iterations, tolerance 1e-7), one gradient per iteration
   grad20     20-qubit complex64 gradient, 8 layers (641 circuits), 200-term
              random 2-local Hamiltonian: batched vs one circuit at a time
+  sweeps     single-gate sweeps on an 8 GiB state: GB/s per gate and bit
   deep30     30-qubit complex64 depth-40 U3 + CZ circuit: fused vs unfused
   serving    Poisson stream of mixed requests through the serving queue
              (bounded sample), p50/p99 latency vs a serial loop
@@ -200,6 +203,24 @@ def bench_deep30(ctx, sv, inputs, n=30, depth=40):
     return rec
 
 
+def bench_vqe(ctx, sv, inputs):
+    """Config-1 VQE at the paper's optimiser settings (Adam, lr 1e-2, at most
+    350 iterations, tolerance 1e-7), one batched gradient per iteration."""
+    c = inputs.hea_circuit(10, 4)
+    ham = inputs.xyz_chain(10)
+    p0 = inputs.uniform_params(c.n_params, 1)
+    ctx.vqe_adam(c, p0, ham, sv.C128, max_iters=3)  # warm-up
+    t0 = time.perf_counter()
+    th, e = ctx.vqe_adam(c, p0, ham, sv.C128)
+    dt = time.perf_counter() - t0
+    e0 = -9.161997432407  # exact diagonalisation of the 10-site chain
+    rec = {"n": 10, "dtype": "c128", "iterations": int(len(e)), "ms": dt * 1e3,
+           "ms_per_iteration": dt * 1e3 / len(e), "energy_first": float(e[0]), "energy_final": float(e[-1]),
+           "exact_ground_energy": e0, "gap_to_ground": float(e[-1] - e0)}
+    log(f"[bench] vqe10: {len(e)} iterations in {dt*1e3:.1f} ms, E {e[0]:.6f} -> {e[-1]:.6f} (E0 {e0})")
+    return rec
+
+
 def bench_sweeps(ctx, sv, inputs):
     """GB/s of single-gate sweeps (the plain path: one launch per gate) on an
     8 GiB state, per gate and target position: algorithmic bytes (the
@@ -382,6 +403,7 @@ def main():
                               {"sequential": sv.FLAG_SEQUENTIAL,
                                "sequential_unfused": sv.FLAG_SEQUENTIAL | sv.FLAG_UNFUSED}, direct)
         extras["grad10_c128"] = rec10
+        extras["vqe10_c128"] = bench_vqe(ctx, sv, inputs)
         log(f"[bench] grad10: {rec10['batched_ms']:.3f} ms (direct launches "
             f"{rec10['batched_direct_launch_ms']:.3f} ms)")
         rec20, _ = bench_grad(ctx, sv, inputs, 20, 8, sv.C64, inputs.random_2local(20, 200, 3), 2, 1,

@@ -251,6 +251,26 @@ int sv_param_shift_grad_ex(sv_ctx *ctx, int dtype, const sv_circuit *circuit,
                            double *energy, double *grad);
 
 /*
+ * Variational eigensolver loop (Sec. "Variational Quantum Eigensolver"): minimise
+ * E(theta) = <psi(theta)|H|psi(theta)> with Adam (Kingma and Ba: first and
+ * second moment decay 0.9 and 0.999, denominator offset 1e-8, bias-corrected)
+ * at learning rate lr, each step driven by one batched parameter-shift
+ * gradient as in sv_param_shift_grad (same dtype and tolerances).  Iteration
+ * t evaluates E_t and the gradient at the current parameters, records E_t in
+ * energies[t - 1] (nullable; room for max_iters values) and stops when
+ * t == max_iters or |E_t - E_{t-1}| < tol (t > 1); otherwise it takes the
+ * Adam step.  params (n_params values) holds the initial parameters on entry
+ * and, on return, those at which the last recorded energy was evaluated;
+ * *iterations (nullable) receives the number of evaluations.  max_iters >= 1,
+ * lr > 0 and tol >= 0 must be finite.  Errors as for sv_param_shift_grad;
+ * on an error params are left unchanged (energies may hold the iterations
+ * that completed).
+ */
+int sv_vqe_adam(sv_ctx *ctx, int dtype, const sv_circuit *circuit, double *params,
+                size_t n_params, const sv_pauli_sum *ham, double lr, int max_iters,
+                double tol, double *energies, int *iterations);
+
+/*
  * Energies of many independent circuits of possibly different qubit counts
  * in one batched launch, each from |0...0>: energies[i] =
  * <psi_i|H_i|psi_i> for circuits[i], params[i], hams[i].

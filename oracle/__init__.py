@@ -208,6 +208,38 @@ def param_shift_two_term(circuit, params, ham) -> np.ndarray:
     return g[:ca.n_params].copy()
 
 
+def adam_minimise(fg, theta0, lr=1e-2, max_iters=350, tol=1e-7,
+                  beta1=0.9, beta2=0.999, eps=1e-8):
+    """Adam (Kingma and Ba) on a function given as fg(theta) -> (f, grad):
+    first and second moment estimates with decay beta1 / beta2, divided by
+    1 - beta^t (bias correction), step -lr * m_hat / (sqrt(v_hat) + eps).
+    The VQE loop of Sec. "Variational Quantum Eigensolver" uses lr = 1e-2,
+    at most 350 iterations and tolerance 1e-7; the stopping rule read here:
+    iteration t evaluates f_t at the current theta and stops when t equals
+    max_iters or |f_t - f_{t-1}| < tol, else steps.  Returns (theta of the
+    last evaluation, [f_1, ..., f_T])."""
+    theta = np.array(theta0, dtype=np.float64, copy=True)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    fs = []
+    for t in range(1, max_iters + 1):
+        f, g = fg(theta)
+        fs.append(f)
+        if t == max_iters or (t > 1 and abs(f - fs[-2]) < tol):
+            break
+        m = beta1 * m + (1.0 - beta1) * g
+        v = beta2 * v + (1.0 - beta2) * g * g
+        m_hat = m / (1.0 - beta1 ** t)
+        v_hat = v / (1.0 - beta2 ** t)
+        theta = theta - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return theta, np.array(fs)
+
+
+def vqe_adam(circuit, params, ham, lr=1e-2, max_iters=350, tol=1e-7):
+    """VQE energy minimisation: Adam driven by parameter-shift gradients."""
+    return adam_minimise(lambda th: param_shift(circuit, th, ham), params, lr, max_iters, tol)
+
+
 def norm2(psi: np.ndarray) -> float:
     psi = _state(psi)
     return float(lib().or_norm2(_d(psi), _nq(psi)))

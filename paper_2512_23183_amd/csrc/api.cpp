@@ -438,6 +438,46 @@ int sv_param_shift_grad(sv_ctx *ctx, int dtype, const sv_circuit *circuit, const
     return sv_param_shift_grad_ex(ctx, dtype, circuit, params, n_params, ham, 0, energy, grad);
 }
 
+int sv_vqe_adam(sv_ctx *ctx, int dtype, const sv_circuit *circuit, double *params, size_t n_params,
+                const sv_pauli_sum *ham, double lr, int max_iters, double tol, double *energies,
+                int *iterations) {
+    return guard([&] {
+        need(ctx != nullptr, "ctx is NULL");
+        check_dtype(dtype);
+        check_circuit(circuit, params, n_params);
+        check_pauli_sum(ham, circuit->n_qubits);
+        need(max_iters >= 1, "max_iters must be at least 1");
+        need(std::isfinite(lr) && lr > 0.0, "lr must be finite and positive");
+        need(std::isfinite(tol) && tol >= 0.0, "tol must be finite and non-negative");
+        use_device(ctx);
+        if (iterations) *iterations = 0;
+        // Adam moments (Kingma and Ba), bias-corrected
+        const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+        std::vector<double> theta(params, params + n_params), m(n_params, 0.0), v(n_params, 0.0);
+        double prev = 0.0, p1 = 1.0, p2 = 1.0;
+        for (int t = 1; t <= max_iters; ++t) {
+            BatchSpec spec = psr_spec(circuit, theta.data(), n_params, ham, dtype, true);
+            std::vector<double> E, g;
+            run_batch(ctx, spec, 0, E, g);
+            check_finite(E[0], "energy");
+            for (double x : g) check_finite(x, "gradient");
+            if (energies) energies[t - 1] = E[0];
+            if (iterations) *iterations = t;
+            if (t == max_iters || (t > 1 && std::fabs(E[0] - prev) < tol)) break;
+            prev = E[0];
+            p1 *= b1;
+            p2 *= b2;
+            for (size_t i = 0; i < n_params; ++i) {
+                m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+                v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+                const double mh = m[i] / (1.0 - p1), vh = v[i] / (1.0 - p2);
+                theta[i] -= lr * mh / (std::sqrt(vh) + eps);
+            }
+        }
+        std::copy(theta.begin(), theta.end(), params);
+    });
+}
+
 int sv_batch_energies(sv_ctx *ctx, int dtype, size_t n_circuits, const sv_circuit *circuits,
                       const double *const *params, const sv_pauli_sum *hams, double *energies) {
     return guard([&] {

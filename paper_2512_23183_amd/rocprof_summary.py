@@ -1,8 +1,9 @@
 """Short text summaries of rocprofv3 SQLite results (``*_results.db``).
 
-  python -m paper_2512_23183_amd.rocprof_summary stats DB [--match REGEX]
+  python -m paper_2512_23183_amd.rocprof_summary stats DB [--match REGEX] [--last N]
       per-kernel dispatch count, total / mean / min / max duration and the
-      launch shape of the first dispatch (the ``--kernel-trace --stats`` view)
+      launch shape of the last dispatch (the ``--kernel-trace --stats`` view);
+      --last keeps the last N dispatches of each kernel
   python -m paper_2512_23183_amd.rocprof_summary pmc DB [--match REGEX]
       per-kernel mean of every collected counter per dispatch
   python -m paper_2512_23183_amd.rocprof_summary traffic --kernel REGEX
@@ -47,13 +48,18 @@ def short(name: str) -> str:
     return name.replace("void ", "")
 
 
-def stats(db, match=None):
+def stats(db, match=None, last=0):
     groups = collections.OrderedDict()
     for name, dur, gx, wx, lds, vgpr, sgpr, scratch in _kernels(db):
         if match and not re.search(match, name):
             continue
         g = groups.setdefault(short(name), {"d": [], "shape": (gx, wx, lds, vgpr, sgpr, scratch)})
         g["d"].append(dur / 1e3)  # ns -> us
+        g["shape"] = (gx, wx, lds, vgpr, sgpr, scratch)
+    if last:
+        # the workload of interest runs at the end of the command
+        for g in groups.values():
+            g["d"] = g["d"][-last:]
     out = ["| kernel | calls | total ms | avg us | min us | max us | grid | wg | LDS B | VGPR | SGPR | scratch |",
            "|---|---|---|---|---|---|---|---|---|---|---|---|"]
     for k, g in sorted(groups.items(), key=lambda kv: -sum(kv[1]["d"])):
@@ -116,6 +122,7 @@ def main():
     a = sub.add_parser("stats")
     a.add_argument("db")
     a.add_argument("--match")
+    a.add_argument("--last", type=int, default=0, help="only the last N dispatches of each kernel")
     a = sub.add_parser("pmc")
     a.add_argument("db")
     a.add_argument("--match")
@@ -129,7 +136,7 @@ def main():
     a.add_argument("--copy-match", default="neg|elementwise")
     args = ap.parse_args()
     if args.cmd == "stats":
-        print(stats(args.db, args.match))
+        print(stats(args.db, args.match, args.last))
     elif args.cmd == "pmc":
         print(pmc(args.db, args.match))
     else:

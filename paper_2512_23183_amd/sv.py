@@ -124,6 +124,9 @@ def lib():
             "sv_profile_reset": [_vp],
             "sv_autotune": [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(_Config)],
             "sv_graph_stats": [_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
+            "sv_vqe_adam": [_vp, ctypes.c_int, ctypes.POINTER(_Circuit), _dp, ctypes.c_size_t,
+                            ctypes.POINTER(_PauliSum), ctypes.c_double, ctypes.c_int, ctypes.c_double, _dp,
+                            ctypes.POINTER(ctypes.c_int)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -256,6 +259,18 @@ class Context:
                                             a.params.size, ctypes.byref(h.h), flags,
                                             ctypes.byref(e), _dptr(g)))
         return e.value, g[:a.params.size].copy()
+
+    def vqe_adam(self, circuit: Circuit, params, ham: PauliSum, dtype: int = C64, lr: float = 1e-2,
+                 max_iters: int = 350, tol: float = 1e-7) -> Tuple[np.ndarray, np.ndarray]:
+        """Adam on the energy with batched parameter-shift gradients; returns
+        (parameters of the last evaluation, energies of every iteration)."""
+        a, h = _CircArgs(circuit, params), _HamArgs(ham)
+        theta = np.array(a.params, dtype=np.float64, copy=True)
+        energies = np.zeros(max(max_iters, 1))
+        it = ctypes.c_int()
+        _check(lib().sv_vqe_adam(self.h, dtype, ctypes.byref(a.c), _dptr(theta), theta.size,
+                                 ctypes.byref(h.h), lr, max_iters, tol, _dptr(energies), ctypes.byref(it)))
+        return theta, energies[:it.value]
 
     def batch_energies(self, circuits: Sequence[Circuit], params: Sequence,
                        hams: Sequence[PauliSum], dtype: int = C64) -> np.ndarray:

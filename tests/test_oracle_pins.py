@@ -291,3 +291,54 @@ def test_app_d_edge_case_table(case):
     # in this circuit the two-term rule is exact for the CRY parameter too
     np.testing.assert_allclose(g_paper_rule, g_general, atol=1e-12)
     np.testing.assert_allclose(g_general, _fd_grad(c, params, ham), atol=1e-9)
+
+
+# --- Adam and the VQE loop (Sec. "Variational Quantum Eigensolver") ---------
+
+def test_adam_first_step_is_lr_times_sign():
+    # from the definition: m_hat_1 = g and v_hat_1 = g^2, so the first step
+    # is lr * g / (|g| + eps), i.e. lr times the sign of every nonzero entry
+    g0 = np.array([3.0, -0.25, 1e-3, -40.0])
+    steps = []
+
+    def fg(th):
+        steps.append(th.copy())
+        return 0.0 if len(steps) == 1 else 1.0, g0
+
+    th, fs = oracle.adam_minimise(fg, np.zeros(4), lr=0.05, max_iters=2, tol=0.0)
+    # (within lr * eps / min|g| = 5e-7 of it)
+    np.testing.assert_allclose(steps[1], -0.05 * np.sign(g0), rtol=0, atol=1e-6)
+    assert len(fs) == 2 and np.array_equal(th, steps[1])
+
+
+def test_adam_reaches_the_minimum_of_a_convex_quadratic():
+    a = np.array([1.0, 4.0, 0.25])
+    c = np.array([0.3, -0.7, 1.1])
+    th, fs = oracle.adam_minimise(lambda x: (float(np.sum(a * (x - c) ** 2)), 2 * a * (x - c)),
+                                  np.zeros(3), lr=0.02, max_iters=5000, tol=0.0)
+    assert np.max(np.abs(th - c)) <= 2e-3
+    assert fs[-1] <= 1e-5
+
+
+def test_adam_stops_on_the_energy_tolerance():
+    # a constant function: the second evaluation differs by 0 < tol
+    calls = []
+    th, fs = oracle.adam_minimise(lambda x: (calls.append(1) or 2.0, np.ones(2)), np.zeros(2),
+                                  lr=0.1, max_iters=50, tol=1e-7)
+    assert len(fs) == 2 and len(calls) == 2
+    np.testing.assert_allclose(th, [-0.1, -0.1], atol=1e-8)
+
+
+def test_vqe_energies_respect_the_variational_bound_and_descend():
+    # 4-qubit XYZ chain, 2-layer ansatz: every energy of the loop is at or
+    # above the exact ground energy; the loop lowers the energy by a lot
+    n = 4
+    ham = I.xyz_chain(n)
+    e0 = np.linalg.eigh(brute.hamiltonian_matrix(ham))[0][0]
+    c = I.hea_circuit(n, 2)
+    th, fs = oracle.vqe_adam(c, I.uniform_params(c.n_params, 1), ham, max_iters=350)
+    assert np.all(fs >= e0 - 1e-12)
+    assert fs[-1] < fs[0] - 2.0
+    assert fs[-1] - e0 < 0.5
+    # the returned parameters are those of the last energy
+    assert abs(oracle.circuit_energy(c, th, ham) - fs[-1]) <= 1e-12
