@@ -15,6 +15,7 @@ Extras in the same JSON line (each bounded in time):
   grad20     20-qubit complex64 gradient, 8 layers (641 circuits), 200-term
              random 2-local Hamiltonian: batched vs one circuit at a time
   sweeps     single-gate sweeps on an 8 GiB state: GB/s per gate and bit
+  trotter    26-qubit XYZ-chain time evolution (20 first-order Trotter steps)
   deep30     30-qubit complex64 depth-40 U3 + CZ circuit: fused vs unfused
   serving    Poisson stream of mixed requests through the serving queue
              (bounded sample), p50/p99 latency vs a serial loop
@@ -221,6 +222,26 @@ def bench_vqe(ctx, sv, inputs):
     return rec
 
 
+def bench_trotter(ctx, sv, inputs, n=26, steps=20, t_total=2.0):
+    """Time evolution of the XYZ chain (first-order Trotter, field
+    h(t) = 2 sin t) on a resident complex64 state, and its final energy."""
+    c = inputs.trotter_xyz_circuit(n, steps, t_total)
+    st = ctx.alloc(n, sv.C64)
+    st.apply(c)  # warm-up
+    st.reset()
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    st.apply(c)
+    ctx.synchronize()
+    dt = time.perf_counter() - t0
+    e = st.expectation(inputs.xyz_chain(n, h=inputs.xyz_field(t_total)))
+    st.free()
+    rec = {"n": n, "steps": steps, "t": t_total, "gates": c.n_gates, "ms": dt * 1e3,
+           "au_per_s": c.n_gates * float(1 << n) / dt, "energy_final": e}
+    log(f"[bench] trotter n={n}: {dt*1e3:.1f} ms, {rec['au_per_s']:.3e} AU/s")
+    return rec
+
+
 def bench_sweeps(ctx, sv, inputs):
     """GB/s of single-gate sweeps (the plain path: one launch per gate) on an
     8 GiB state, per gate and target position: algorithmic bytes (the
@@ -413,6 +434,7 @@ def main():
             f"{rec20['batched_direct_launch_ms']:.2f} ms)")
         direct.close()
         extras["sweeps"] = bench_sweeps(ctx, sv, inputs)
+        extras["trotter_xyz_c64"] = bench_trotter(ctx, sv, inputs)
         extras["deep30_c64"] = bench_deep30(ctx, sv, inputs)
         if args.serving > 0:
             extras["serving"] = bench_serving(ctx, sv, inputs, args.serving)

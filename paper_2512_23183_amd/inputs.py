@@ -237,6 +237,35 @@ def deep_random_circuit(n: int, depth: int, seed: int) -> Circuit:
     return b.build(0)
 
 
+def xyz_field(t: float, amplitude: float = 2.0, omega: float = 1.0) -> float:
+    """Longitudinal field h(t) = A sin(omega t) of Eq. "xyz_hamiltonian"."""
+    return amplitude * math.sin(omega * t)
+
+
+def trotter_xyz_circuit(n: int, steps: int, t_total: float, jx: float = 1.0, jy: float = 0.8,
+                        jz: float = 0.6, amplitude: float = 2.0, omega: float = 1.0) -> Circuit:
+    """First-order Trotter circuit (Eq. "trotter") for the open XYZ chain of
+    Eq. "xyz_hamiltonian": X on every qubit (|1...1> from |0...0>), then per
+    step j (t_j = j dt, dt = t_total / steps) the factor exp(-i H_k dt) of
+    every term in the order bond (i, i+1) XX, YY, ZZ for i = 0..n-2, then
+    the field on every qubit.  H's terms are -J P_i P_{i+1} and -h(t) Z_i,
+    so exp(-i H_k dt) = R_PP(-2 J dt) and R_Z(-2 h(t_j) dt) with
+    R_P(theta) = exp(-i theta P / 2).
+    """
+    dt = t_total / steps
+    b = CircuitBuilder(n)
+    for q in range(n):
+        b.add(X, [q])
+    for j in range(steps):
+        h = xyz_field(j * dt, amplitude, omega)
+        for i in range(n - 1):
+            for kind, jv in ((RXX, jx), (RYY, jy), (RZZ, jz)):
+                b.add(kind, [i, i + 1], angles=[-2.0 * jv * dt])
+        for q in range(n):
+            b.add(RZ, [q], angles=[-2.0 * h * dt])
+    return b.build(0)
+
+
 def app_d_circuit() -> Circuit:
     """Edge-case circuit of the paper's App. D (Fig. "edge_case_circuit"):
     RX(t0) q0, RY(t1) q1, RZ(t2) q0, CNOT(0 -> 1), CRY(t3) control 1 target 0.

@@ -94,6 +94,27 @@ def test_each_kind_every_position(ctx, kind, n, dtype):
 
 
 @pytest.mark.parametrize("dtype", [C128, C64])
+@pytest.mark.parametrize("n,steps", [(10, 12), (15, 6)])
+def test_trotter_xyz_evolution_vs_oracle(ctx, n, steps, dtype):
+    # XX / YY / ZZ rotations and time-dependent Z fields from |1...1>, then
+    # the energy under H(t) at the final time
+    t = 1.2
+    c = I.trotter_xyz_circuit(n, steps, t)
+    want = oracle.run_circuit(c)
+    ham = I.xyz_chain(n, h=I.xyz_field(t))
+    e_ref, _ = oracle.energy(want, ham)
+    for flags in (0, 1):
+        st = ctx.alloc(n, dtype)
+        st.apply(c, None, flags)
+        got = st.get_amplitudes()
+        e = st.expectation(ham)
+        st.free()
+        ok, err = amp_tol_ok(got, want, dtype, c.n_gates)
+        assert ok, (flags, err)
+        assert abs(e - e_ref) <= (1e-10 if dtype == C128 else 1e-5), (flags, e, e_ref)
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
 def test_sweeps_on_far_apart_bits(ctx, dtype):
     # one launch per gate on a 24-qubit state: index sets 32 MiB and more
     # apart (several work items per thread), in-wavefront partners (lane

@@ -342,3 +342,69 @@ def test_vqe_energies_respect_the_variational_bound_and_descend():
     assert fs[-1] - e0 < 0.5
     # the returned parameters are those of the last energy
     assert abs(oracle.circuit_energy(c, th, ham) - fs[-1]) <= 1e-12
+
+
+# --- Trotter evolution of the XYZ chain (Eqs. "xyz_hamiltonian", "trotter") ---
+
+def _xyz_terms_dense(n, jx=1.0, jy=0.8, jz=0.6):
+    """Dense matrices of the chain's bond terms in circuit order, and of Z_i."""
+    bonds = []
+    for i in range(n - 1):
+        for p, jv in (("X", jx), ("Y", jy), ("Z", jz)):
+            s = ["I"] * n
+            s[i] = s[i + 1] = p
+            bonds.append((jv, brute.pauli_operator("".join(s))))
+    zs = []
+    for q in range(n):
+        s = ["I"] * n
+        s[q] = "Z"
+        zs.append(brute.pauli_operator("".join(s)))
+    return bonds, zs
+
+
+def test_trotter_circuit_is_the_product_of_term_exponentials():
+    import scipy.linalg as sla
+    n, steps, t = 4, 5, 0.9
+    bonds, zs = _xyz_terms_dense(n)
+    dt = t / steps
+    psi = np.zeros(1 << n, dtype=complex)
+    psi[-1] = 1.0  # |1111>
+    for j in range(steps):
+        h = 2.0 * math.sin(j * dt)
+        for jv, P in bonds:
+            psi = sla.expm(-1j * (-jv * P) * dt) @ psi
+        for Z in zs:
+            psi = sla.expm(-1j * (-h * Z) * dt) @ psi
+    got = oracle.run_circuit(I.trotter_xyz_circuit(n, steps, t))
+    assert np.max(np.abs(got - psi)) <= 1e-12
+
+
+def test_trotter_converges_to_the_time_ordered_evolution_at_first_order():
+    import scipy.linalg as sla
+    n, t = 4, 1.0
+    bonds, zs = _xyz_terms_dense(n)
+    Hb = sum(-jv * P for jv, P in bonds)
+    Zs = sum(zs)
+    # reference: midpoint products of the full H(t) over 2000 slices
+    psi = np.zeros(1 << n, dtype=complex)
+    psi[-1] = 1.0
+    m = 2000
+    for k in range(m):
+        tm = (k + 0.5) * t / m
+        psi = sla.expm(-1j * (Hb - 2.0 * math.sin(tm) * Zs) * (t / m)) @ psi
+    errs = [np.linalg.norm(oracle.run_circuit(I.trotter_xyz_circuit(n, s, t)) - psi) for s in (16, 32, 64)]
+    assert errs[0] > errs[1] > errs[2]
+    for a, b in zip(errs, errs[1:]):
+        assert 1.6 <= a / b <= 2.5  # first order in dt
+    # the other sign of the printed gate angles evolves under -H: no convergence
+    b = I.CircuitBuilder(n)
+    for q in range(n):
+        b.add(I.X, [q])
+    dt = t / 64
+    for j in range(64):
+        for i in range(n - 1):
+            for kind, jv in ((I.RXX, 1.0), (I.RYY, 0.8), (I.RZZ, 0.6)):
+                b.add(kind, [i, i + 1], angles=[2.0 * jv * dt])
+        for q in range(n):
+            b.add(I.RZ, [q], angles=[2.0 * 2.0 * math.sin(j * dt) * dt])
+    assert np.linalg.norm(oracle.run_circuit(b.build(0)) - psi) > 10 * errs[2]
