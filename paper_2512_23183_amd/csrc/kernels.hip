@@ -244,8 +244,14 @@ __device__ __forceinline__ uint32_t swz(uint32_t x) {
 
 // In-place involution on index bits.  The local bit set is closed under the
 // involution, so tile v maps onto tile w = P(v); the workgroup owning
-// min(v, w) exchanges both.  lperm[j] is the image of local position j.
-template <typename R>
+// min(v, w) exchanges both.  The local part of P is a bit permutation, so
+// the image of local position j is lo[j & 63] ^ hi[j >> 6] (two 64-entry
+// tables in LDS).  Software-pipelined: the loads of a workgroup's next item
+// are issued before the LDS exchange and the stores of the current one, so
+// HBM reads overlap the rest of the item.  MAXA = 16-byte accesses per
+// thread and tile (2^m / (EPA * TILE_TPB), at most 4): the registers that
+// hold two items scale with it.
+template <typename R, int MAXA>
 __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uint64_t dim, int nc,
                                                    const DevPass *__restrict__ passes, int pidx,
                                                    const uint64_t *__restrict__ aux,
@@ -258,47 +264,97 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uin
     V2<R> *B = A + T;
     uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem + 2 * (sizeof(V2<R>) << m));
     const uint32_t nhi = 1u << (m - l);
+    uint32_t *plo = reinterpret_cast<uint32_t *>(hi_off + nhi);
+    uint32_t *phi = plo + 64;
     const uint32_t lowm = (1u << l) - 1;
     for (uint32_t h = threadIdx.x; h < nhi; h += TILE_TPB) hi_off[h] = aux[P.hi_begin + h];
     const uint32_t *lperm = aux32 + P.lperm_begin;
+    if (threadIdx.x < 64) {
+        plo[threadIdx.x] = threadIdx.x < T ? lperm[threadIdx.x] : 0u;
+        phi[threadIdx.x] = (threadIdx.x << 6) < T ? lperm[threadIdx.x << 6] : 0u;
+    }
     const uint64_t fmask = P.free_mask;
     const int nfp = P.nfp;
     __syncthreads();
-    typedef typename Pair<R>::T PT;
-    constexpr int EPA = sizeof(PT) / sizeof(V2<R>);
-    constexpr int MAXA = 4;  // m <= 11: 2^11 / (EPA * TILE_TPB) accesses per thread and tile at most
+    // 16-byte register images of the accesses (two complex64 / one complex128)
+    typedef float PT __attribute__((ext_vector_type(4)));
+    constexpr int EPA = 16 / sizeof(V2<R>);
+    auto half = [](PT v, int h) __attribute__((always_inline)) {
+        V2<R> r;
+        if constexpr (EPA == 2) {
+            r.x = h ? v.z : v.x;
+            r.y = h ? v.w : v.y;
+        } else {
+            __builtin_memcpy(&r, &v, 16);
+        }
+        return r;
+    };
+    auto join = [](V2<R> a, V2<R> b) __attribute__((always_inline)) {
+        PT v;
+        if constexpr (EPA == 2) {
+            v.x = a.x;
+            v.y = a.y;
+            v.z = b.x;
+            v.w = b.y;
+        } else {
+            __builtin_memcpy(&v, &a, 16);
+        }
+        return v;
+    };
     const uint32_t nacc = T / EPA;
     const uint64_t nw = (uint64_t)nc * ntiles;
-    for (uint64_t w = blockIdx.x; w < nw; w += gridDim.x) {
+    struct Item {
+        V2<R> *psi;
+        uint64_t bv, bw;
+    };
+    // the item's tiles; false when the partner tile's workgroup owns it
+    auto meta = [&](uint64_t w, Item &it) __attribute__((always_inline)) {
         const uint64_t c = w / ntiles, t = w - c * ntiles;
-        V2<R> *__restrict__ psi = slab + c * dim;
-        const uint64_t bv = deposit(t, fmask);
-        uint64_t bw = bv;
+        it.psi = slab + c * dim;
+        it.bv = deposit(t, fmask);
+        it.bw = it.bv;
         for (int i = 0; i < nfp; ++i) {
             const int a = P.fpa[i], b = P.fpb[i];
-            if (((bv >> a) ^ (bv >> b)) & 1) bw ^= (1ull << a) | (1ull << b);
+            if (((it.bv >> a) ^ (it.bv >> b)) & 1) it.bw ^= (1ull << a) | (1ull << b);
         }
-        if (bw < bv) continue;  // the workgroup of the partner tile does both
-        const bool two = bw != bv;
+        return it.bw >= it.bv;
+    };
+    auto load = [&](const Item &it, PT (&x)[MAXA], PT (&y)[MAXA]) __attribute__((always_inline)) {
+        const bool two = it.bw != it.bv;
 #pragma unroll
         for (int a = 0; a < MAXA; ++a) {
             const uint32_t q = threadIdx.x + (uint32_t)a * TILE_TPB;
             if (q < nacc) {
                 const uint32_t j = q * EPA;
                 const uint64_t off = hi_off[j >> l] | (j & lowm);
-                const PT x = *reinterpret_cast<const PT *>(psi + (bv | off));
-                PT y;
-                if (two) y = *reinterpret_cast<const PT *>(psi + (bw | off));
+                x[a] = *reinterpret_cast<const PT *>(it.psi + (it.bv | off));
+                if (two) y[a] = *reinterpret_cast<const PT *>(it.psi + (it.bw | off));
+            }
+        }
+    };
+    Item cur;
+    PT xc[MAXA], yc[MAXA];
+    uint64_t w = blockIdx.x;
+    while (w < nw && !meta(w, cur)) w += gridDim.x;
+    if (w < nw) load(cur, xc, yc);
+    while (w < nw) {
+        // next owned item: its loads go out before this item's exchange
+        Item nxt;
+        uint64_t wn = w + gridDim.x;
+        while (wn < nw && !meta(wn, nxt)) wn += gridDim.x;
+        PT xn[MAXA], yn[MAXA];
+        if (wn < nw) load(nxt, xn, yn);
+        const bool two = cur.bw != cur.bv;
+#pragma unroll
+        for (int a = 0; a < MAXA; ++a) {
+            const uint32_t q = threadIdx.x + (uint32_t)a * TILE_TPB;
+            if (q < nacc) {
+                const uint32_t j = q * EPA;
+                A[swz<R>(j)] = half(xc[a], 0);
+                if (two) B[swz<R>(j)] = half(yc[a], 0);
                 if constexpr (EPA == 2) {
-                    A[swz<R>(j)] = make_float2(x.x, x.y);
-                    A[swz<R>(j + 1)] = make_float2(x.z, x.w);
-                    if (two) {
-                        B[swz<R>(j)] = make_float2(y.x, y.y);
-                        B[swz<R>(j + 1)] = make_float2(y.z, y.w);
-                    }
-                } else {
-                    A[swz<R>(j)] = x;
-                    if (two) B[swz<R>(j)] = y;
+                    A[swz<R>(j + 1)] = half(xc[a], 1);
+                    if (two) B[swz<R>(j + 1)] = half(yc[a], 1);
                 }
             }
         }
@@ -310,24 +366,31 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uin
                 const uint32_t j = q * EPA;
                 const uint64_t off = hi_off[j >> l] | (j & lowm);
                 PT x, y;
+                const uint32_t s0 = swz<R>(plo[j & 63] ^ phi[j >> 6]);
                 if constexpr (EPA == 2) {
-                    const uint32_t s0 = swz<R>(lperm[j]), s1 = swz<R>(lperm[j + 1]);
-                    x = pack_pair(A[s0], A[s1]);
-                    if (two) y = pack_pair(B[s0], B[s1]);
+                    const uint32_t s1 = swz<R>(plo[(j + 1) & 63] ^ phi[(j + 1) >> 6]);
+                    x = join(A[s0], A[s1]);
+                    if (two) y = join(B[s0], B[s1]);
                 } else {
-                    const uint32_t s0 = swz<R>(lperm[j]);
-                    x = A[s0];
-                    if (two) y = B[s0];
+                    x = join(A[s0], A[s0]);
+                    if (two) y = join(B[s0], B[s0]);
                 }
                 if (two) {
-                    *reinterpret_cast<PT *>(psi + (bw | off)) = x;
-                    *reinterpret_cast<PT *>(psi + (bv | off)) = y;
+                    *reinterpret_cast<PT *>(cur.psi + (cur.bw | off)) = x;
+                    *reinterpret_cast<PT *>(cur.psi + (cur.bv | off)) = y;
                 } else {
-                    *reinterpret_cast<PT *>(psi + (bv | off)) = x;
+                    *reinterpret_cast<PT *>(cur.psi + (cur.bv | off)) = x;
                 }
             }
         }
         __syncthreads();
+        w = wn;
+        cur = nxt;
+#pragma unroll
+        for (int a = 0; a < MAXA; ++a) {
+            xc[a] = xn[a];
+            yc[a] = yn[a];
+        }
     }
 }
 
@@ -859,11 +922,19 @@ void launch_plan(Ctx *ctx, const Plan &plan, const DevPlanHost<R> &h, const DevP
             // k_perm moves at most 4 accesses per thread per tile
             if ((1u << ps.m) > 4u * TILE_TPB * (16 / sizeof(V2<R>)))
                 fail(SV_EDEVICE, "internal: permutation tile too wide");
-            const size_t lds = 2 * (sizeof(V2<R>) << ps.m) + 8 * nhi;
-            set_lds_limit((const void *)k_perm<R>, lds);
-            LaunchScope ls(ctx, "perm", 2.0 * S);
-            hipLaunchKernelGGL(k_perm<R>, dim3(grid), dim3(TILE_TPB), lds, ctx->stream, slab, dim, nc, d.pass, (int)i,
-                               d.aux, d.aux32, tiles);
+            const size_t lds = 2 * (sizeof(V2<R>) << ps.m) + 8 * nhi + 2 * 64 * 4;
+            const uint32_t acc = (1u << ps.m) / (16 / sizeof(V2<R>));
+            const int maxa = acc <= TILE_TPB ? 1 : acc <= 2 * TILE_TPB ? 2 : 4;
+            auto go = [&](auto MA) {
+                constexpr int M = decltype(MA)::value;
+                set_lds_limit((const void *)k_perm<R, M>, lds);
+                LaunchScope ls(ctx, "perm", 2.0 * S);
+                hipLaunchKernelGGL((k_perm<R, M>), dim3(grid), dim3(TILE_TPB), lds, ctx->stream, slab, dim, nc,
+                                   d.pass, (int)i, d.aux, d.aux32, tiles);
+            };
+            if (maxa == 1) go(std::integral_constant<int, 1>{});
+            else if (maxa == 2) go(std::integral_constant<int, 2>{});
+            else go(std::integral_constant<int, 4>{});
         }
         SV_HIP(hipGetLastError());
     }
