@@ -24,7 +24,33 @@ struct alignas(16) DevCirc {
     int32_t n, op_begin, op_end, ovr_index;  // ovr_index: absolute op index or -1
     int32_t ovr_slot, ch_begin, ch_end, T;   // term chunks [ch_begin, ch_end)
     int32_t coeff_begin, out_slot, stage_begin, stage_end;
+    int32_t paux_begin, paux_end, pad[2];    // the op set's layout-map tables
 };
+
+// LDS copy of one circuit's ops, stages and layout-map tables (offsets in
+// bytes within the cache; counts are the maxima over the batch's op sets).
+struct SmallCache {
+    uint32_t ops, ovr, stages, paux, end;
+};
+template <typename R>
+__host__ __device__ inline SmallCache small_cache_layout(uint32_t base, int max_ops, int max_stages, int max_paux) {
+    auto al = [](uint32_t x) { return (x + 15u) & ~15u; };
+    SmallCache c;
+    c.ops = al(base);
+    c.ovr = c.ops + al((uint32_t)sizeof(DevOp<R>) * (uint32_t)max_ops);
+    c.stages = c.ovr + al((uint32_t)sizeof(DevOp<R>));
+    c.paux = c.stages + al((uint32_t)sizeof(DevStage) * (uint32_t)max_stages);
+    c.end = c.paux + al(4u * (uint32_t)max_paux);
+    return c;
+}
+
+// Copy n16 16-byte words (all threads of the workgroup).
+__device__ __forceinline__ void lds_copy16(void *dst, const void *src, uint32_t n16) {
+    typedef uint32_t w4 __attribute__((ext_vector_type(4)));
+    w4 *d = reinterpret_cast<w4 *>(dst);
+    const w4 *s = reinterpret_cast<const w4 *>(src);
+    for (uint32_t i = threadIdx.x; i < n16; i += blockDim.x) d[i] = s[i];
+}
 
 // Pauli terms of the small-circuit path in chunks of <= ESUM_CHUNK terms
 // that share an X/Y support x (local = global bits) and the part (Re / Im)
@@ -49,20 +75,30 @@ __global__ void k_fill_u32(unsigned *p, unsigned v, int count) {
     if (i < count) p[i] = v;
 }
 
-// LDS: state[2^max_n], red[TPB/64], vals[max_T + 1]; ladder tables are read
-// from global memory.
+// LDS: state[2^max_n], red[TPB/64], vals[max_T + 1], then (cache != 0) a
+// copy of the current circuit's ops, shifted op, stages and layout-map
+// tables.  A circuit is a chain of dependent steps run by one workgroup; with
+// its ops in LDS each step reads them at LDS latency instead of a cache miss
+// to L2 per op.  Ladder tables are read from global memory.
 template <typename R>
 __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
     const DevCirc *__restrict__ circ, int ncirc, unsigned *__restrict__ counter,
     const DevOp<R> *__restrict__ ops, const DevStage *__restrict__ stages, const V2<R> *__restrict__ ltab,
     const uint32_t *__restrict__ paux, const DevOp<R> *__restrict__ ovr_ops,
     const SChunk *__restrict__ chunks, const STerm *__restrict__ sterms, const double *__restrict__ coeffs,
-    double *__restrict__ energies, int max_n, int max_T) {
+    double *__restrict__ energies, int max_n, int max_T, int cache, int max_ops, int max_stages, int max_paux) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cur;
     V2<R> *st = reinterpret_cast<V2<R> *>(smem);
     double *red = reinterpret_cast<double *>(smem + (sizeof(V2<R>) << max_n));
     double *vals = red + SMALL_TPB / 64;
+    const SmallCache lay = small_cache_layout<R>((uint32_t)((sizeof(V2<R>) << max_n) + 8 * (SMALL_TPB / 64) +
+                                                            8 * ((max_T + 2) & ~1)),
+                                                 max_ops, max_stages, max_paux);
+    DevOp<R> *c_ops = reinterpret_cast<DevOp<R> *>(smem + lay.ops);
+    DevOp<R> *c_ovr = reinterpret_cast<DevOp<R> *>(smem + lay.ovr);
+    DevStage *c_st = reinterpret_cast<DevStage *>(smem + lay.stages);
+    uint32_t *c_paux = reinterpret_cast<uint32_t *>(smem + lay.paux);
     for (;;) {
         if (threadIdx.x == 0) cur = (int)atomicAdd(counter, 1u);
         __syncthreads();
@@ -93,9 +129,28 @@ __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
         tc.ltabs = ltab;
         tc.Gs = nullptr;
         ladder_split(n, tc.lsa, tc.lsb);
-        __syncthreads();
-        run_stages<R, SMALL_TPB>(st, nullptr, tc, stages, C.stage_begin, C.stage_end, ops, C.ovr_index,
-                                    ovr_ops + C.ovr_slot);
+        if (cache) {
+            // ops, stages and tables of this circuit, renumbered from 0
+            const int nops = C.op_end - C.op_begin, nst = C.stage_end - C.stage_begin;
+            lds_copy16(c_ops, ops + C.op_begin, (uint32_t)(nops * sizeof(DevOp<R>) / 16));
+            if (C.ovr_index >= 0) lds_copy16(c_ovr, ovr_ops + C.ovr_slot, (uint32_t)(sizeof(DevOp<R>) / 16));
+            for (int i = threadIdx.x; i < C.paux_end - C.paux_begin; i += SMALL_TPB) c_paux[i] = paux[C.paux_begin + i];
+            for (int i = threadIdx.x; i < nst; i += SMALL_TPB) {
+                DevStage S = stages[C.stage_begin + i];
+                S.op_begin -= C.op_begin;
+                S.op_end -= C.op_begin;
+                S.perm_tab -= C.paux_begin;
+                c_st[i] = S;
+            }
+            tc.paux = c_paux;
+            __syncthreads();
+            run_stages<R, SMALL_TPB>(st, nullptr, tc, c_st, 0, nst, c_ops,
+                                     C.ovr_index >= 0 ? C.ovr_index - C.op_begin : -1, c_ovr);
+        } else {
+            __syncthreads();
+            run_stages<R, SMALL_TPB>(st, nullptr, tc, stages, C.stage_begin, C.stage_end, ops, C.ovr_index,
+                                     ovr_ops + C.ovr_slot);
+        }
         // one wave per chunk of terms; each term's value has one writer
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const uint32_t lane = threadIdx.x & 63;
@@ -176,7 +231,8 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     std::vector<V2<R>> ltab;
     std::vector<uint32_t> paux;
     std::vector<int> set_sb(spec.op_sets.size(), -1), set_se(spec.op_sets.size(), -1);
-    int max_n = 3, max_T = 0;
+    std::vector<int> set_pb(spec.op_sets.size(), 0), set_pe(spec.op_sets.size(), 0);
+    int max_n = 3, max_T = 0, max_ops = 0, max_stages = 0, max_paux = 0;
     for (int c : idx) {
         const BatchCircuit &bc = spec.circuits[c];
         // states of fewer than 3 qubits run as 3-qubit states whose extra
@@ -194,8 +250,13 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
             }
             set_end[bc.op_set] = (int)dops.size();
             set_sb[bc.op_set] = (int)stages.size();
+            set_pb[bc.op_set] = (int)paux.size();
             build_stages<R>(dops, set_begin[bc.op_set], set_end[bc.op_set], loc, stages, paux, false);
             set_se[bc.op_set] = (int)stages.size();
+            set_pe[bc.op_set] = (int)paux.size();
+            max_ops = std::max(max_ops, set_end[bc.op_set] - set_begin[bc.op_set]);
+            max_stages = std::max(max_stages, set_se[bc.op_set] - set_sb[bc.op_set]);
+            max_paux = std::max(max_paux, set_pe[bc.op_set] - set_pb[bc.op_set]);
         }
         if (ham_gb[bc.ham] < 0) {
             DevTerms dt = build_dev_terms(spec.hams[bc.ham]);
@@ -237,6 +298,8 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
         d.op_end = set_end[bc.op_set];
         d.stage_begin = set_sb[bc.op_set];
         d.stage_end = set_se[bc.op_set];
+        d.paux_begin = set_pb[bc.op_set];
+        d.paux_end = set_pe[bc.op_set];
         d.ovr_index = -1;
         d.ovr_slot = 0;
         if (bc.ovr_index >= 0) {
@@ -285,7 +348,11 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
     char *base = (char *)scratch(ctx, "batch_small", blob.host.size());
     upload(ctx, base, blob.host.data(), blob.host.size());
     unsigned *d_cnt = (unsigned *)(base + o_cnt);
-    const size_t lds = (sizeof(V2<R>) << max_n) + 8 * (SMALL_TPB / 64) + 8 * ((max_T + 2) & ~1);
+    const size_t lds0 = (sizeof(V2<R>) << max_n) + 8 * (SMALL_TPB / 64) + 8 * ((max_T + 2) & ~1);
+    // the circuit's ops in LDS when they fit beside the state
+    const SmallCache cl = small_cache_layout<R>((uint32_t)lds0, max_ops, max_stages, max_paux);
+    const int cache = cl.end <= 96u * 1024u ? 1 : 0;
+    const size_t lds = cache ? cl.end : lds0;
     set_lds_limit((const void *)k_small_batch<R>, lds);
     const int nc = (int)circ.size();
     const int per_cu = lds <= 40 * 1024 ? 4 : lds <= 80 * 1024 ? 2 : 1;
@@ -301,7 +368,8 @@ void launch_small(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &idx, 
                            (const DevStage *)(base + o_stg), (const V2<R> *)(base + o_lt),
                            (const uint32_t *)(base + o_pa), (const DevOp<R> *)(base + o_ovr),
                            (const SChunk *)(base + o_ch), (const STerm *)(base + o_st),
-                           (const double *)(base + o_cf), d_E, max_n, max_T);
+                           (const double *)(base + o_cf), d_E, max_n, max_T, cache, max_ops, max_stages,
+                           max_paux);
         SV_HIP(hipGetLastError());
     });
 }
