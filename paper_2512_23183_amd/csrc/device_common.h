@@ -687,10 +687,10 @@ template <> struct Pair<double> { using T = double2; };
 __device__ __forceinline__ float4 pack_pair(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
 
 // Run stages [sb, se) of a tile.  With gpsi: a one-stage pass streams
-// HBM -> registers -> HBM; a multi-stage pass bulk-loads the tile into
-// LDS, runs every stage there and bulk-stores it.  Without gpsi everything
-// stays in the LDS tile.  NI = groups per thread per chunk; MAXA = 16-byte
-// accesses per thread for the bulk moves (2^m / (EPA * TPB) at most).
+// HBM -> registers -> HBM; in a multi-stage pass the first stage reads its
+// groups from HBM and writes them to the LDS tile, the middle stages work in
+// LDS and the last one writes its groups to HBM.  Without gpsi everything
+// stays in the LDS tile.  A barrier follows every stage.
 template <typename R, int TPB>
 __device__ __forceinline__ void run_stages(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
                                            const DevStage *__restrict__ stages, int sb, int se,
