@@ -446,7 +446,13 @@ void release_graph(Ctx *ctx) {
 void launch_recorded(Ctx *ctx, std::vector<std::function<void()>> &work) {
     if (work.empty()) return;
     hipGraph_t g = nullptr;
-    SV_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+    if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        // the stream cannot be captured (e.g. the caller is capturing it):
+        // launch the same kernels directly
+        (void)hipGetLastError();
+        for (auto &f : work) f();
+        return;
+    }
     try {
         for (auto &f : work) f();
     } catch (...) {

@@ -78,3 +78,22 @@ def test_batch_energies_graph_mixed_groups_and_shapes(sv):
         launches, inst = g.graph_stats()
         assert launches == 6
         assert 2 <= inst <= 6
+
+
+def test_graph_update_with_changed_arguments(sv):
+    # gradients of the same launch shape (small-circuit kernel, counter
+    # clear, combination) but different sizes: the executable graph is
+    # updated with new arguments (qubit count, LDS size, circuit count,
+    # possibly new buffers) instead of re-instantiated; every result must
+    # equal the direct launches
+    with sv.Context(0) as g, sv.Context(0, graph_batch=-1) as d:
+        for n, layers, dtype in ((6, 1, C128), (9, 2, C128), (7, 3, C128), (9, 2, C64), (11, 1, C64)):
+            c = I.hea_circuit(n, layers)
+            ham = I.random_2local(n, 12, 40 + n)
+            params = I.uniform_params(c.n_params, 50 + n)
+            e_g, g_g = g.param_shift_grad(c, params, ham, dtype)
+            e_d, g_d = d.param_shift_grad(c, params, ham, dtype)
+            assert e_g == e_d and np.array_equal(g_g, g_d), (n, layers, dtype)
+        launches, inst = g.graph_stats()
+        assert launches == 5
+        assert inst <= 3  # one per dtype at most, plus a possible change of shape
