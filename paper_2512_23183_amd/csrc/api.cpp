@@ -218,6 +218,7 @@ int sv_shutdown(sv_ctx *ctx) {
         queue_shutdown_all(ctx);
         (void)hipStreamSynchronize(ctx->stream);
         release_graph(ctx);
+        release_pinned(ctx);
         for (auto &kv : ctx->scratch)
             if (kv.second.ptr) (void)hipFree(kv.second.ptr);
         for (auto &p : ctx->pending) {

@@ -593,12 +593,32 @@ void run_batch(Ctx *ctx, const BatchSpec &spec, uint32_t flags, std::vector<doub
     const int nc = (int)spec.circuits.size();
     const int np = spec.comb_begin.empty() ? 0 : (int)spec.comb_begin.size() - 1;
     double *d_E = (double *)scratch(ctx, "batch_E", (size_t)(std::max(nc, 1) + np) * 8);
-    run_batch_dev(ctx, spec, flags, d_E, np > 0 ? d_E + nc : nullptr);
-    grad.assign(np, 0.0);
-    if (np > 0) SV_HIP(hipMemcpyAsync(grad.data(), d_E + nc, (size_t)np * 8, hipMemcpyDeviceToHost, ctx->stream));
-    E.assign(nc, 0.0);
-    if (nc) SV_HIP(hipMemcpyAsync(E.data(), d_E, (size_t)nc * 8, hipMemcpyDeviceToHost, ctx->stream));
-    SV_HIP(hipStreamSynchronize(ctx->stream));
+    pinned_begin(ctx);
+    try {
+        run_batch_dev(ctx, spec, flags, d_E, np > 0 ? d_E + nc : nullptr);
+    } catch (...) {
+        (void)hipStreamSynchronize(ctx->stream);  // the arena may still feed copies
+        pinned_end(ctx);
+        throw;
+    }
+    // energies and gradient in one copy
+    const size_t rb = (size_t)(nc + np) * 8;
+    double *h = nullptr;
+    if (ctx->pinned_on && ctx->pinned_used + rb <= ctx->pinned_cap) {
+        h = reinterpret_cast<double *>(ctx->pinned + ctx->pinned_used);
+        ctx->pinned_used += (rb + 255) & ~(size_t)255;
+    }
+    std::vector<double> hv;
+    if (!h) {
+        hv.resize(nc + np);
+        h = hv.data();
+    }
+    if (rb) SV_HIP(hipMemcpyAsync(h, d_E, rb, hipMemcpyDeviceToHost, ctx->stream));
+    const hipError_t se = hipStreamSynchronize(ctx->stream);
+    pinned_end(ctx);
+    SV_HIP(se);
+    E.assign(h, h + nc);
+    grad.assign(h + nc, h + nc + np);
     if (ctx->profile) profile_collect(ctx);
 }
 

@@ -425,7 +425,40 @@ void *scratch(Ctx *ctx, const std::string &name, size_t bytes) {
 }
 
 void upload(Ctx *ctx, void *dst, const void *src, size_t bytes) {
-    if (bytes) SV_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+    if (!bytes) return;
+    if (ctx->pinned_on && ctx->pinned_used + bytes <= ctx->pinned_cap) {
+        // through the batch call's pinned arena (a pageable copy stages
+        // through driver buffers and costs more for these small blobs)
+        char *p = ctx->pinned + ctx->pinned_used;
+        ctx->pinned_used += (bytes + 255) & ~(size_t)255;
+        std::memcpy(p, src, bytes);
+        SV_HIP(hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, ctx->stream));
+        return;
+    }
+    SV_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+}
+
+void pinned_begin(Ctx *ctx) {
+    constexpr size_t cap = (size_t)4 << 20;
+    if (!ctx->pinned) {
+        if (hipHostMalloc((void **)&ctx->pinned, cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->pinned = nullptr;
+            return;  // pageable copies then
+        }
+        ctx->pinned_cap = cap;
+    }
+    ctx->pinned_used = 0;
+    ctx->pinned_on = true;
+}
+
+void pinned_end(Ctx *ctx) { ctx->pinned_on = false; }
+
+void release_pinned(Ctx *ctx) {
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_cap = ctx->pinned_used = 0;
+    ctx->pinned_on = false;
 }
 
 void launch_or_record(Ctx *ctx, std::function<void()> f) {

@@ -272,6 +272,7 @@ void queue_destroy_impl(QueueImpl *q) {
     (void)hipSetDevice(q->ctx->device);
     (void)hipStreamSynchronize(q->ctx->stream);
     release_graph(q->ctx);
+    release_pinned(q->ctx);
     if (q->d_pool) (void)hipFree(q->d_pool);
     for (auto &kv : q->ctx->scratch)
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);

@@ -264,6 +264,11 @@ struct Ctx {
     std::vector<std::string> record_slots;                  // scratch slots touched while recording
     hipGraphExec_t graph_exec = nullptr;
     uint64_t graph_launches = 0, graph_instantiations = 0;
+    // pinned host staging for the uploads and results of one batch call
+    // (run_batch synchronises before returning, so the arena is reused)
+    char *pinned = nullptr;
+    size_t pinned_cap = 0, pinned_used = 0;
+    bool pinned_on = false;
     // profiling
     bool profile = false;
     std::map<std::string, ProfileEntry> prof;
@@ -289,6 +294,11 @@ void launch_or_record(Ctx *ctx, std::function<void()> f);
 // Launch the recorded work as one hipGraph on ctx->stream.
 void launch_recorded(Ctx *ctx, std::vector<std::function<void()>> &work);
 void release_graph(Ctx *ctx);
+// Pinned staging of a synchronous batch call: uploads between begin and end
+// go through a pinned arena (released by release_pinned).
+void pinned_begin(Ctx *ctx);
+void pinned_end(Ctx *ctx);
+void release_pinned(Ctx *ctx);
 
 // Profiling hooks around a launch.
 struct LaunchScope {
