@@ -373,7 +373,9 @@ def copy_calibration():
 
 
 def cpu_baseline(oracle_mod, inputs):
-    n = 24
+    # the headline workload itself (one QFT of the 28-qubit input), about
+    # ten seconds of FP64 oracle work on the host's cores
+    n = 28
     psi = inputs.gaussian_state(n, 2)
     t0 = time.perf_counter()
     oracle_mod.qft(psi)
