@@ -335,7 +335,9 @@ const char *sv_last_error(void);
  * Autotuner: times the gate tile width, then the permutation width, then the
  * expectation tile width of dtype on synthetic work of n_qubits qubits (a
  * gate-based QFT plus two RY/RZ + CNOT-ladder layers; a 2-local Pauli sum),
- * clamped to 8..28 qubits (27 for complex128), and keeps the fastest in ctx.
+ * clamped to 8..28 qubits (27 for complex128), and keeps the fastest in ctx;
+ * for complex64 it then times two layers of U3 + CZ with and without dense
+ * four-qubit MFMA blocks (dense_fuse).
  * cache_path (nullable): a text file with one line per device, dtype and
  * size; a valid line is used without timing, a new result is appended.
  * chosen (nullable) receives every width of ctx afterwards.  Needs a free

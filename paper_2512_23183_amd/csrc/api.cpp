@@ -556,6 +556,7 @@ int sv_autotune(sv_ctx *ctx, int dtype, int n_qubits, const char *cache_path, sv
             chosen->expect_bits_c128 = ctx->expect_bits[SV_C128];
             chosen->perm_bits_c64 = ctx->perm_bits[SV_C64];
             chosen->perm_bits_c128 = ctx->perm_bits[SV_C128];
+            chosen->dense_fuse = ctx->dense4 ? 1 : -1;
         }
     });
 }

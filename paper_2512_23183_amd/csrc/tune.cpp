@@ -68,6 +68,22 @@ Gates tuning_circuit(int n) {
     return G;
 }
 
+// Layers of fixed dense gates: U3 on every qubit, then CZ on (q, q + 1) for
+// even q, twice (runs that the planner may fuse into dense four-qubit
+// blocks).
+Gates dense_circuit(int n) {
+    Gates G;
+    for (int l = 0; l < 2; ++l) {
+        for (int q = 0; q < n; ++q) {
+            G.add(SV_U3, q, -1, 0.3 + 0.05 * q + l);
+            G.g.back().angle[1] = 0.7 + 0.03 * q;
+            G.g.back().angle[2] = 1.1 + 0.02 * q;
+        }
+        for (int q = 0; q + 1 < n; q += 2) G.add(SV_CZ, q, q + 1);
+    }
+    return G;
+}
+
 // 2-local Pauli sum with every support pattern of a chain plus long-range
 // pairs: (q, q+1) XX / YY / ZZ and (q, q + n/2) XY.
 void tuning_hamiltonian(int n, std::vector<double> &coeffs, std::string &paulis) {
@@ -124,13 +140,15 @@ void autotune(Ctx *ctx, sv_ctx *ctx_, int dtype, int n_qubits, const char *cache
         std::string line;
         while (std::getline(in, line)) {
             if (line.compare(0, key.size() + 1, key + " ") != 0) continue;
-            int tb = 0, eb = 0, pb = 0;
-            if (std::sscanf(line.c_str() + key.size(), " tile=%d expect=%d perm=%d", &tb, &eb, &pb) == 3 &&
+            int tb = 0, eb = 0, pb = 0, dn = 0;
+            if (std::sscanf(line.c_str() + key.size(), " tile=%d expect=%d perm=%d dense=%d", &tb, &eb, &pb, &dn) ==
+                    4 &&
                 tb >= 6 && tb <= TILE_MAX[dtype] && eb >= 6 && eb <= EXPECT_MAX[dtype] && pb >= 6 &&
-                pb <= PERM_MAX[dtype]) {
+                pb <= PERM_MAX[dtype] && (dn == 0 || dn == 1)) {
                 ctx->tile_bits[dtype] = tb;
                 ctx->expect_bits[dtype] = eb;
                 ctx->perm_bits[dtype] = pb;
+                if (dtype == SV_C64) ctx->dense4 = dn == 1;
                 hit = true;
             }
         }
@@ -179,9 +197,28 @@ void autotune(Ctx *ctx, sv_ctx *ctx_, int dtype, int n_qubits, const char *cache
         const int best_tb = sweep(&ctx->tile_bits[dtype], TILE_MAX[dtype] - 3, TILE_MAX[dtype], apply);
         const int best_pb = sweep(&ctx->perm_bits[dtype], PERM_MAX[dtype] - 2, PERM_MAX[dtype], apply);
         const int best_eb = sweep(&ctx->expect_bits[dtype], EXPECT_MAX[dtype] - 3, EXPECT_MAX[dtype], expect);
+        // complex64: dense four-qubit blocks on MFMA or the register stages,
+        // whichever runs the dense layers faster
+        int best_dn = ctx->dense4 ? 1 : 0;
+        if (dtype == SV_C64) {
+            Gates D = dense_circuit(n);
+            const sv_circuit dc = D.circuit(n);
+            auto apply_dense = [&] {
+                if (sv_reset(st) != SV_OK || sv_apply_circuit(st, &dc, nullptr, 0) != SV_OK)
+                    fail(SV_EDEVICE, std::string("tuning run: ") + sv_last_error());
+            };
+            int dn = best_dn;
+            sweep(&dn, 0, 1, [&] {
+                ctx->dense4 = dn == 1;
+                apply_dense();
+            });
+            best_dn = dn;
+            ctx->dense4 = best_dn == 1;
+        }
         if (cache_path && *cache_path) {
             std::ofstream out(cache_path, std::ios::app);
-            out << key << " tile=" << best_tb << " expect=" << best_eb << " perm=" << best_pb << "\n";
+            out << key << " tile=" << best_tb << " expect=" << best_eb << " perm=" << best_pb
+                << " dense=" << best_dn << "\n";
         }
     }
 }

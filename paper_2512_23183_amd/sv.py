@@ -227,7 +227,7 @@ class Context:
         cfg = _Config()
         _check(lib().sv_autotune(self.h, dtype, n_qubits,
                                  cache_path.encode() if cache_path else None, ctypes.byref(cfg)))
-        return {k: getattr(cfg, k) for k, _ in _Config._fields_ if k not in ("graph_batch", "dense_fuse")}
+        return {k: getattr(cfg, k) for k, _ in _Config._fields_ if k != "graph_batch"}
 
     def graph_stats(self) -> Tuple[int, int]:
         """(hipGraph launches, instantiations) of this context's batches."""

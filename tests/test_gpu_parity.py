@@ -435,8 +435,9 @@ def test_autotune_picks_valid_widths_and_caches(sv, tmp_path):
         first = c.autotune(C64, 14, cache)
         assert 11 <= first["tile_bits_c64"] <= 14 and 11 <= first["expect_bits_c64"] <= 14
         assert 10 <= first["perm_bits_c64"] <= 12
+        assert first["dense_fuse"] in (1, -1)
         lines = open(cache).read().splitlines()
-        assert len(lines) == 1 and "dtype0 n14" in lines[0]
+        assert len(lines) == 1 and "dtype0 n14" in lines[0] and " dense=" in lines[0]
         second = c.autotune(C64, 14, cache)        # cache hit: same widths, no new line
         assert second == first
         assert len(open(cache).read().splitlines()) == 1
