@@ -83,7 +83,7 @@ def test_each_gate_kind_every_qubit_order(kind, n):
         np.testing.assert_allclose(got, want, atol=1e-12, rtol=0)
 
 
-@pytest.mark.parametrize("n,seed", [(4, 1), (6, 2), (7, 3)])
+@pytest.mark.parametrize("n,seed", [(4, 1), (6, 2), (7, 3), (8, 4)])
 def test_random_circuit_vs_unitary_product(n, seed):
     c = I.random_circuit(n, 60, seed, n_params=5)
     params = I.uniform_params(c.n_params, seed + 10)
