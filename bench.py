@@ -330,7 +330,8 @@ def bench_serving(ctx, sv, inputs, count, seed=5):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_qft28_c64_traffic.md")
 TRAFFIC_SOURCES = ["paper_2512_23183_amd/csrc/kernels.hip", "paper_2512_23183_amd/csrc/tile_kernel.h",
                    "paper_2512_23183_amd/csrc/device_common.h", "paper_2512_23183_amd/csrc/plan.cpp",
-                   "paper_2512_23183_amd/csrc/lower.cpp"]
+                   "paper_2512_23183_amd/csrc/lower.cpp", "paper_2512_23183_amd/csrc/sv_internal.h",
+                   "paper_2512_23183_amd/csrc/tune.cpp"]
 
 
 def traffic_sources_sha():

@@ -126,6 +126,7 @@ __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
         tc.scaled = false;
         tc.base = 0;
         tc.hi_off = nullptr;
+        tc.ltl = nullptr;
         tc.ltabs = ltab;
         tc.Gs = nullptr;
         ladder_split(n, tc.lsa, tc.lsb);

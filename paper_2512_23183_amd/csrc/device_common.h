@@ -106,15 +106,29 @@ inline std::vector<int> bits_of(uint64_t m) {
 // up to three mixing gates and any number of diagonal ones.
 // ---------------------------------------------------------------------------
 
+// Pointers into LDS, typed so that reads through them compile to LDS
+// instructions (a generic pointer gives flat loads, which also wait on the
+// vector-memory counter of every global access still in flight).
+#define SV_LDS __attribute__((address_space(3)))
+
+template <typename R>
+__device__ __forceinline__ V2<R> lds_v2(const SV_LDS R *p, uint32_t i) {
+    V2<R> v;
+    v.x = p[2 * i];
+    v.y = p[2 * i + 1];
+    return v;
+}
+
 template <typename R>
 struct TileCtx {
     int m, l;
     uint32_t lowm;
     bool ident;               // global index == local index
     uint64_t base;            // global bits fixed for this tile
-    const uint64_t *hi_off;   // LDS: global offset of the high local bits
-    const V2<R> *ltabs;       // ladder phase tables (LDS copy or global)
-    const V2<R> *Gs;          // per-tile ladder factors by op.tslot (LDS), null = 1
+    const SV_LDS uint64_t *hi_off;  // global offset of the high local bits
+    const SV_LDS R *ltl;      // ladder phase tables in LDS (re, im pairs), or null:
+    const V2<R> *ltabs;       // then read here (global memory or LDS)
+    const SV_LDS R *Gs;       // per-tile ladder factors by op.tslot (re, im pairs), null = 1
     int lsa, lsb;             // ladder table split of the local bits
     bool zero;                // first global read synthesises |0...0>
     const uint32_t *paux;     // stage layout-map tables
@@ -455,11 +469,18 @@ __device__ __forceinline__ void rg_bit_scale(Grp<R> &g, const V2<R> r) {
 template <int RA, typename R>
 __device__ __forceinline__ void rg_ladder(Grp<R> &g, const DevOp<R> &op, const TileCtx<R> &tc) {
     if (RA < 0 && !((g.k0 >> op.a) & 1)) return;
-    const V2<R> *T = tc.ltabs + op.tab;
     const uint32_t j = g.j0;
-    V2<R> p = cmul(cmul(T[j & ((1u << tc.lsa) - 1)], T[(1 << tc.lsa) + ((j >> tc.lsa) & ((1u << tc.lsb) - 1))]),
-                   T[(1 << tc.lsa) + (1 << tc.lsb) + (j >> (tc.lsa + tc.lsb))]);
-    if (tc.Gs) p = cmul(p, tc.Gs[op.tslot]);
+    const uint32_t i0 = j & ((1u << tc.lsa) - 1), i1 = (1 << tc.lsa) + ((j >> tc.lsa) & ((1u << tc.lsb) - 1)),
+                   i2 = (1 << tc.lsa) + (1 << tc.lsb) + (j >> (tc.lsa + tc.lsb));
+    V2<R> p;
+    if (tc.ltl) {
+        const SV_LDS R *T = tc.ltl + 2 * op.tab;
+        p = cmul(cmul(lds_v2<R>(T, i0), lds_v2<R>(T, i1)), lds_v2<R>(T, i2));
+    } else {
+        const V2<R> *T = tc.ltabs + op.tab;
+        p = cmul(cmul(T[i0], T[i1]), T[i2]);
+    }
+    if (tc.Gs) p = cmul(p, lds_v2<R>(tc.Gs, op.tslot));
     static_for<0, 8>([&](auto EC) {
         constexpr int e = decltype(EC)::value;
         if constexpr (RA < 0 || (e & (1 << (RA < 0 ? 0 : RA)))) {
@@ -620,10 +641,44 @@ __device__ __forceinline__ void mfma_stage(V2<R> *tile, V2<R> *__restrict__ gpsi
     }
 }
 
+// 16-byte access to two adjacent complex64 amplitudes / one complex128.
+template <typename R> struct Pair;
+template <> struct Pair<float> { using T = float4; };
+template <> struct Pair<double> { using T = double2; };
+__device__ __forceinline__ float2 pair_lo(float4 v) { return make_float2(v.x, v.y); }
+__device__ __forceinline__ float2 pair_hi(float4 v) { return make_float2(v.z, v.w); }
+__device__ __forceinline__ float4 pair_join(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
+// (complex128 never takes the paired path; these only keep it compiling)
+__device__ __forceinline__ double2 pair_lo(double2 v) { return v; }
+__device__ __forceinline__ double2 pair_hi(double2 v) { return v; }
+__device__ __forceinline__ double2 pair_join(double2 a, double2) { return a; }
+
+// Issue the HBM loads of the 8 elements of a group at global index k0 (the
+// offsets of its register bits: G) into d.
+template <typename R>
+__device__ __forceinline__ void load_group(V2<R> (&d)[8], const V2<R> *__restrict__ gpsi, uint64_t k0,
+                                           const uint64_t (&G)[3], bool pairg) {
+    if (pairg) {
+        static_for<0, 4>([&](auto IC) {
+            constexpr int e = 2 * decltype(IC)::value;
+            const typename Pair<R>::T v = *reinterpret_cast<const typename Pair<R>::T *>(gpsi + (k0 | goff<e>(G)));
+            d[e] = pair_lo(v);
+            d[e + 1] = pair_hi(v);
+        });
+    } else {
+        static_for<0, 8>([&](auto EC) {
+            constexpr int e = decltype(EC)::value;
+            d[e] = gpsi[k0 | goff<e>(G)];
+        });
+    }
+}
+
 // One 3-bit stage over the tile.  MODE bit 0: read the groups from global
 // memory (else from the LDS tile); MODE bit 1: write them to global memory
 // (else to the LDS tile).  Each thread handles groups threadIdx.x, +TPB, ...
-// one at a time (holding two at once spills registers).
+// one at a time (holding two at once spills registers; so does holding the
+// next tile's first groups while this one is processed, and at three waves
+// per SIMD that measured 25-70% slower).
 template <typename R, int TPB, int MODE>
 __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
                                           const DevStage &S, const DevOp<R> *__restrict__ ops,
@@ -639,29 +694,27 @@ __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi,
     const uint32_t L[3] = {1u << r0, 1u << r1, 1u << r2};
     const uint64_t G[3] = {gbit(tc, r0), gbit(tc, r1), gbit(tc, r2)};
     const bool perm = S.perm != 0;
-    for (uint32_t it = threadIdx.x; it < nitems; it += TPB) {
+    // complex64 with global bit 0 as register bit r0: elements 2i, 2i + 1
+    // are adjacent in HBM and move as one 16-byte access (in LDS, 16-byte
+    // accesses measured slower)
+    const bool pairg = sizeof(R) == 4 && G[0] == 1ull;
+    auto group = [&](uint32_t it) {
         Grp<R> g;
         g.live = true;
         g.j0 = ins0(ins0(ins0(it, r0), r1), r2);
         g.k0 = gaddr(tc, g.j0);
-        // LDS position of element e: pos0 ^ pd[e] (layout map) or j0 | loff(e)
-        const uint32_t pos0 = perm ? tc.paux[S.perm_tab + (g.j0 & 127u)] ^ tc.paux[S.perm_tab + 128 + (g.j0 >> 7)]
-                                   : g.j0;
-        static_for<0, 8>([&](auto EC) {
-            constexpr int e = decltype(EC)::value;
-            if constexpr (MODE & 1) {
-                if (tc.zero) {
-                    V2<R> z;
-                    z.x = (g.k0 | goff<e>(G)) == 0 ? (R)1 : (R)0;
-                    z.y = 0;
-                    el<e>(g) = z;
-                } else {
-                    el<e>(g) = gpsi[g.k0 | goff<e>(G)];
-                }
-            } else {
-                el<e>(g) = tile[perm ? pos0 ^ (uint32_t)S.pd[e] : pos0 | loff<e>(L)];
-            }
-        });
+        return g;
+    };
+    // LDS position of element e: pos0 ^ pd[e] (layout map) or j0 | loff(e)
+    auto lpos0 = [&](const Grp<R> &g) {
+        return perm ? tc.paux[S.perm_tab + (g.j0 & 127u)] ^ tc.paux[S.perm_tab + 128 + (g.j0 >> 7)] : g.j0;
+    };
+    auto lpos = [&](uint32_t pos0, auto EC) {
+        constexpr int e = decltype(EC)::value;
+        return perm ? pos0 ^ (uint32_t)S.pd[e] : pos0 | loff<e>(L);
+    };
+    // the stage's ops, the pass scale on a store to HBM, the store
+    auto finish = [&](Grp<R> &g, uint32_t pos0) {
         stage_ops<R>(g, tc, S, L, G, ops, ovr_index, ovr);
         if constexpr (MODE & 2) {
             if (tc.scaled) {
@@ -671,20 +724,54 @@ __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi,
                     el<e>(g).y *= tc.scale;
                 });
             }
+            if (pairg) {
+                static_for<0, 4>([&](auto IC) {
+                    constexpr int e = 2 * decltype(IC)::value;
+                    *reinterpret_cast<typename Pair<R>::T *>(gpsi + (g.k0 | goff<e>(G))) =
+                        pair_join(el<e>(g), el<e + 1>(g));
+                });
+            } else {
+                static_for<0, 8>([&](auto EC) {
+                    constexpr int e = decltype(EC)::value;
+                    gpsi[g.k0 | goff<e>(G)] = el<e>(g);
+                });
+            }
+        } else {
+            static_for<0, 8>([&](auto EC) {
+                constexpr int e = decltype(EC)::value;
+                tile[lpos(pos0, EC)] = el<e>(g);
+            });
         }
-        static_for<0, 8>([&](auto EC) {
-            constexpr int e = decltype(EC)::value;
-            if constexpr (MODE & 2) gpsi[g.k0 | goff<e>(G)] = el<e>(g);
-            else tile[perm ? pos0 ^ (uint32_t)S.pd[e] : pos0 | loff<e>(L)] = el<e>(g);
-        });
+    };
+    for (uint32_t it = threadIdx.x; it < nitems; it += TPB) {
+        Grp<R> g = group(it);
+        const uint32_t pos0 = lpos0(g);
+        if constexpr (MODE & 1) {
+            if (tc.zero) {
+                static_for<0, 8>([&](auto EC) {
+                    constexpr int e = decltype(EC)::value;
+                    V2<R> z;
+                    z.x = (g.k0 | goff<e>(G)) == 0 ? (R)1 : (R)0;
+                    z.y = 0;
+                    el<e>(g) = z;
+                });
+            } else {
+                V2<R> d[8];
+                load_group<R>(d, gpsi, g.k0, G, pairg);
+                static_for<0, 8>([&](auto EC) {
+                    constexpr int e = decltype(EC)::value;
+                    el<e>(g) = d[e];
+                });
+            }
+        } else {
+            static_for<0, 8>([&](auto EC) {
+                constexpr int e = decltype(EC)::value;
+                el<e>(g) = tile[lpos(pos0, EC)];
+            });
+        }
+        finish(g, pos0);
     }
 }
-
-// 16-byte access to two adjacent complex64 amplitudes / one complex128.
-template <typename R> struct Pair;
-template <> struct Pair<float> { using T = float4; };
-template <> struct Pair<double> { using T = double2; };
-__device__ __forceinline__ float4 pack_pair(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
 
 // Run stages [sb, se) of a tile.  With gpsi: a one-stage pass streams
 // HBM -> registers -> HBM; in a multi-stage pass the first stage reads its

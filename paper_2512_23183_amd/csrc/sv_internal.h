@@ -140,7 +140,7 @@ struct Pass {
 
 struct PlanOptions {
     int tile_bits = 13;    // m
-    int low_bits = 5;      // l
+    int low_bits = 4;      // l: 128 B (complex64) / 256 B (complex128) contiguous runs
     int perm_bits = 11;    // tile width of permutation passes
     bool fuse = true;      // false: one sweep op per gate
     bool dense4 = false;   // fuse runs of fixed gates on four bits into OP_DENSE4
@@ -249,7 +249,7 @@ struct Ctx {
     // widths in bits, indexed by dtype (0 = complex64, 1 = complex128):
     // gate tile passes, expectation passes, permutation passes
     // (ranges: TILE_MAX / EXPECT_MAX / PERM_MAX below, minimum 6)
-    int tile_bits[2] = {13, 12};
+    int tile_bits[2] = {12, 12};
     int expect_bits[2] = {13, 12};
     int perm_bits[2] = {12, 11};
     bool dense4 = true;  // complex64 circuits: MFMA stages for dense four-qubit runs

@@ -36,14 +36,15 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
     tc.mtab = mtab;
     const uint32_t nhi = 1u << (P.m - P.l);
     uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem);
-    tc.hi_off = hi_off;
+    tc.hi_off = (const SV_LDS uint64_t *)hi_off;
     ladder_split(P.m, tc.lsa, tc.lsb);
     const LdsLayout lay = tile_lds_layout(nhi, P.nlad, P.ltab_count, sizeof(V2<R>));
     V2<R> *Gs = reinterpret_cast<V2<R> *>(smem + lay.gs);
     V2<R> *ltl = reinterpret_cast<V2<R> *>(smem + lay.tabs);
     V2<R> *tile = reinterpret_cast<V2<R> *>(smem + lay.tile);
-    tc.Gs = Gs;
-    tc.ltabs = lay.tabs_in_lds ? ltl : ltab + P.ltab_begin;
+    tc.Gs = (const SV_LDS R *)Gs;
+    tc.ltl = lay.tabs_in_lds ? (const SV_LDS R *)ltl : nullptr;
+    tc.ltabs = ltab + P.ltab_begin;
     for (uint32_t h = threadIdx.x; h < nhi; h += TPB) hi_off[h] = aux[P.hi_begin + h];
     if (lay.tabs_in_lds)
         for (int i = threadIdx.x; i < P.ltab_count; i += TPB) ltl[i] = ltab[P.ltab_begin + i];
