@@ -5,9 +5,15 @@ final swaps; 420 logical gates) applied to a resident 28-qubit complex64
 state with i.i.d. complex Gaussian amplitudes (seed 2).  Metric: amplitude
 updates per second = logical gates x 2^n per step / time.
 
+roofline also carries the measured device-copy ceiling (read + write GB/s
+of a plain 2 GiB copy) and the tile pass's fraction of it.
+
 Extras in the same JSON line (each bounded in time):
+  headline   touched amplitude-updates/s (2^n per H, 2^(n-2) per CP,
+             2^(n-1) per SWAP), permutation pass time, GB/s over all passes
   qft        20/24/28 qubits at complex64 and complex128, fused and one
-             launch per gate, GB/s per pass
+             launch per gate, GB/s per pass (states of at most 256 MiB
+             stay in the Infinity Cache: marked cache_resident)
   grad10     10-qubit complex128 VQE gradient (161 circuits): batched vs one
              circuit at a time
   vqe10      the same ansatz and Hamiltonian minimised by Adam (lr 1e-2, at
@@ -19,6 +25,7 @@ Extras in the same JSON line (each bounded in time):
   deep30     30-qubit complex64 depth-40 U3 + CZ circuit: fused vs unfused
   serving    Poisson stream of mixed requests through the serving queue
              (bounded sample), p50/p99 latency vs a serial loop
+  cpu_oracle_1thread  the oracle QFT at 24 qubits on one host thread
 """
 from __future__ import annotations
 
@@ -26,6 +33,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -39,6 +47,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def qft_touched(n):
+    """Amplitudes a gate-based QFT touches: 2^n per H, 2^(n-2) per CP (one
+    quarter of the index set has both bits set), 2^(n-1) per SWAP."""
+    return n * (1 << n) + n * (n - 1) // 2 * (1 << (n - 2)) + (n // 2) * (1 << (n - 1))
 
 
 def qft_gates(n):
@@ -91,6 +105,7 @@ def bench_qft_headline(ctx, sv, inputs, args):
     st.free()
     return {
         "value": au / dt, "ms_per_step": dt / args.steps * 1e3, "n": n, "gates": G,
+        "touched_au_per_s": qft_touched(n) * float(args.steps) / dt,
         "passes_per_step": (tile_n + perm_n) / args.steps,
         "tile_avg_ms": tile_ms / max(tile_n, 1), "perm_avg_ms": perm_ms / max(perm_n, 1),
         "tile_launches": tile_n, "achieved_gbs": achieved, "S": S,
@@ -123,6 +138,10 @@ def bench_qft_table(ctx, sv, inputs, oracle_mod):
             perm_ms, perm_n, _ = prof["perm"]
             passes = (tile_n + perm_n) / reps
             rec = {"au_per_s": G * float(1 << n) * reps / dt, "ms": dt / reps * 1e3,
+                   "touched_au_per_s": qft_touched(n) * float(reps) / dt,
+                   # a state of at most 256 MiB stays in the Infinity Cache
+                   # between passes: not an HBM roofline measurement
+                   "cache_resident": S <= 256.0 * 2 ** 20,
                    "passes": passes,
                    "gbs_per_pass": 2 * S * (tile_n + perm_n) / ((tile_ms + perm_ms) / 1e3) / 1e9
                    if tile_n + perm_n else None,
@@ -361,6 +380,26 @@ def recorded_traffic():
         return None
 
 
+def copy_ceiling_gbs(nbytes=2 << 30, reps=5):
+    """Read + write GB/s of a plain device-to-device copy of nbytes (torch's
+    copy kernel, HIP events): the practical streaming ceiling beside the
+    8 TB/s peak."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms / 1e3) / 1e9
+
+
 def copy_calibration():
     """A plain streaming kernel of known size (read 1 GiB, write 1 GiB per
     dispatch) whose FETCH_SIZE / WRITE_SIZE scale the counter readings."""
@@ -386,6 +425,22 @@ def cpu_baseline(oracle_mod, inputs):
             "kind": "oracle",
             "sample": f"FP64 oracle gate-by-gate QFT on one {n}-qubit Gaussian state "
                       f"({qft_gates(n)} gates, {dt:.1f} s)"}
+
+
+def cpu_baseline_1thread(n=24):
+    """The same oracle QFT on one host thread (OMP_NUM_THREADS=1, a child
+    process that never touches the GPU), on a smaller state."""
+    code = ("import sys, time; sys.path.insert(0, %r); import oracle; "
+            "from paper_2512_23183_amd import inputs; psi = inputs.gaussian_state(%d, 2); "
+            "t0 = time.perf_counter(); oracle.qft(psi); print(time.perf_counter() - t0)" % (ROOT, n))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return None
+    dt = float(r.stdout.strip().splitlines()[-1])
+    return {"value": qft_gates(n) * float(1 << n) / dt, "unit": "amplitude-updates/s", "cores": 1,
+            "kind": "oracle", "sample": f"FP64 oracle gate-by-gate QFT on one {n}-qubit Gaussian state "
+                                        f"({qft_gates(n)} gates, {dt:.1f} s, one thread)"}
 
 
 def main():
@@ -419,8 +474,12 @@ def main():
     tuned = ctx.autotune(sv.C64, 28, cache)
     log(f"[bench] autotuned widths: {tuned}")
     head = bench_qft_headline(ctx, sv, inputs, args)
-    extras = {}
+    extras = {"headline": {"touched_au_per_s": head["touched_au_per_s"], "perm_avg_ms": head["perm_avg_ms"],
+                           "pass_gbs": head["pass_gbs"]}}
+    copy_gbs = None
     if not args.quick:
+        copy_gbs = copy_ceiling_gbs()
+        log(f"[bench] device copy ceiling: {copy_gbs:.0f} GB/s")
         extras["qft"] = bench_qft_table(ctx, sv, inputs, oracle)
         direct = sv.Context(0, graph_batch=-1, **tuned)
         rec10, _ = bench_grad(ctx, sv, inputs, 10, 4, sv.C128, inputs.xyz_chain(10), 20, 3,
@@ -442,6 +501,8 @@ def main():
         if args.serving > 0:
             extras["serving"] = bench_serving(ctx, sv, inputs, args.serving)
     cpu = cpu_baseline(oracle, inputs) if rank == 0 and not args.skip_cpu else None
+    if cpu is not None and not args.quick:
+        extras["cpu_oracle_1thread"] = cpu_baseline_1thread()
     ctx.close()
     frac = head["achieved_gbs"] / HBM_PEAK_GBS
     line = {
@@ -454,7 +515,9 @@ def main():
                    "passes_per_step": head["passes_per_step"], "autotuned_widths": tuned},
         "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": frac, "traffic": recorded_traffic(), "kernel": "k_tile (fused LDS tile pass)",
-                     "bytes_per_launch": 2 * head["S"], "avg_launch_ms": head["tile_avg_ms"]},
+                     "bytes_per_launch": 2 * head["S"], "avg_launch_ms": head["tile_avg_ms"],
+                     "copy_ceiling_gbs": copy_gbs,
+                     "frac_of_copy_ceiling": head["achieved_gbs"] / copy_gbs if copy_gbs else None},
         "cpu_baseline": cpu,
         "extras": extras,
     }

@@ -59,6 +59,28 @@ def test_queue_matches_oracle_and_is_mix_invariant(ctx, sv):
         assert m[2] >= 0.0
 
 
+def test_queue_200_request_sample_matches_oracle(ctx):
+    # a seeded sample of 200 requests of the serving mix (qubit counts kept
+    # at 8..10 so the oracle finishes in seconds), submitted at once to a
+    # queue whose budget forces continuous batching; every result against
+    # the oracle (complex128: 1e-10)
+    reqs = I.serving_requests(200, 5, rate_per_s=0.0, n_range=(8, 10), depth_range=(2, 4),
+                              terms_range=(20, 60))
+    q = ctx.queue(8 << 20)
+    tickets = [q.submit(r.circuit, r.params, r.hamiltonian, r.grad, C128) for r in reqs]
+    got = [q.wait(t, 120000) for t in tickets]
+    st = q.stats()
+    q.close()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    for r, (e, g, _) in zip(reqs, got):
+        if r.grad:
+            e_ref, g_ref = oracle.param_shift(r.circuit, r.params, r.hamiltonian)
+            assert np.max(np.abs(g - g_ref)) <= 1e-10, r.rid
+        else:
+            e_ref = oracle.circuit_energy(r.circuit, r.params, r.hamiltonian)
+        assert abs(e - e_ref) <= 1e-10, r.rid
+
+
 def test_queue_c64_tolerance(ctx):
     reqs = _requests()[:8]
     q = ctx.queue(1 << 30)
