@@ -436,6 +436,12 @@ void run_large_batched(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &
         std::map<int, int> dop_of_gate;
         for (size_t i = 0; i < G->h.gate.size(); ++i)
             if (G->h.gate[i] >= 0) dop_of_gate[G->h.gate[i]] = (int)i;
+        // tile pass holding each plan op
+        std::vector<int> pass_of_op(G->h.dops.size(), -1);
+        for (size_t i = 0; i < G->plan.passes.size(); ++i)
+            if (G->plan.passes[i].kind == PASS_TILE)
+                for (int o = G->h.dpass[i].op_begin; o < G->h.dpass[i].op_end; ++o) pass_of_op[o] = (int)i;
+        const int npass = (int)G->plan.passes.size();
         const std::vector<int> &cs = G->cs;
         const uint64_t dim = 1ull << G->plan.n;
         for (size_t c0 = 0; c0 < cs.size(); c0 += G->chunk) {
@@ -466,8 +472,54 @@ void run_large_batched(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &
                 o.gcmask = bp.gcmask;
                 o.lmask = bp.lmask;
                 o.flags = (o.flags & ~OPF_PLACEMENT) | (bp.flags & OPF_PLACEMENT);
+                // the scale of its pass with o in place of the base op, in
+                // the order build_dev_plan multiplies the factors
+                o.pscale = 1.0;
+                const int pi = pass_of_op[it->second];
+                if (pi >= 0)
+                    for (int q = G->h.dpass[pi].op_begin; q < G->h.dpass[pi].op_end; ++q) {
+                        const DevOp<R> &oq = q == it->second ? o : G->h.dops[q];
+                        if (oq.flags & OPF_SCALED) o.pscale *= oq.sfac;
+                    }
                 ovr[c] = o;
                 oidx[c] = it->second;
+            }
+            // Shared prefixes: every circuit of a group runs the same ops
+            // except its one shifted op, so before the pass that holds that
+            // op its state equals the unshifted circuit's.  With an unshifted
+            // circuit in the chunk, it goes first in the slab and the others
+            // follow by the pass of their shifted op; a circuit joins at that
+            // pass with a copy of the first one's state (bitwise the state it
+            // would have computed itself) and skips the passes before it.
+            std::vector<int> nc_pass;
+            {
+                int ref = -1;
+                for (int c = 0; c < nc && ref < 0; ++c)
+                    if (oidx[c] < 0) ref = c;
+                if (ref >= 0 && npass > 1) {
+                    std::vector<int> start(nc, 0);
+                    for (int c = 0; c < nc; ++c) start[c] = oidx[c] < 0 ? 0 : std::max(0, pass_of_op[oidx[c]]);
+                    std::vector<int> order;
+                    order.reserve(nc);
+                    order.push_back(ref);
+                    for (int c = 0; c < nc; ++c)
+                        if (c != ref) order.push_back(c);
+                    std::stable_sort(order.begin() + 1, order.end(),
+                                     [&](int a, int b) { return start[a] < start[b]; });
+                    std::vector<int> oi2(nc), os2(nc);
+                    std::vector<DevOp<R>> ov2(nc);
+                    for (int k = 0; k < nc; ++k) {
+                        oi2[k] = oidx[order[k]];
+                        os2[k] = oslot[order[k]];
+                        ov2[k] = ovr[order[k]];
+                    }
+                    oidx.swap(oi2);
+                    oslot.swap(os2);
+                    ovr.swap(ov2);
+                    nc_pass.assign(npass, 0);
+                    for (int k = 0; k < nc; ++k)
+                        for (int i = start[order[k]]; i < npass; ++i) ++nc_pass[i];
+                }
             }
             Blob ob;
             const size_t o_oi = ob.add(oidx.data(), nc * 4);
@@ -477,7 +529,7 @@ void run_large_batched(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &
             upload(ctx, obase, ob.host.data(), ob.host.size());
             launch_or_record(ctx, [=] {
                 launch_plan<R>(ctx, G->plan, G->h, d, slab, dim, nc, (const int *)(obase + o_oi),
-                               (const DevOp<R> *)(obase + o_ov), true);
+                               (const DevOp<R> *)(obase + o_ov), true, nc_pass.empty() ? nullptr : nc_pass.data());
                 launch_expect<R>(ctx, G->E, ed, slab, dim, nc, part, (const int *)(obase + o_os), d_E, nullptr);
             });
         }

@@ -996,9 +996,14 @@ inline void launch_tile(Ctx *ctx, int tpb, size_t lds, unsigned grid, V2<R> *sla
 
 template <typename R> DevPlanHost<R> build_dev_plan(const Plan &plan);
 template <typename R> DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const std::string &slot);
+// Run every pass of a plan over a slab of nc states.  nc_pass (host, one
+// count per pass, non-decreasing, last = nc): only states [0, nc_pass[i])
+// take part in pass i; states [nc_pass[i-1], nc_pass[i]) first receive a
+// copy of state 0 (whose ops up to pass i they share).
 template <typename R>
 void launch_plan(Ctx *ctx, const Plan &plan, const DevPlanHost<R> &h, const DevPlanDev<R> &d, V2<R> *slab,
-                 uint64_t dim, int nc, const int *ovr_idx, const DevOp<R> *ovr, bool from_zero);
+                 uint64_t dim, int nc, const int *ovr_idx, const DevOp<R> *ovr, bool from_zero,
+                 const int *nc_pass = nullptr);
 
 void upload(Ctx *ctx, void *dst, const void *src, size_t bytes);
 unsigned grid_for(uint64_t items, int tpb, int cu);

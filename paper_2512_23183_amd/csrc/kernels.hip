@@ -935,12 +935,39 @@ template DevPlanDev<double> upload_dev_plan<double>(Ctx *, const DevPlanHost<dou
 // each).  Sweep passes (the plain path) only exist for nc == 1.  With
 // from_zero the first pass synthesises |0...0> instead of reading memory
 // (it must be a tile pass then).
+// Copy state 0 of a slab (dim amplitudes per state) into states [c0, c1):
+// 16-byte accesses, one grid row per destination state.
+template <typename R>
+__global__ void k_bcast(V2<R> *__restrict__ slab, uint64_t dim, int c0) {
+    const uint64_t nacc = dim * sizeof(V2<R>) / 16;
+    const uint4 *src = reinterpret_cast<const uint4 *>(slab);
+    uint4 *dst = reinterpret_cast<uint4 *>(slab + (uint64_t)(c0 + (int)blockIdx.y) * dim);
+    for (uint64_t a = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; a < nacc; a += (uint64_t)gridDim.x * blockDim.x)
+        dst[a] = src[a];
+}
+
 template <typename R>
 void launch_plan(Ctx *ctx, const Plan &plan, const DevPlanHost<R> &h, const DevPlanDev<R> &d, V2<R> *slab,
-                 uint64_t dim, int nc, const int *ovr_idx, const DevOp<R> *ovr, bool from_zero) {
-    const double S = (double)sizeof(V2<R>) * (double)dim * nc;
+                 uint64_t dim, int nc_all, const int *ovr_idx, const DevOp<R> *ovr, bool from_zero,
+                 const int *nc_pass) {
+    int joined = 0;
     for (size_t i = 0; i < plan.passes.size(); ++i) {
         const Pass &ps = plan.passes[i];
+        // circuits [joined, nc) enter at this pass with circuit 0's state
+        const int nc = nc_pass ? nc_pass[i] : nc_all;
+        if (nc_pass && i > 0 && nc > joined) {
+            if ((dim * sizeof(V2<R>)) % 16 != 0) fail(SV_EDEVICE, "internal: state too small to share");
+            const uint64_t nacc = dim * sizeof(V2<R>) / 16;
+            const unsigned gx = (unsigned)std::min<uint64_t>((nacc + 255) / 256, (uint64_t)ctx->cu_count * 8);
+            LaunchScope ls(ctx, "share", 2.0 * (double)sizeof(V2<R>) * (double)dim * (nc - joined));
+            for (int c = joined; c < nc; c += 32768) {  // grid rows (y) per launch
+                const unsigned rows = (unsigned)std::min(nc - c, 32768);
+                hipLaunchKernelGGL((k_bcast<R>), dim3(gx, rows), dim3(256), 0, ctx->stream, slab, dim, c);
+                SV_HIP(hipGetLastError());
+            }
+        }
+        joined = nc;
+        const double S = (double)sizeof(V2<R>) * (double)dim * nc;
         if (ps.kind == PASS_SWEEP) {
             if (nc != 1 || ovr_idx) fail(SV_EDEVICE, "internal: sweep pass in a batched plan");
             sweep_one<R>(ctx, slab, plan.n, ps.ops[0]);
@@ -979,9 +1006,10 @@ void launch_plan(Ctx *ctx, const Plan &plan, const DevPlanHost<R> &h, const DevP
     }
 }
 template void launch_plan<float>(Ctx *, const Plan &, const DevPlanHost<float> &, const DevPlanDev<float> &,
-                                 V2<float> *, uint64_t, int, const int *, const DevOp<float> *, bool);
+                                 V2<float> *, uint64_t, int, const int *, const DevOp<float> *, bool, const int *);
 template void launch_plan<double>(Ctx *, const Plan &, const DevPlanHost<double> &, const DevPlanDev<double> &,
-                                  V2<double> *, uint64_t, int, const int *, const DevOp<double> *, bool);
+                                  V2<double> *, uint64_t, int, const int *, const DevOp<double> *, bool,
+                                  const int *);
 
 template <typename R>
 static void run_plan_t(Ctx *ctx, State *st, const Plan &plan) {

@@ -88,6 +88,8 @@ struct alignas(16) DevOp {
     int32_t flags;    // OPF_* below
     int32_t tab;      // LADDER: offset of its host-built phase tables
     double sfac;      // OPF_HAD / OPF_ROTC / OPF_ROTS: factor taken out
+    double pscale;    // replacement op of a batched circuit: the scale of the
+                      // pass that holds it, with its own factor in its place
     R m[32];          // complex entries as (re, im)
 };
 enum {

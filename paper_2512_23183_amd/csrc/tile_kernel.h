@@ -64,12 +64,10 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
             __syncthreads();
         }
         const int oi = ovr_idx ? ovr_idx[c] : -1;
-        // pass scale of this circuit: a shifted op of the pass brings its own factor
-        double sc = P.scale;
-        if (oi >= P.op_begin && oi < P.op_end) {
-            if (ops[oi].flags & OPF_SCALED) sc /= ops[oi].sfac;
-            if (ovr[c].flags & OPF_SCALED) sc *= ovr[c].sfac;
-        }
+        // pass scale of this circuit: with its shifted op in this pass, the
+        // product of the pass's factors taken with the shifted op's own
+        // (formed on the host in op order, as for a one-circuit plan)
+        const double sc = (oi >= P.op_begin && oi < P.op_end) ? ovr[c].pscale : P.scale;
         tc.scale = (R)sc;
         tc.scaled = sc != 1.0;
         run_stages<R, TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
