@@ -845,50 +845,93 @@ __device__ __forceinline__ double parity_sign(uint32_t j, uint32_t z) {
     return __hiloint2double((int)((__popc(j & z) << 31) | 0x3ff00000u), 0);
 }
 
-__device__ __forceinline__ uint32_t below_of(uint32_t xl) { return (1u << (31 - __clz(xl))) - 1; }
-
 // One wave's sums over a tile in LDS for CNT terms of one group chunk.
 // MODE 0: diagonal, items = amplitudes j, value |psi_j|^2.  MODE 1/2: items
 // = pairs (j, j ^ xl) with j's top bit of xl clear, value Re/Im conj(b) a.
-// acc[q] += (-1)^popcount(j & zl[q]) value (an exact product); loads of U items are issued
-// before their arithmetic.
+// acc[q] += (-1)^popcount(j & zl[q]) value (exact sign flips).
+//
+// Lane l takes items l, l + 64, l + 128, ... (block k = item / 64).  Item
+// 64k + l sits at j = B(k) + Lj(l) with B(k) a multiple of 64 (of 128 when
+// the pair bit is below 6) common to the wave and Lj(l) < 64 (< 128), so
+// the sign splits into a wave-uniform factor (-1)^popcount(B & z), applied
+// per block, and a lane factor (-1)^popcount(Lj & z), applied once at the
+// end; the partner is (B ^ xhi) + Lp(l).  Blocks go four at a time from a
+// multiple of four, where B(k + u) = B(k) + B(u) with disjoint bits, so the
+// uniform signs of the four come from one parity of B(k) and four per-group
+// constants.  Per pair that leaves two LDS reads, the value and one FMA per
+// term.  Blocks are summed in the order of their items.
 template <typename R, int CNT, int MODE>
-__device__ __forceinline__ void esum(const V2<R> *__restrict__ tile, uint32_t items, uint32_t xl, uint32_t below,
+__device__ __forceinline__ void esum(const V2<R> *__restrict__ tile, uint32_t T, uint32_t xl,
                                      const uint32_t (&zl)[ESUM_CHUNK], double (&acc)[ESUM_CHUNK], uint32_t lane) {
     constexpr int U = 4;
-    auto item = [&](uint32_t it) { return MODE == 0 ? it : (((it & ~below) << 1) | (it & below)); };
     auto value = [&](const V2<R> &a, const V2<R> &b) {
         const double ax = a.x, ay = a.y;
         if (MODE == 0) return ax * ax + ay * ay;
         const double bx = b.x, by = b.y;
         return MODE == 1 ? bx * ax + by * ay : bx * ay - by * ax;
     };
-    uint32_t it = lane;
-    for (; it + 64 * (U - 1) < items; it += 64 * U) {
-        uint32_t j[U];
-        V2<R> a[U], b[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            j[u] = item(it + 64 * u);
-            a[u] = tile[j[u]];
-            if (MODE != 0) b[u] = tile[j[u] ^ xl];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double v = value(a[u], MODE != 0 ? b[u] : a[u]);
-#pragma unroll
-            for (int q = 0; q < CNT; ++q) acc[q] = fma(parity_sign(j[u], zl[q]), v, acc[q]);
+    const uint32_t items = MODE == 0 ? T : T / 2;
+    const int hb = MODE == 0 ? 0 : 31 - __clz(xl);  // the pair bit (top bit of xl)
+    // lane parts of j and of its partner; the partner's block part is B ^ xhi
+    uint32_t Lj = lane, Lp = 0, xhi = 0;
+    if (MODE != 0) {
+        if (hb <= 5) {
+            Lj = ins0(lane, hb);
+            Lp = Lj ^ xl;
+        } else {
+            Lp = lane ^ (xl & 63u);
+            xhi = xl & ~63u;
         }
     }
-    for (; it < items; it += 64) {
-        const uint32_t jj = item(it);
-        const V2<R> a = tile[jj];
-        const double v = value(a, MODE != 0 ? tile[jj ^ xl] : a);
+    // B(k) = 64k (MODE 0), 128k (pair bit below 6), else 64k + (k >> (hb - 6)) 2^hb
+    const bool wide = MODE != 0 && hb >= 6;
+    const uint32_t sh1 = MODE != 0 && hb <= 5 ? 7u : 6u, s2 = wide ? (uint32_t)hb - 6u : 0u,
+                   h2 = wide ? (uint32_t)hb : 0u, m2 = wide ? ~0u : 0u;
+    auto base = [&](uint32_t k) -> uint32_t { return (k << sh1) + (((k >> s2) << h2) & m2); };
+    // high words of +-1.0: sign bit = parity of (B(u) & z), u = 0..3
+    uint32_t shi[CNT][U];
 #pragma unroll
-        for (int q = 0; q < CNT; ++q) acc[q] = fma(parity_sign(jj, zl[q]), v, acc[q]);
+    for (int q = 0; q < CNT; ++q)
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            shi[q][u] = ((uint32_t)__popc(base((uint32_t)u) & zl[q]) << 31) | 0x3ff00000u;
+    double part[CNT];
+#pragma unroll
+    for (int q = 0; q < CNT; ++q) part[q] = 0.0;
+    if (items >= 64 || lane < items) {
+        const uint32_t nblk = items >= 64 ? items / 64 : 1;
+        uint32_t k = 0;
+        for (; k + U <= nblk; k += U) {
+            const uint32_t Bk = base(k);
+            V2<R> a[U], b[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t B = Bk + base((uint32_t)u);
+                a[u] = tile[B + Lj];
+                if (MODE != 0) b[u] = tile[(B ^ xhi) + Lp];
+            }
+            uint32_t flip[CNT];
+#pragma unroll
+            for (int q = 0; q < CNT; ++q) flip[q] = (uint32_t)__popc(Bk & zl[q]) << 31;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double v = value(a[u], MODE != 0 ? b[u] : a[u]);
+#pragma unroll
+                for (int q = 0; q < CNT; ++q)
+                    part[q] = fma(__hiloint2double((int)(shi[q][u] ^ flip[q]), 0), v, part[q]);
+            }
+        }
+        for (; k < nblk; ++k) {
+            const uint32_t Bk = base(k);
+            const V2<R> a = tile[Bk + Lj];
+            const double v = value(a, MODE != 0 ? tile[(Bk ^ xhi) + Lp] : a);
+#pragma unroll
+            for (int q = 0; q < CNT; ++q) part[q] = fma(parity_sign(Bk, zl[q]), v, part[q]);
+        }
     }
+#pragma unroll
+    for (int q = 0; q < CNT; ++q) acc[q] = fma(parity_sign(Lj, zl[q]), part[q], acc[q]);
 }
-
 
 // esum for a chunk of cnt (1..ESUM_CHUNK) terms over a tile of T amplitudes:
 // mode 0 diagonal, 1 / 2 pairs on X/Y support xl using Re / Im.
@@ -898,9 +941,9 @@ __device__ __forceinline__ void esum_dispatch(const V2<R> *__restrict__ tile, ui
                                               double (&acc)[ESUM_CHUNK], uint32_t lane) {
     switch (cnt * 3 + mode) {
 #define SV_ESUM_CASE(C)                                                                            \
-    case C * 3 + 0: esum<R, C, 0>(tile, T, 0u, 0u, zl, acc, lane); break;                          \
-    case C * 3 + 1: esum<R, C, 1>(tile, T / 2, xl, below_of(xl), zl, acc, lane); break;            \
-    case C * 3 + 2: esum<R, C, 2>(tile, T / 2, xl, below_of(xl), zl, acc, lane); break;
+    case C * 3 + 0: esum<R, C, 0>(tile, T, 0u, zl, acc, lane); break;                              \
+    case C * 3 + 1: esum<R, C, 1>(tile, T, xl, zl, acc, lane); break;                              \
+    case C * 3 + 2: esum<R, C, 2>(tile, T, xl, zl, acc, lane); break;
         SV_ESUM_CASE(1)
         SV_ESUM_CASE(2)
         SV_ESUM_CASE(3)
