@@ -190,6 +190,22 @@ def bench_grad(ctx, sv, inputs, n, layers, dtype, ham, reps, seq_reps=1, seq_fla
         rec[f"{name}_ms"] = dts * 1e3
         rec[f"{name}_grads_per_s"] = 1.0 / dts
         rec[f"{name}_max_abs_diff_vs_batched"] = float(np.max(np.abs(g2 - g)))
+    # one more call with per-kernel timing (launched directly): tile passes,
+    # expectation passes and the shared-prefix copies; state_passes counts
+    # (state, tile pass) pairs, each moving 2 x 2^n amplitudes
+    ctx.profile_reset()
+    ctx.profile(True)
+    ctx.param_shift_grad(c, params, ham, dtype)
+    amp = 8 if dtype == sv.C64 else 16
+    for name in ("tile", "expect_tile", "share"):
+        ms, nl, nbytes = ctx.profile_get(name)
+        rec[f"{name}_ms"] = ms
+        rec[f"{name}_launches"] = int(nl)
+        if name == "tile":
+            rec["state_passes"] = nbytes / (2.0 * amp * (1 << n))
+            rec["tile_gbs"] = nbytes / (ms / 1e3) / 1e9 if ms > 0 else None
+    ctx.profile(False)
+    ctx.profile_reset()
     rec["energy"] = e
     return rec, (c, params, e, g)
 
@@ -457,6 +473,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain streaming kernel used to scale HBM byte counters")
+    ap.add_argument("--only", choices=["grad10", "grad20", "vqe10", "trotter", "deep30"],
+                    help="profiling aid: run only this extra (no headline) and print its record")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -477,6 +495,20 @@ def main():
     ctx.autotune(sv.C128, 27, cache)
     tuned = ctx.autotune(sv.C64, 28, cache)
     log(f"[bench] autotuned widths: {tuned}")
+    if args.only:
+        if args.only == "grad10":
+            rec, _ = bench_grad(ctx, sv, inputs, 10, 4, sv.C128, inputs.xyz_chain(10), 20, 3)
+        elif args.only == "grad20":
+            rec, _ = bench_grad(ctx, sv, inputs, 20, 8, sv.C64, inputs.random_2local(20, 200, 3), 2, 1)
+        elif args.only == "vqe10":
+            rec = bench_vqe(ctx, sv, inputs)
+        elif args.only == "trotter":
+            rec = bench_trotter(ctx, sv, inputs)
+        else:
+            rec = bench_deep30(ctx, sv, inputs)
+        ctx.close()
+        print(json.dumps({"only": args.only, "record": rec}), flush=True)
+        return
     head = bench_qft_headline(ctx, sv, inputs, args)
     extras = {"headline": {"touched_au_per_s": head["touched_au_per_s"], "perm_avg_ms": head["perm_avg_ms"],
                            "pass_gbs": head["pass_gbs"]}}
