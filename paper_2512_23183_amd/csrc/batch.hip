@@ -121,6 +121,8 @@ __global__ __launch_bounds__(SMALL_TPB) void k_small_batch(
         tc.ident = true;
         tc.zero = false;
         tc.paux = paux;
+        tc.pauxl = nullptr;
+        tc.paux_off = 0;
         tc.mtab = nullptr;
         tc.scale = (R)1;
         tc.scaled = false;

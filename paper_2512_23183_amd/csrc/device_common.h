@@ -131,7 +131,9 @@ struct TileCtx {
     const SV_LDS R *Gs;       // per-tile ladder factors by op.tslot (re, im pairs), null = 1
     int lsa, lsb;             // ladder table split of the local bits
     bool zero;                // first global read synthesises |0...0>
-    const uint32_t *paux;     // stage layout-map tables
+    const uint32_t *paux;     // stage layout-map tables (memory), or
+    const SV_LDS uint32_t *pauxl;  // their LDS copy (non-null) holding entries from paux_off
+    int paux_off;
     const float *mtab;        // MFMA stage matrices
     R scale;                  // pass scale (OPF_SCALED factors), applied
     bool scaled;              // by the store of the pass's last stage
@@ -153,16 +155,19 @@ __host__ __device__ inline int ladder_entries(int m) {
 // host sizes the launch with the same function.
 constexpr int LTAB_LDS_CAP = 2048;  // ladder table entries kept in LDS
 struct LdsLayout {
-    uint32_t gs, tabs, tile, end;
+    uint32_t gs, tabs, paux, tile, end;
     bool tabs_in_lds;
 };
-__host__ __device__ inline LdsLayout tile_lds_layout(uint32_t nhi, int nlad, int ltab_count, uint32_t amp) {
+// paux_lds: 32-bit layout-map entries copied to LDS (0 = read from memory)
+__host__ __device__ inline LdsLayout tile_lds_layout(uint32_t nhi, int nlad, int ltab_count, uint32_t amp,
+                                                     int paux_lds = 0) {
     auto al = [](uint32_t x) { return (x + 15u) & ~15u; };
     LdsLayout L;
     L.gs = al(8 * nhi);
     L.tabs = L.gs + al(amp * (uint32_t)nlad);
     L.tabs_in_lds = ltab_count <= LTAB_LDS_CAP;
-    L.tile = L.tabs + (L.tabs_in_lds ? al(amp * (uint32_t)ltab_count) : 0u);
+    L.paux = L.tabs + (L.tabs_in_lds ? al(amp * (uint32_t)ltab_count) : 0u);
+    L.tile = L.paux + al(4u * (uint32_t)paux_lds);
     L.end = L.tile;
     return L;
 }
@@ -706,8 +711,13 @@ __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi,
         return g;
     };
     // LDS position of element e: pos0 ^ pd[e] (layout map) or j0 | loff(e)
-    auto lpos0 = [&](const Grp<R> &g) {
-        return perm ? tc.paux[S.perm_tab + (g.j0 & 127u)] ^ tc.paux[S.perm_tab + 128 + (g.j0 >> 7)] : g.j0;
+    auto lpos0 = [&](const Grp<R> &g) -> uint32_t {
+        if (!perm) return g.j0;
+        if (tc.pauxl) {
+            const int t = S.perm_tab - tc.paux_off;
+            return tc.pauxl[t + (g.j0 & 127u)] ^ tc.pauxl[t + 128 + (g.j0 >> 7)];
+        }
+        return tc.paux[S.perm_tab + (g.j0 & 127u)] ^ tc.paux[S.perm_tab + 128 + (g.j0 >> 7)];
     };
     auto lpos = [&](uint32_t pos0, auto EC) {
         constexpr int e = decltype(EC)::value;

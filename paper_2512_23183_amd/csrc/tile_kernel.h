@@ -38,7 +38,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
     uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem);
     tc.hi_off = (const SV_LDS uint64_t *)hi_off;
     ladder_split(P.m, tc.lsa, tc.lsb);
-    const LdsLayout lay = tile_lds_layout(nhi, P.nlad, P.ltab_count, sizeof(V2<R>));
+    const LdsLayout lay = tile_lds_layout(nhi, P.nlad, P.ltab_count, sizeof(V2<R>), P.paux_lds ? P.paux_count : 0);
     V2<R> *Gs = reinterpret_cast<V2<R> *>(smem + lay.gs);
     V2<R> *ltl = reinterpret_cast<V2<R> *>(smem + lay.tabs);
     V2<R> *tile = reinterpret_cast<V2<R> *>(smem + lay.tile);
@@ -48,6 +48,14 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
     for (uint32_t h = threadIdx.x; h < nhi; h += TPB) hi_off[h] = aux[P.hi_begin + h];
     if (lay.tabs_in_lds)
         for (int i = threadIdx.x; i < P.ltab_count; i += TPB) ltl[i] = ltab[P.ltab_begin + i];
+    tc.pauxl = nullptr;
+    tc.paux_off = 0;
+    if (P.paux_lds) {
+        uint32_t *pl = reinterpret_cast<uint32_t *>(smem + lay.paux);
+        for (int i = threadIdx.x; i < P.paux_count; i += TPB) pl[i] = aux32[P.paux_begin + i];
+        tc.pauxl = (const SV_LDS uint32_t *)pl;
+        tc.paux_off = P.paux_begin;
+    }
     const uint64_t fmask = P.free_mask;
     const int sb = P.stage_begin, se = P.stage_end;
     __syncthreads();
