@@ -71,3 +71,21 @@ def test_shared_prefix_with_controlled_rotations(sv):
     e_ref, g_ref = oracle.param_shift(c, params, ham)
     assert abs(e_b - e_ref) <= 1e-10
     assert np.max(np.abs(g_b - g_ref)) <= 1e-10
+
+
+def test_shared_prefix_over_several_slab_chunks(sv):
+    # 24 qubits complex64: 193 circuits of 128 MiB exceed one 16 GiB slab, so
+    # the batch runs in two chunks (the unshifted circuit, and with it the
+    # prefix sharing, in the first); bitwise equal to one circuit at a time,
+    # and the energy against the oracle
+    n = 24
+    c = I.hea_circuit(n, 2)
+    ham = I.random_2local(n, 20, 29)
+    params = I.uniform_params(c.n_params, 31)
+    assert 2 * c.n_params + 1 > (16 << 30) // (8 << n)
+    with sv.Context(0) as ctx:
+        e_b, g_b = ctx.param_shift_grad(c, params, ham, C64)
+        e_s, g_s = ctx.param_shift_grad(c, params, ham, C64, flags=sv.FLAG_SEQUENTIAL)
+    assert e_b == e_s
+    assert np.array_equal(g_b, g_s), np.max(np.abs(g_b - g_s))
+    assert abs(e_b - oracle.circuit_energy(c, params, ham)) <= 1e-5
