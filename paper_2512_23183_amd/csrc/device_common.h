@@ -1028,7 +1028,7 @@ struct DevPlanDev {
 // Tile-pass launch with TPB threads per workgroup (tile_t<TPB>.hip).
 template <typename R, int TPB>
 void launch_tile_tpb(Ctx *ctx, size_t lds, unsigned grid, V2<R> *slab, uint64_t dim, int nc, const int *ovr_idx,
-                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero);
+                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero, bool h4);
 
 // Workgroup size of a tile pass of m local bits: two 8-amplitude groups per
 // thread per stage (measured fastest at every width: more independent
@@ -1038,12 +1038,12 @@ inline int tile_tpb(int m) { return std::max(64, std::min(512, 1 << std::max(0, 
 template <typename R>
 inline void launch_tile(Ctx *ctx, int tpb, size_t lds, unsigned grid, V2<R> *slab, uint64_t dim, int nc,
                         const int *ovr_idx, const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles,
-                        bool from_zero) {
+                        bool from_zero, bool h4) {
     switch (tpb) {
-    case 64: launch_tile_tpb<R, 64>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero); break;
-    case 128: launch_tile_tpb<R, 128>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero); break;
-    case 256: launch_tile_tpb<R, 256>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero); break;
-    default: launch_tile_tpb<R, 512>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero); break;
+    case 64: launch_tile_tpb<R, 64>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4); break;
+    case 128: launch_tile_tpb<R, 128>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4); break;
+    case 256: launch_tile_tpb<R, 256>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4); break;
+    default: launch_tile_tpb<R, 512>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4); break;
     }
 }
 
@@ -1175,6 +1175,78 @@ inline void localise(DevOp<R> &d, const std::vector<int> &local_bits) {
 // stage without ops realises the layout (it must then write to global
 // memory: folding needs final_to_global).  Fills ra / rb / tslot of every
 // op that stays in a stage.
+// Four-bit stages for a pass of Hadamards, ladders and all-ones-pattern
+// diagonals only (h4_eligible): a stage takes ops in order until a fifth
+// distinct Hadamard bit would be needed; its register bits are those
+// Hadamard bits, padded with the highest other local bits.  A ladder gets
+// its register slot (or -1) and, in complex slots 0..15 of m, the phase of
+// each element's register-bit offset.
+template <typename R>
+inline bool h4_eligible(const std::vector<DevOp<R>> &ops, int ob, int oe, int m) {
+    if (m < 6 || m > 16 || oe <= ob) return false;
+    for (int o = ob; o < oe; ++o) {
+        const DevOp<R> &d = ops[o];
+        const bool had = d.kind == OP_U1 && (d.flags & OPF_HAD) && d.cmask == 0;
+        const bool pat = d.kind == OP_DIAG && (d.flags & OPF_PAT);
+        if (!had && !pat && d.kind != OP_LADDER) return false;
+    }
+    return true;
+}
+
+template <typename R>
+inline void build_stages_h4(std::vector<DevOp<R>> &ops, int ob, int oe, const std::vector<int> &local_bits,
+                            std::vector<DevStage> &out) {
+    const int m = (int)local_bits.size();
+    int start = ob;
+    std::vector<int> regs;
+    auto close = [&](int end) {
+        if (end <= start) return;
+        for (int b = m - 1; b >= 0 && (int)regs.size() < 4; --b)
+            if (std::find(regs.begin(), regs.end(), b) == regs.end()) regs.push_back(b);
+        std::sort(regs.begin(), regs.end());
+        DevStage S;
+        std::memset(&S, 0, sizeof S);
+        S.r0 = regs[0];
+        S.r1 = regs[1];
+        S.r2 = regs[2];
+        S.r3 = regs[3];
+        S.op_begin = start;
+        S.op_end = end;
+        auto slot = [&](int lb) {
+            const auto it = std::find(regs.begin(), regs.end(), lb);
+            return it == regs.end() ? -1 : (int)(it - regs.begin());
+        };
+        for (int o = start; o < end; ++o) {
+            DevOp<R> &d = ops[o];
+            d.flags &= ~OPF_PLACEMENT;
+            if (d.kind == OP_U1) {
+                d.ra = slot(d.la);
+                if (d.ra < 0) fail(SV_EDEVICE, "internal: Hadamard bit outside its stage");
+            } else if (d.kind == OP_LADDER) {
+                d.ra = d.la >= 0 ? slot(d.la) : -1;
+                for (int e = 0; e < 16; ++e) {
+                    uint32_t lo = 0;
+                    for (int i = 0; i < 4; ++i)
+                        if ((e >> i) & 1) lo |= 1u << regs[i];
+                    const V2<R> k = host_phase<R>(d.turns, local_offset(lo, local_bits) & d.lmask);
+                    d.m[2 * e] = k.x;
+                    d.m[2 * e + 1] = k.y;
+                }
+            }
+        }
+        out.push_back(S);
+        start = end;
+        regs.clear();
+    };
+    for (int o = ob; o < oe; ++o) {
+        const DevOp<R> &d = ops[o];
+        if (d.kind != OP_U1 || std::find(regs.begin(), regs.end(), d.la) != regs.end()) continue;
+        if ((int)regs.size() == 4) close(o);
+        regs.push_back(d.la);
+    }
+    close(oe);
+}
+
 template <typename R>
 inline void build_stages(std::vector<DevOp<R>> &ops, int ob, int oe, const std::vector<int> &local_bits,
                          std::vector<DevStage> &out, std::vector<uint32_t> &aux32, bool final_to_global) {

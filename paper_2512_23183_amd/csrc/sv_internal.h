@@ -195,7 +195,8 @@ struct alignas(16) DevPass {
     int32_t lad_list, nlad;    // TILE: ladder ops (indices in the 32-bit aux array)
     int32_t ltab_begin, ltab_count;  // TILE: their phase tables in the plan's table array
     int32_t paux_begin, paux_count;  // TILE: its stages' layout-map tables (32-bit aux array)
-    int32_t paux_lds, pad2;          // TILE: 1 = those tables are copied to LDS
+    int32_t paux_lds;                // TILE: 1 = those tables are copied to LDS
+    int32_t h4;                      // TILE: four-bit Hadamard / ladder stages
 };
 
 // ---------------------------------------------------------------------------

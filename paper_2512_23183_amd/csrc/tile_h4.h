@@ -1,0 +1,192 @@
+// Tile passes made only of Hadamards, ladders (merged controlled-phase runs)
+// and all-ones-pattern diagonals (a lone CP or CZ): the passes of the
+// gate-based QFT (Alg. "Gate-Based QFT").  The stages hold four register
+// bits (16 amplitudes per thread) instead of three, so a pass of h
+// Hadamards takes ceil(h / 4) stages and ceil(h / 4) - 1 LDS round trips,
+// and the op loop knows only these three kinds.
+#pragma once
+#include "device_common.h"
+
+namespace sv {
+
+template <int E>
+__device__ __forceinline__ uint32_t loff4(const uint32_t (&L)[4]) {
+    return ((E & 1) ? L[0] : 0u) | ((E & 2) ? L[1] : 0u) | ((E & 4) ? L[2] : 0u) | ((E & 8) ? L[3] : 0u);
+}
+template <int E>
+__device__ __forceinline__ uint64_t goff4(const uint64_t (&G)[4]) {
+    return ((E & 1) ? G[0] : 0ull) | ((E & 2) ? G[1] : 0ull) | ((E & 4) ? G[2] : 0ull) | ((E & 8) ? G[3] : 0ull);
+}
+
+// Sums and differences on register slot I (the 1/sqrt 2 goes to the pass
+// scale, as in the three-bit engine).
+template <int I, typename R>
+__device__ __forceinline__ void h4_had(V2<R> (&v)[16]) {
+    static_for<0, 16>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        if constexpr (!(e & (1 << I))) {
+            const V2<R> a = v[e], b = v[e | (1 << I)];
+            v[e].x = a.x + b.x;
+            v[e].y = a.y + b.y;
+            v[e | (1 << I)].x = a.x - b.x;
+            v[e | (1 << I)].y = a.y - b.y;
+        }
+    });
+}
+
+// Ladder: where bit a is set, multiply by exp(2 pi i turns (k & lmask)) =
+// (group phase from the tile-independent tables and the tile factor) x K_e
+// (the phase of element e's register-bit offset, complex slot e of op.m).
+// RA: register slot of a, or -1 when a is the same for the whole group.
+template <int RA, typename R>
+__device__ __forceinline__ void h4_ladder(V2<R> (&v)[16], uint32_t j0, uint64_t k0, const DevOp<R> &op,
+                                          const TileCtx<R> &tc) {
+    if (RA < 0 && !((k0 >> op.a) & 1)) return;
+    const uint32_t i0 = j0 & ((1u << tc.lsa) - 1), i1 = (1 << tc.lsa) + ((j0 >> tc.lsa) & ((1u << tc.lsb) - 1)),
+                   i2 = (1 << tc.lsa) + (1 << tc.lsb) + (j0 >> (tc.lsa + tc.lsb));
+    V2<R> p;
+    if (tc.ltl) {
+        const SV_LDS R *T = tc.ltl + 2 * op.tab;
+        p = cmul(cmul(lds_v2<R>(T, i0), lds_v2<R>(T, i1)), lds_v2<R>(T, i2));
+    } else {
+        const V2<R> *T = tc.ltabs + op.tab;
+        p = cmul(cmul(T[i0], T[i1]), T[i2]);
+    }
+    if (tc.Gs) p = cmul(p, lds_v2<R>(tc.Gs, op.tslot));
+    static_for<0, 16>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        if constexpr (RA < 0 || (e & (1 << (RA < 0 ? 0 : RA)))) v[e] = cmul(v[e], cmul(p, mat_at(op, e)));
+    });
+}
+
+// Diagonal whose only factor differs from 1 on the all-ones pattern of
+// (controls, a, b): that factor (-1 exactly with NEG) where all are set.
+// The pattern splits into the group's bits (all set in k0, else nothing to
+// do) and the register slots it covers (emask: all set in e).
+template <bool NEG, typename R>
+__device__ __forceinline__ void h4_pat(V2<R> (&v)[16], uint64_t k0, const uint64_t (&G)[4], const DevOp<R> &op) {
+    const uint64_t all = op.cmask | (1ull << op.a) | (op.b >= 0 ? (1ull << op.b) : 0ull);
+    const uint64_t gmask = all & ~(G[0] | G[1] | G[2] | G[3]);
+    if ((k0 & gmask) != gmask) return;
+    const uint32_t emask = ((all & G[0]) ? 1u : 0u) | ((all & G[1]) ? 2u : 0u) | ((all & G[2]) ? 4u : 0u) |
+                           ((all & G[3]) ? 8u : 0u);
+    const V2<R> dl = op.b >= 0 ? mat_at(op, 3) : mat_at(op, 1);
+    static_for<0, 16>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        const bool on = ((uint32_t)e & emask) == emask;
+        if constexpr (NEG) {
+            v[e].x = on ? -v[e].x : v[e].x;
+            v[e].y = on ? -v[e].y : v[e].y;
+        } else {
+            v[e] = vsel(on, cmul(v[e], dl), v[e]);
+        }
+    });
+}
+
+// One four-bit stage.  MODE bit 0: read the groups from global memory (or
+// synthesise |0...0>), else from the LDS tile; MODE bit 1: write them to
+// global memory (scaled by the pass scale), else to the LDS tile.
+template <typename R, int TPB, int MODE>
+__device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
+                                         const DevStage &S, const DevOp<R> *__restrict__ ops, int ovr_index,
+                                         const DevOp<R> *ovr) {
+    const uint32_t nitems = (1u << tc.m) >> 4;
+    const int r[4] = {S.r0, S.r1, S.r2, S.r3};
+    const uint32_t L[4] = {1u << r[0], 1u << r[1], 1u << r[2], 1u << r[3]};
+    const uint64_t G[4] = {gbit(tc, r[0]), gbit(tc, r[1]), gbit(tc, r[2]), gbit(tc, r[3])};
+    // complex64 with global bit 0 as register slot 0: elements 2i, 2i + 1
+    // are adjacent in HBM and move as one 16-byte access
+    const bool pairg = sizeof(R) == 4 && G[0] == 1ull;
+    using P = typename Pair<R>::T;
+    for (uint32_t it = threadIdx.x; it < nitems; it += TPB) {
+        const uint32_t j0 = ins0(ins0(ins0(ins0(it, r[0]), r[1]), r[2]), r[3]);
+        const uint64_t k0 = gaddr(tc, j0);
+        V2<R> v[16];
+        if constexpr (MODE & 1) {
+            if (tc.zero) {
+                static_for<0, 16>([&](auto EC) {
+                    constexpr int e = decltype(EC)::value;
+                    v[e].x = (k0 | goff4<e>(G)) == 0 ? (R)1 : (R)0;
+                    v[e].y = 0;
+                });
+            } else if (pairg) {
+                static_for<0, 8>([&](auto IC) {
+                    constexpr int e = 2 * decltype(IC)::value;
+                    const P w = *reinterpret_cast<const P *>(gpsi + (k0 | goff4<e>(G)));
+                    v[e] = pair_lo(w);
+                    v[e + 1] = pair_hi(w);
+                });
+            } else {
+                static_for<0, 16>([&](auto EC) {
+                    constexpr int e = decltype(EC)::value;
+                    v[e] = gpsi[k0 | goff4<e>(G)];
+                });
+            }
+        } else {
+            static_for<0, 16>([&](auto EC) {
+                constexpr int e = decltype(EC)::value;
+                v[e] = tile[j0 | loff4<e>(L)];
+            });
+        }
+        for (int o = S.op_begin; o < S.op_end; ++o) {
+            const DevOp<R> &op = (o == ovr_index) ? *ovr : ops[o];
+            if (op.kind == OP_U1) {
+                if (op.ra == 0) h4_had<0, R>(v);
+                else if (op.ra == 1) h4_had<1, R>(v);
+                else if (op.ra == 2) h4_had<2, R>(v);
+                else h4_had<3, R>(v);
+            } else if (op.kind == OP_LADDER) {
+                if (op.ra == 0) h4_ladder<0>(v, j0, k0, op, tc);
+                else if (op.ra == 1) h4_ladder<1>(v, j0, k0, op, tc);
+                else if (op.ra == 2) h4_ladder<2>(v, j0, k0, op, tc);
+                else if (op.ra == 3) h4_ladder<3>(v, j0, k0, op, tc);
+                else h4_ladder<-1>(v, j0, k0, op, tc);
+            } else {
+                if (op.flags & OPF_NEG) h4_pat<true>(v, k0, G, op);
+                else h4_pat<false>(v, k0, G, op);
+            }
+        }
+        if constexpr (MODE & 2) {
+            if (tc.scaled) {
+                static_for<0, 16>([&](auto EC) {
+                    constexpr int e = decltype(EC)::value;
+                    v[e].x *= tc.scale;
+                    v[e].y *= tc.scale;
+                });
+            }
+            if (pairg) {
+                static_for<0, 8>([&](auto IC) {
+                    constexpr int e = 2 * decltype(IC)::value;
+                    *reinterpret_cast<P *>(gpsi + (k0 | goff4<e>(G))) = pair_join(v[e], v[e + 1]);
+                });
+            } else {
+                static_for<0, 16>([&](auto EC) {
+                    constexpr int e = decltype(EC)::value;
+                    gpsi[k0 | goff4<e>(G)] = v[e];
+                });
+            }
+        } else {
+            static_for<0, 16>([&](auto EC) {
+                constexpr int e = decltype(EC)::value;
+                tile[j0 | loff4<e>(L)] = v[e];
+            });
+        }
+    }
+}
+
+template <typename R, int TPB>
+__device__ __forceinline__ void run_stages_h4(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
+                                              const DevStage *__restrict__ stages, int sb, int se,
+                                              const DevOp<R> *__restrict__ ops, int ovr_index, const DevOp<R> *ovr) {
+    for (int s = sb; s < se; ++s) {
+        const DevStage &S = stages[s];
+        const bool first = s == sb, last = s == se - 1;
+        if (first && last) h4_stage<R, TPB, 3>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        else if (first) h4_stage<R, TPB, 1>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        else if (last) h4_stage<R, TPB, 2>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        else h4_stage<R, TPB, 0>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        __syncthreads();
+    }
+}
+
+}  // namespace sv

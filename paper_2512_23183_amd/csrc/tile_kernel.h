@@ -1,6 +1,7 @@
 // The tile-pass kernel, instantiated per workgroup size in tile_t*.hip.
 #pragma once
 #include "device_common.h"
+#include "tile_h4.h"
 
 namespace sv {
 
@@ -13,7 +14,8 @@ namespace sv {
 // factors Gs[nlad], the pass's ladder tables when they fit
 // (ltab_count <= LTAB_LDS_CAP; else they are read from global memory), then
 // the tile (2^m amplitudes, only for multi-stage passes).
-template <typename R, int TPB>
+// H4: the pass's stages are four-bit Hadamard / ladder stages (tile_h4.h).
+template <typename R, int TPB, bool H4>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) void k_tile(V2<R> *__restrict__ slab, uint64_t dim, int nc,
                                                    const int *__restrict__ ovr_idx,
                                                    const DevOp<R> *__restrict__ ovr,
@@ -78,26 +80,32 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
         const double sc = (oi >= P.op_begin && oi < P.op_end) ? ovr[c].pscale : P.scale;
         tc.scale = (R)sc;
         tc.scaled = sc != 1.0;
-        run_stages<R, TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
+        if constexpr (H4) run_stages_h4<R, TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
+        else run_stages<R, TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
     }
 }
 
 
 template <typename R, int TPB>
 void launch_tile_tpb(Ctx *ctx, size_t lds, unsigned grid, V2<R> *slab, uint64_t dim, int nc, const int *ovr_idx,
-                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero) {
-    set_lds_limit((const void *)k_tile<R, TPB>, lds);
-    hipLaunchKernelGGL((k_tile<R, TPB>), dim3(grid), dim3(TPB), lds, ctx->stream, slab, dim, nc, ovr_idx, ovr, d.pass,
-                       pidx, d.stages, d.ops, d.aux, d.aux32, d.ltab, d.mtab, tiles, from_zero ? 1 : 0);
+                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero, bool h4) {
+    auto go = [&](auto H) {
+        constexpr bool H4 = decltype(H)::value;
+        set_lds_limit((const void *)k_tile<R, TPB, H4>, lds);
+        hipLaunchKernelGGL((k_tile<R, TPB, H4>), dim3(grid), dim3(TPB), lds, ctx->stream, slab, dim, nc, ovr_idx, ovr,
+                           d.pass, pidx, d.stages, d.ops, d.aux, d.aux32, d.ltab, d.mtab, tiles, from_zero ? 1 : 0);
+    };
+    if (h4) go(std::true_type{});
+    else go(std::false_type{});
     SV_HIP(hipGetLastError());
 }
 
 #define SV_TILE_INSTANTIATE(TPB)                                                                              \
     template void launch_tile_tpb<float, TPB>(Ctx *, size_t, unsigned, V2<float> *, uint64_t, int, const int *, \
                                               const DevOp<float> *, const DevPlanDev<float> &, int, uint64_t,   \
-                                              bool);                                                           \
+                                              bool, bool);                                                     \
     template void launch_tile_tpb<double, TPB>(Ctx *, size_t, unsigned, V2<double> *, uint64_t, int,           \
                                                const int *, const DevOp<double> *, const DevPlanDev<double> &,  \
-                                               int, uint64_t, bool);
+                                               int, uint64_t, bool, bool);
 
 }  // namespace sv
