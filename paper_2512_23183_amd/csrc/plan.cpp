@@ -409,6 +409,7 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
         std::vector<Op> deferred;
         std::vector<OpSets> dsets;
         const uint64_t all = (n >= 64) ? ~0ull : (bit(n) - 1);
+        std::vector<char> taken(rest.size(), 0);
         for (size_t i = 0; i < rest.size(); ++i) {
             const Op &o = rest[i];
             const OpSets &s = rsets[i];
@@ -423,6 +424,7 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
             }
             if (can) {
                 ps.ops.push_back(o);
+                taken[i] = 1;
             } else {
                 deferred.push_back(o);
                 dsets.push_back(s);
@@ -436,6 +438,61 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
                     }
                     break;
                 }
+            }
+        }
+        // A pass of Hadamards and diagonals runs in four-bit stages: when
+        // another pass follows anyway, hand its Hadamards beyond a multiple
+        // of four (and every op taken after the first of them) to the next
+        // pass, where they share stages with that pass's own.
+        if (!deferred.empty()) {
+            auto is_had = [](const Op &o) {
+                return o.kind == OP_U1 && o.cmask == 0 && o.m[0] == o.m[1] && o.m[0] == o.m[2] &&
+                       o.m[3] == -o.m[0] && o.m[0].imag() == 0.0 && o.m[0].real() > 0.0;
+            };
+            bool only = true;
+            std::vector<int> hbits;
+            for (size_t i = 0; i < rest.size() && only; ++i) {
+                if (!taken[i]) continue;
+                const Op &o = rest[i];
+                if (o.kind == OP_U1) {
+                    only = is_had(o);
+                    if (std::find(hbits.begin(), hbits.end(), o.a) == hbits.end()) hbits.push_back(o.a);
+                } else {
+                    only = o.kind == OP_LADDER || o.kind == OP_DIAG;
+                }
+            }
+            const int h = (int)hbits.size(), drop = h % 4;
+            if (only && h > 4 && drop != 0) {
+                const uint64_t dropped = [&] {
+                    uint64_t d = 0;
+                    for (int k = h - drop; k < h; ++k) d |= bit(hbits[k]);
+                    return d;
+                }();
+                size_t cut = rest.size();
+                for (size_t i = 0; i < rest.size(); ++i)
+                    if (taken[i] && rest[i].kind == OP_U1 && (bit(rest[i].a) & dropped)) {
+                        cut = i;
+                        break;
+                    }
+                // this pass keeps the ops taken before the cut; the next
+                // passes get the untaken ones and the taken ones from the
+                // cut on, in their original order
+                std::vector<Op> keep_ops, back;
+                std::vector<OpSets> back_sets;
+                for (size_t i = 0; i < rest.size(); ++i) {
+                    if (taken[i] && i < cut) {
+                        keep_ops.push_back(rest[i]);
+                    } else {
+                        back.push_back(rest[i]);
+                        back_sets.push_back(rsets[i]);
+                    }
+                }
+                ps.ops.swap(keep_ops);
+                deferred.swap(back);
+                dsets.swap(back_sets);
+                S = low;
+                for (const Op &o : ps.ops) S |= sets_of(o).target;
+                nS = __builtin_popcountll(S);
             }
         }
         // pad the tile with the lowest unused bits (longer contiguous runs)
