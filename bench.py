@@ -367,7 +367,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_qft28_c64_traffic.md")
 TRAFFIC_SOURCES = ["paper_2512_23183_amd/csrc/kernels.hip", "paper_2512_23183_amd/csrc/tile_kernel.h",
                    "paper_2512_23183_amd/csrc/device_common.h", "paper_2512_23183_amd/csrc/plan.cpp",
                    "paper_2512_23183_amd/csrc/lower.cpp", "paper_2512_23183_amd/csrc/sv_internal.h",
-                   "paper_2512_23183_amd/csrc/tune.cpp"]
+                   "paper_2512_23183_amd/csrc/tune.cpp", "paper_2512_23183_amd/csrc/tile_h4.h"]
 
 
 def traffic_sources_sha():
@@ -550,7 +550,7 @@ def main():
                    "input": "iid complex Gaussian, normalised (seed 2)",
                    "passes_per_step": head["passes_per_step"], "autotuned_widths": tuned},
         "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": frac, "traffic": recorded_traffic(), "kernel": "k_tile (fused LDS tile pass)",
+                     "frac": frac, "traffic": recorded_traffic(), "kernel": "k_tile (fused LDS tile pass; the QFT's passes in four-bit Hadamard/ladder stages)",
                      "bytes_per_launch": 2 * head["S"], "avg_launch_ms": head["tile_avg_ms"],
                      "copy_ceiling_gbs": copy_gbs, "copy_ceiling_kernel": copy_kernel,
                      "frac_of_copy_ceiling": head["achieved_gbs"] / copy_gbs if copy_gbs else None},
