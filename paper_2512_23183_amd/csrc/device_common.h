@@ -1028,7 +1028,7 @@ struct DevPlanDev {
 // Tile-pass launch with TPB threads per workgroup (tile_t<TPB>.hip).
 template <typename R, int TPB>
 void launch_tile_tpb(Ctx *ctx, size_t lds, unsigned grid, V2<R> *slab, uint64_t dim, int nc, const int *ovr_idx,
-                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero, bool h4);
+                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero, int h4);
 
 // Workgroup size of a tile pass of m local bits: two 8-amplitude groups per
 // thread per stage (measured fastest at every width: more independent
@@ -1038,7 +1038,7 @@ inline int tile_tpb(int m) { return std::max(64, std::min(512, 1 << std::max(0, 
 template <typename R>
 inline void launch_tile(Ctx *ctx, int tpb, size_t lds, unsigned grid, V2<R> *slab, uint64_t dim, int nc,
                         const int *ovr_idx, const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles,
-                        bool from_zero, bool h4) {
+                        bool from_zero, int h4) {
     switch (tpb) {
     case 64: launch_tile_tpb<R, 64>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4); break;
     case 128: launch_tile_tpb<R, 128>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4); break;
@@ -1175,22 +1175,27 @@ inline void localise(DevOp<R> &d, const std::vector<int> &local_bits) {
 // stage without ops realises the layout (it must then write to global
 // memory: folding needs final_to_global).  Fills ra / rb / tslot of every
 // op that stays in a stage.
-// Four-bit stages for a pass of Hadamards, ladders and all-ones-pattern
-// diagonals only (h4_eligible): a stage takes ops in order until a fifth
-// distinct Hadamard bit would be needed; its register bits are those
-// Hadamard bits, padded with the highest other local bits.  A ladder gets
+// Four-bit stages for a pass of uncontrolled one-qubit gates, ladders and
+// diagonals only (h4_kind): a stage takes ops in order until a fifth
+// distinct gate bit would be needed; its register bits are those gate
+// bits, padded with the highest other local bits.  A ladder gets
 // its register slot (or -1) and, in complex slots 0..15 of m, the phase of
 // each element's register-bit offset.
+// 0: not eligible; 1: general four-bit stages; 2: Hadamards, ladders and
+// all-ones-pattern diagonals only (the QFT's passes, a smaller kernel).
 template <typename R>
-inline bool h4_eligible(const std::vector<DevOp<R>> &ops, int ob, int oe, int m) {
-    if (m < 6 || m > 16 || oe <= ob) return false;
+inline int h4_kind(const std::vector<DevOp<R>> &ops, int ob, int oe, int m) {
+    if (m < 6 || m > 16 || oe <= ob) return 0;
+    bool qft = true;
     for (int o = ob; o < oe; ++o) {
         const DevOp<R> &d = ops[o];
-        const bool had = d.kind == OP_U1 && (d.flags & OPF_HAD) && d.cmask == 0;
-        const bool pat = d.kind == OP_DIAG && (d.flags & OPF_PAT);
-        if (!had && !pat && d.kind != OP_LADDER) return false;
+        const bool mix = (d.kind == OP_U1 || d.kind == OP_XPERM) && d.cmask == 0;
+        if (!mix && d.kind != OP_DIAG && d.kind != OP_LADDER) return 0;
+        if ((d.kind == OP_U1 && !(d.flags & OPF_HAD)) || d.kind == OP_XPERM ||
+            (d.kind == OP_DIAG && !(d.flags & OPF_PAT)))
+            qft = false;
     }
-    return true;
+    return qft ? 2 : 1;
 }
 
 template <typename R>
@@ -1219,9 +1224,9 @@ inline void build_stages_h4(std::vector<DevOp<R>> &ops, int ob, int oe, const st
         for (int o = start; o < end; ++o) {
             DevOp<R> &d = ops[o];
             d.flags &= ~OPF_PLACEMENT;
-            if (d.kind == OP_U1) {
+            if (d.kind == OP_U1 || d.kind == OP_XPERM) {
                 d.ra = slot(d.la);
-                if (d.ra < 0) fail(SV_EDEVICE, "internal: Hadamard bit outside its stage");
+                if (d.ra < 0) fail(SV_EDEVICE, "internal: gate bit outside its stage");
             } else if (d.kind == OP_LADDER) {
                 d.ra = d.la >= 0 ? slot(d.la) : -1;
                 for (int e = 0; e < 16; ++e) {
@@ -1240,7 +1245,8 @@ inline void build_stages_h4(std::vector<DevOp<R>> &ops, int ob, int oe, const st
     };
     for (int o = ob; o < oe; ++o) {
         const DevOp<R> &d = ops[o];
-        if (d.kind != OP_U1 || std::find(regs.begin(), regs.end(), d.la) != regs.end()) continue;
+        if ((d.kind != OP_U1 && d.kind != OP_XPERM) || std::find(regs.begin(), regs.end(), d.la) != regs.end())
+            continue;
         if ((int)regs.size() == 4) close(o);
         regs.push_back(d.la);
     }

@@ -886,8 +886,9 @@ DevPlanHost<R> build_dev_plan(const Plan &plan) {
             if (h.dops[i].flags & OPF_SCALED) dp.scale *= h.dops[i].sfac;
         dp.stage_begin = (int)h.dstages.size();
         dp.paux_begin = (int)h.aux32.size();
-        // passes of Hadamards and ladders only (the QFT's) take four-bit stages
-        dp.h4 = ps.kind == PASS_TILE && h4_eligible<R>(h.dops, b, (int)h.dops.size(), ps.m) ? 1 : 0;
+        // passes of uncontrolled one-qubit gates, ladders and diagonals take
+        // four-bit stages
+        dp.h4 = ps.kind == PASS_TILE ? h4_kind<R>(h.dops, b, (int)h.dops.size(), ps.m) : 0;
         if (dp.h4) build_stages_h4<R>(h.dops, b, (int)h.dops.size(), ps.local_bits, h.dstages);
         else if (ps.kind == PASS_TILE)
             build_stages<R>(h.dops, b, (int)h.dops.size(), ps.local_bits, h.dstages, h.aux32, true);
@@ -996,7 +997,7 @@ void launch_plan(Ctx *ctx, const Plan &plan, const DevPlanHost<R> &h, const DevP
             if (dp.stage_end - dp.stage_begin > 1) lds += sizeof(V2<R>) << ps.m;
             LaunchScope ls(ctx, "tile", 2.0 * S);
             launch_tile<R>(ctx, tile_tpb(ps.m), lds, grid, slab, dim, nc, ovr_idx, ovr, d, (int)i, tiles,
-                           from_zero && i == 0, dp.h4 != 0);
+                           from_zero && i == 0, dp.h4);
         } else {
             if (from_zero && i == 0) fail(SV_EDEVICE, "internal: plan starts with a permutation");
             // k_perm moves at most 4 accesses per thread per tile

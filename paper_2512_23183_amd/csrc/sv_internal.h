@@ -196,7 +196,7 @@ struct alignas(16) DevPass {
     int32_t ltab_begin, ltab_count;  // TILE: their phase tables in the plan's table array
     int32_t paux_begin, paux_count;  // TILE: its stages' layout-map tables (32-bit aux array)
     int32_t paux_lds;                // TILE: 1 = those tables are copied to LDS
-    int32_t h4;                      // TILE: four-bit Hadamard / ladder stages
+    int32_t h4;                      // TILE: four-bit stages (1 general, 2 Hadamard / ladder only)
 };
 
 // ---------------------------------------------------------------------------

@@ -1,9 +1,9 @@
-// Tile passes made only of Hadamards, ladders (merged controlled-phase runs)
-// and all-ones-pattern diagonals (a lone CP or CZ): the passes of the
-// gate-based QFT (Alg. "Gate-Based QFT").  The stages hold four register
-// bits (16 amplitudes per thread) instead of three, so a pass of h
-// Hadamards takes ceil(h / 4) stages and ceil(h / 4) - 1 LDS round trips,
-// and the op loop knows only these three kinds.
+// Tile passes made only of uncontrolled one-qubit gates, ladders (merged
+// controlled-phase runs) and diagonals -- the passes of the gate-based QFT
+// (Alg. "Gate-Based QFT") and of layered random circuits.  The stages hold
+// four register bits (16 amplitudes per thread) instead of three, so a pass
+// of h mixing gates' bits takes ceil(h / 4) stages and ceil(h / 4) - 1 LDS
+// round trips, and the op loop knows only these kinds.
 #pragma once
 #include "device_common.h"
 
@@ -31,6 +31,88 @@ __device__ __forceinline__ void h4_had(V2<R> (&v)[16]) {
             v[e | (1 << I)].x = a.x - b.x;
             v[e | (1 << I)].y = a.y - b.y;
         }
+    });
+}
+
+// Uncontrolled 2x2 on register slot I (an exchange for X).  K as in the
+// three-bit engine: 0 complex matrix, 1 real matrix, 2 exchange, 4 / 5 the
+// scaled rotations (coefficient in entry 5; their factor, like the
+// Hadamard's, is in the pass scale).
+template <int I, int K, typename R>
+__device__ __forceinline__ void h4_u1(V2<R> (&v)[16], const DevOp<R> &op) {
+    const V2<R> m0 = mat_at(op, (K == 4 || K == 5) ? 5 : 0), m1 = mat_at(op, 1), m2 = mat_at(op, 2),
+                m3 = mat_at(op, 3);
+    static_for<0, 16>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        if constexpr (!(e & (1 << I))) {
+            constexpr int f = e | (1 << I);
+            const V2<R> x = v[e], y = v[f];
+            V2<R> nx, ny;
+            if constexpr (K == 2) {
+                nx = y;
+                ny = x;
+            } else if constexpr (K == 1) {
+                nx.x = m0.x * x.x + m1.x * y.x;
+                nx.y = m0.x * x.y + m1.x * y.y;
+                ny.x = m2.x * x.x + m3.x * y.x;
+                ny.y = m2.x * x.y + m3.x * y.y;
+            } else if constexpr (K == 4) {
+                nx.x = x.x - m0.x * y.x;
+                nx.y = x.y - m0.x * y.y;
+                ny.x = m0.x * x.x + y.x;
+                ny.y = m0.x * x.y + y.y;
+            } else if constexpr (K == 5) {
+                nx.x = m0.x * x.x - y.x;
+                nx.y = m0.x * x.y - y.y;
+                ny.x = x.x + m0.x * y.x;
+                ny.y = x.y + m0.x * y.y;
+            } else {
+                nx = cmac2(m0, x, m1, y);
+                ny = cmac2(m2, x, m3, y);
+            }
+            v[e] = nx;
+            v[f] = ny;
+        }
+    });
+}
+
+template <int K, typename R>
+__device__ __forceinline__ void h4_u1_at(V2<R> (&v)[16], const DevOp<R> &op) {
+    if (op.ra == 0) h4_u1<0, K, R>(v, op);
+    else if (op.ra == 1) h4_u1<1, K, R>(v, op);
+    else if (op.ra == 2) h4_u1<2, K, R>(v, op);
+    else h4_u1<3, K, R>(v, op);
+}
+
+// Diagonal amplitude *= d[2 bit_a + bit_b] (d[bit_a] without b) where all
+// control bits are set; each of a, b and the controls is a register slot
+// (taken from e) or a bit of the group (taken from k0).
+template <typename R>
+__device__ __forceinline__ void h4_diag(V2<R> (&v)[16], uint64_t k0, const uint64_t (&G)[4], const DevOp<R> &op) {
+    const uint64_t regs = G[0] | G[1] | G[2] | G[3];
+    const uint64_t gc = op.cmask & ~regs;
+    if ((k0 & gc) != gc) return;
+    const uint32_t ec = ((op.cmask & G[0]) ? 1u : 0u) | ((op.cmask & G[1]) ? 2u : 0u) |
+                        ((op.cmask & G[2]) ? 4u : 0u) | ((op.cmask & G[3]) ? 8u : 0u);
+    auto slot = [&](int bitpos) {
+        const uint64_t m = 1ull << bitpos;
+        return G[0] == m ? 0 : G[1] == m ? 1 : G[2] == m ? 2 : G[3] == m ? 3 : -1;
+    };
+    const int sa = slot(op.a), sb = op.b >= 0 ? slot(op.b) : -1;
+    const uint32_t ga = (uint32_t)((k0 >> op.a) & 1), gb = op.b >= 0 ? (uint32_t)((k0 >> op.b) & 1) : 0u;
+    const V2<R> d0 = mat_at(op, 0), d1 = mat_at(op, 1), d2 = mat_at(op, 2), d3 = mat_at(op, 3);
+    static_for<0, 16>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        const uint32_t ba = sa >= 0 ? ((uint32_t)e >> sa) & 1u : ga;
+        V2<R> f;
+        if (op.b >= 0) {
+            const uint32_t bb = sb >= 0 ? ((uint32_t)e >> sb) & 1u : gb;
+            f = vsel(ba != 0, vsel(bb != 0, d3, d2), vsel(bb != 0, d1, d0));
+        } else {
+            f = vsel(ba != 0, d1, d0);
+        }
+        const bool on = ((uint32_t)e & ec) == ec;
+        v[e] = vsel(on, cmul(v[e], f), v[e]);
     });
 }
 
@@ -86,7 +168,9 @@ __device__ __forceinline__ void h4_pat(V2<R> (&v)[16], uint64_t k0, const uint64
 // One four-bit stage.  MODE bit 0: read the groups from global memory (or
 // synthesise |0...0>), else from the LDS tile; MODE bit 1: write them to
 // global memory (scaled by the pass scale), else to the LDS tile.
-template <typename R, int TPB, int MODE>
+// GEN: any of the kinds above; else Hadamards, ladders and pattern
+// diagonals only (the QFT's passes: a smaller op loop).
+template <typename R, int TPB, int MODE, bool GEN>
 __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
                                          const DevStage &S, const DevOp<R> *__restrict__ ops, int ovr_index,
                                          const DevOp<R> *ovr) {
@@ -131,19 +215,33 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
         for (int o = S.op_begin; o < S.op_end; ++o) {
             const DevOp<R> &op = (o == ovr_index) ? *ovr : ops[o];
             if (op.kind == OP_U1) {
-                if (op.ra == 0) h4_had<0, R>(v);
-                else if (op.ra == 1) h4_had<1, R>(v);
-                else if (op.ra == 2) h4_had<2, R>(v);
-                else h4_had<3, R>(v);
+                if (!GEN || (op.flags & OPF_HAD)) {
+                    if (op.ra == 0) h4_had<0, R>(v);
+                    else if (op.ra == 1) h4_had<1, R>(v);
+                    else if (op.ra == 2) h4_had<2, R>(v);
+                    else h4_had<3, R>(v);
+                } else if (op.flags & OPF_ROTC) {
+                    h4_u1_at<4>(v, op);
+                } else if (op.flags & OPF_ROTS) {
+                    h4_u1_at<5>(v, op);
+                } else if (op.flags & OPF_REAL) {
+                    h4_u1_at<1>(v, op);
+                } else {
+                    h4_u1_at<0>(v, op);
+                }
+            } else if (GEN && op.kind == OP_XPERM) {
+                h4_u1_at<2>(v, op);
             } else if (op.kind == OP_LADDER) {
                 if (op.ra == 0) h4_ladder<0>(v, j0, k0, op, tc);
                 else if (op.ra == 1) h4_ladder<1>(v, j0, k0, op, tc);
                 else if (op.ra == 2) h4_ladder<2>(v, j0, k0, op, tc);
                 else if (op.ra == 3) h4_ladder<3>(v, j0, k0, op, tc);
                 else h4_ladder<-1>(v, j0, k0, op, tc);
-            } else {
+            } else if (!GEN || (op.flags & OPF_PAT)) {
                 if (op.flags & OPF_NEG) h4_pat<true>(v, k0, G, op);
                 else h4_pat<false>(v, k0, G, op);
+            } else {
+                h4_diag(v, k0, G, op);
             }
         }
         if constexpr (MODE & 2) {
@@ -174,17 +272,17 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
     }
 }
 
-template <typename R, int TPB>
+template <typename R, int TPB, bool GEN>
 __device__ __forceinline__ void run_stages_h4(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
                                               const DevStage *__restrict__ stages, int sb, int se,
                                               const DevOp<R> *__restrict__ ops, int ovr_index, const DevOp<R> *ovr) {
     for (int s = sb; s < se; ++s) {
         const DevStage &S = stages[s];
         const bool first = s == sb, last = s == se - 1;
-        if (first && last) h4_stage<R, TPB, 3>(tile, gpsi, tc, S, ops, ovr_index, ovr);
-        else if (first) h4_stage<R, TPB, 1>(tile, gpsi, tc, S, ops, ovr_index, ovr);
-        else if (last) h4_stage<R, TPB, 2>(tile, gpsi, tc, S, ops, ovr_index, ovr);
-        else h4_stage<R, TPB, 0>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        if (first && last) h4_stage<R, TPB, 3, GEN>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        else if (first) h4_stage<R, TPB, 1, GEN>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        else if (last) h4_stage<R, TPB, 2, GEN>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        else h4_stage<R, TPB, 0, GEN>(tile, gpsi, tc, S, ops, ovr_index, ovr);
         __syncthreads();
     }
 }

@@ -14,8 +14,10 @@ namespace sv {
 // factors Gs[nlad], the pass's ladder tables when they fit
 // (ltab_count <= LTAB_LDS_CAP; else they are read from global memory), then
 // the tile (2^m amplitudes, only for multi-stage passes).
-// H4: the pass's stages are four-bit Hadamard / ladder stages (tile_h4.h).
-template <typename R, int TPB, bool H4>
+// H4: 0 = three-bit register stages; four-bit stages (tile_h4.h) with
+// 1 = one-qubit gates, ladders and diagonals, 2 = Hadamards, ladders and
+// pattern diagonals only.
+template <typename R, int TPB, int H4>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) void k_tile(V2<R> *__restrict__ slab, uint64_t dim, int nc,
                                                    const int *__restrict__ ovr_idx,
                                                    const DevOp<R> *__restrict__ ovr,
@@ -80,7 +82,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
         const double sc = (oi >= P.op_begin && oi < P.op_end) ? ovr[c].pscale : P.scale;
         tc.scale = (R)sc;
         tc.scaled = sc != 1.0;
-        if constexpr (H4) run_stages_h4<R, TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
+        if constexpr (H4 != 0)
+            run_stages_h4<R, TPB, H4 == 1>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
         else run_stages<R, TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
     }
 }
@@ -88,24 +91,25 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
 
 template <typename R, int TPB>
 void launch_tile_tpb(Ctx *ctx, size_t lds, unsigned grid, V2<R> *slab, uint64_t dim, int nc, const int *ovr_idx,
-                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero, bool h4) {
+                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero, int h4) {
     auto go = [&](auto H) {
-        constexpr bool H4 = decltype(H)::value;
+        constexpr int H4 = decltype(H)::value;
         set_lds_limit((const void *)k_tile<R, TPB, H4>, lds);
         hipLaunchKernelGGL((k_tile<R, TPB, H4>), dim3(grid), dim3(TPB), lds, ctx->stream, slab, dim, nc, ovr_idx, ovr,
                            d.pass, pidx, d.stages, d.ops, d.aux, d.aux32, d.ltab, d.mtab, tiles, from_zero ? 1 : 0);
     };
-    if (h4) go(std::true_type{});
-    else go(std::false_type{});
+    if (h4 == 1) go(std::integral_constant<int, 1>{});
+    else if (h4 == 2) go(std::integral_constant<int, 2>{});
+    else go(std::integral_constant<int, 0>{});
     SV_HIP(hipGetLastError());
 }
 
 #define SV_TILE_INSTANTIATE(TPB)                                                                              \
     template void launch_tile_tpb<float, TPB>(Ctx *, size_t, unsigned, V2<float> *, uint64_t, int, const int *, \
                                               const DevOp<float> *, const DevPlanDev<float> &, int, uint64_t,   \
-                                              bool, bool);                                                     \
+                                              bool, int);                                                      \
     template void launch_tile_tpb<double, TPB>(Ctx *, size_t, unsigned, V2<double> *, uint64_t, int,           \
                                                const int *, const DevOp<double> *, const DevPlanDev<double> &,  \
-                                               int, uint64_t, bool, bool);
+                                               int, uint64_t, bool, int);
 
 }  // namespace sv
