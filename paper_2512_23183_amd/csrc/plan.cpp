@@ -255,8 +255,14 @@ void fuse_dense4(Pass &ps, Plan &plan) {
     uint64_t B = 0;
     auto flush = [&]() {
         double cost = 0;
-        for (const Op &o : blk) cost += op_cost(o);
-        if (blk.size() >= 2 && cost >= DENSE4_MIN_COST) {
+        bool two = false;  // a two-qubit gate that mixes amplitudes
+        for (const Op &o : blk) {
+            cost += op_cost(o);
+            two |= o.kind == OP_U2;
+        }
+        // runs of one-qubit gates and diagonals alone are left to the
+        // four-bit register stages (measured faster than the block)
+        if (two && blk.size() >= 2 && cost >= DENSE4_MIN_COST) {
             // pad to four bits with the lowest local bits not in the block
             for (int b : ps.local_bits)
                 if (__builtin_popcountll(B) < 4 && !(B & bit(b))) B |= bit(b);

@@ -88,7 +88,8 @@ __device__ __forceinline__ void h4_u1_at(V2<R> (&v)[16], const DevOp<R> &op) {
 // control bits are set; each of a, b and the controls is a register slot
 // (taken from e) or a bit of the group (taken from k0).
 template <typename R>
-__device__ __forceinline__ void h4_diag(V2<R> (&v)[16], uint64_t k0, const uint64_t (&G)[4], const DevOp<R> &op) {
+__device__ __forceinline__ void h4_diag(V2<R> (&v)[16], V2<R> &acc, uint64_t k0, const uint64_t (&G)[4],
+                                        const DevOp<R> &op) {
     const uint64_t regs = G[0] | G[1] | G[2] | G[3];
     const uint64_t gc = op.cmask & ~regs;
     if ((k0 & gc) != gc) return;
@@ -101,6 +102,11 @@ __device__ __forceinline__ void h4_diag(V2<R> (&v)[16], uint64_t k0, const uint6
     const int sa = slot(op.a), sb = op.b >= 0 ? slot(op.b) : -1;
     const uint32_t ga = (uint32_t)((k0 >> op.a) & 1), gb = op.b >= 0 ? (uint32_t)((k0 >> op.b) & 1) : 0u;
     const V2<R> d0 = mat_at(op, 0), d1 = mat_at(op, 1), d2 = mat_at(op, 2), d3 = mat_at(op, 3);
+    if (sa < 0 && sb < 0 && ec == 0) {
+        const V2<R> f = op.b >= 0 ? vsel(ga != 0, vsel(gb != 0, d3, d2), vsel(gb != 0, d1, d0)) : vsel(ga != 0, d1, d0);
+        acc = cmul(acc, f);
+        return;
+    }
     static_for<0, 16>([&](auto EC) {
         constexpr int e = decltype(EC)::value;
         const uint32_t ba = sa >= 0 ? ((uint32_t)e >> sa) & 1u : ga;
@@ -145,14 +151,26 @@ __device__ __forceinline__ void h4_ladder(V2<R> (&v)[16], uint32_t j0, uint64_t 
 // (controls, a, b): that factor (-1 exactly with NEG) where all are set.
 // The pattern splits into the group's bits (all set in k0, else nothing to
 // do) and the register slots it covers (emask: all set in e).
+// acc: the group's factor of the diagonals that involve no register bit
+// (they commute with every op of the stage; applied once after them).
 template <bool NEG, typename R>
-__device__ __forceinline__ void h4_pat(V2<R> (&v)[16], uint64_t k0, const uint64_t (&G)[4], const DevOp<R> &op) {
+__device__ __forceinline__ void h4_pat(V2<R> (&v)[16], V2<R> &acc, uint64_t k0, const uint64_t (&G)[4],
+                                       const DevOp<R> &op) {
     const uint64_t all = op.cmask | (1ull << op.a) | (op.b >= 0 ? (1ull << op.b) : 0ull);
     const uint64_t gmask = all & ~(G[0] | G[1] | G[2] | G[3]);
     if ((k0 & gmask) != gmask) return;
     const uint32_t emask = ((all & G[0]) ? 1u : 0u) | ((all & G[1]) ? 2u : 0u) | ((all & G[2]) ? 4u : 0u) |
                            ((all & G[3]) ? 8u : 0u);
     const V2<R> dl = op.b >= 0 ? mat_at(op, 3) : mat_at(op, 1);
+    if (emask == 0) {
+        if constexpr (NEG) {
+            acc.x = -acc.x;
+            acc.y = -acc.y;
+        } else {
+            acc = cmul(acc, dl);
+        }
+        return;
+    }
     static_for<0, 16>([&](auto EC) {
         constexpr int e = decltype(EC)::value;
         const bool on = ((uint32_t)e & emask) == emask;
@@ -212,6 +230,9 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
                 v[e] = tile[j0 | loff4<e>(L)];
             });
         }
+        V2<R> acc;
+        acc.x = (R)1;
+        acc.y = (R)0;
         for (int o = S.op_begin; o < S.op_end; ++o) {
             const DevOp<R> &op = (o == ovr_index) ? *ovr : ops[o];
             if (op.kind == OP_U1) {
@@ -238,11 +259,22 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
                 else if (op.ra == 3) h4_ladder<3>(v, j0, k0, op, tc);
                 else h4_ladder<-1>(v, j0, k0, op, tc);
             } else if (!GEN || (op.flags & OPF_PAT)) {
-                if (op.flags & OPF_NEG) h4_pat<true>(v, k0, G, op);
-                else h4_pat<false>(v, k0, G, op);
+                if (op.flags & OPF_NEG) h4_pat<true>(v, acc, k0, G, op);
+                else h4_pat<false>(v, acc, k0, G, op);
             } else {
-                h4_diag(v, k0, G, op);
+                h4_diag(v, acc, k0, G, op);
             }
+        }
+        if constexpr (GEN) {
+            static_for<0, 16>([&](auto EC) {
+                constexpr int e = decltype(EC)::value;
+                v[e] = cmul(v[e], acc);
+            });
+        } else if (acc.x != (R)1 || acc.y != (R)0) {
+            static_for<0, 16>([&](auto EC) {
+                constexpr int e = decltype(EC)::value;
+                v[e] = cmul(v[e], acc);
+            });
         }
         if constexpr (MODE & 2) {
             if (tc.scaled) {

@@ -68,9 +68,9 @@ Gates tuning_circuit(int n) {
     return G;
 }
 
-// Layers of fixed dense gates: U3 on every qubit, then CZ on (q, q + 1) for
-// even q, twice (runs that the planner may fuse into dense four-qubit
-// blocks).
+// Layers of fixed dense gates: U3 on every qubit, CZ on (q, q + 1) for even
+// q, then RXX and RYY on alternating neighbour pairs, twice (the rotation
+// runs are what the planner may fuse into dense four-qubit blocks).
 Gates dense_circuit(int n) {
     Gates G;
     for (int l = 0; l < 2; ++l) {
@@ -80,6 +80,12 @@ Gates dense_circuit(int n) {
             G.g.back().angle[2] = 1.1 + 0.02 * q;
         }
         for (int q = 0; q + 1 < n; q += 2) G.add(SV_CZ, q, q + 1);
+        // two-qubit rotations on neighbours: the runs dense blocks are made
+        // for (runs of one-qubit gates and diagonals never become blocks)
+        for (int q = l % 2; q + 1 < n; q += 2) {
+            G.add(SV_RXX, q, q + 1, 0.4 + 0.01 * q);
+            G.add(SV_RYY, q, q + 1, 0.5 + 0.01 * q);
+        }
     }
     return G;
 }
