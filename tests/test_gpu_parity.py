@@ -458,10 +458,16 @@ def test_autotune_picks_valid_widths_and_caches(sv, tmp_path):
 
 
 @pytest.mark.parametrize("n,depth", [(9, 4), (14, 3), (17, 2)])
-def test_dense_mfma_blocks_match_oracle(sv, n, depth):
-    # deep random layers (U3 on every qubit, CZ matching): complex64 runs of
-    # fixed gates on four qubits become dense 16x16 blocks on MFMA
-    circ = I.deep_random_circuit(n, depth, 40 + n)
+@pytest.mark.parametrize("kind", ["trotter", "deep"])
+def test_dense_mfma_blocks_match_oracle(sv, n, depth, kind):
+    # complex64 runs of fixed gates on four qubits that include a two-qubit
+    # rotation (the XYZ Trotter circuit's RXX / RYY / RZZ) become dense
+    # 16x16 blocks on MFMA; layers of U3 and CZ (one-qubit gates and
+    # diagonals only) stay with the four-bit register stages either way
+    if kind == "trotter":
+        circ = I.trotter_xyz_circuit(n, depth, 0.7)
+    else:
+        circ = I.deep_random_circuit(n, depth, 40 + n)
     psi0 = I.gaussian_state(n, 41 + n)
     want = oracle.run_circuit(circ, None, psi0)
     for fuse in (1, -1):
