@@ -151,9 +151,10 @@ __device__ __forceinline__ void h4_ladder(V2<R> (&v)[16], uint32_t j0, uint64_t 
 // (controls, a, b): that factor (-1 exactly with NEG) where all are set.
 // The pattern splits into the group's bits (all set in k0, else nothing to
 // do) and the register slots it covers (emask: all set in e).
-// acc: the group's factor of the diagonals that involve no register bit
-// (they commute with every op of the stage; applied once after them).
-template <bool NEG, typename R>
+// ACC (general stages): a diagonal that involves no register bit goes into
+// acc, the group's factor (such diagonals commute with every op of the
+// stage; it is applied once after them).
+template <bool NEG, bool ACC, typename R>
 __device__ __forceinline__ void h4_pat(V2<R> (&v)[16], V2<R> &acc, uint64_t k0, const uint64_t (&G)[4],
                                        const DevOp<R> &op) {
     const uint64_t all = op.cmask | (1ull << op.a) | (op.b >= 0 ? (1ull << op.b) : 0ull);
@@ -162,7 +163,7 @@ __device__ __forceinline__ void h4_pat(V2<R> (&v)[16], V2<R> &acc, uint64_t k0, 
     const uint32_t emask = ((all & G[0]) ? 1u : 0u) | ((all & G[1]) ? 2u : 0u) | ((all & G[2]) ? 4u : 0u) |
                            ((all & G[3]) ? 8u : 0u);
     const V2<R> dl = op.b >= 0 ? mat_at(op, 3) : mat_at(op, 1);
-    if (emask == 0) {
+    if (ACC && emask == 0) {
         if constexpr (NEG) {
             acc.x = -acc.x;
             acc.y = -acc.y;
@@ -259,18 +260,13 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
                 else if (op.ra == 3) h4_ladder<3>(v, j0, k0, op, tc);
                 else h4_ladder<-1>(v, j0, k0, op, tc);
             } else if (!GEN || (op.flags & OPF_PAT)) {
-                if (op.flags & OPF_NEG) h4_pat<true>(v, acc, k0, G, op);
-                else h4_pat<false>(v, acc, k0, G, op);
+                if (op.flags & OPF_NEG) h4_pat<true, GEN>(v, acc, k0, G, op);
+                else h4_pat<false, GEN>(v, acc, k0, G, op);
             } else {
                 h4_diag(v, acc, k0, G, op);
             }
         }
         if constexpr (GEN) {
-            static_for<0, 16>([&](auto EC) {
-                constexpr int e = decltype(EC)::value;
-                v[e] = cmul(v[e], acc);
-            });
-        } else if (acc.x != (R)1 || acc.y != (R)0) {
             static_for<0, 16>([&](auto EC) {
                 constexpr int e = decltype(EC)::value;
                 v[e] = cmul(v[e], acc);
