@@ -481,7 +481,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(this build runs on a single MI355X)", file=sys.stderr)
+              "(the simulator runs one state per GPU; the measured path is one MI355X's)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
     import oracle
