@@ -70,6 +70,18 @@ def stats(db, match=None, last=0):
     return "\n".join(out)
 
 
+def by_position(db, match, last, period):
+    """Durations of the last `last` dispatches matching `match`, grouped by
+    their position modulo `period` (e.g. the passes of one step)."""
+    d = [dur / 1e3 for name, dur, *_ in _kernels(db) if re.search(match, name)][-last:]
+    out = ["| position | dispatches | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for p in range(period):
+        x = d[p::period]
+        if x:
+            out.append(f"| {p} | {len(x)} | {statistics.mean(x):.1f} | {min(x):.1f} | {max(x):.1f} |")
+    return "\n".join(out)
+
+
 def pmc(db, match=None):
     per, names = _pmc(db)
     agg = collections.OrderedDict()
@@ -123,6 +135,11 @@ def main():
     a.add_argument("db")
     a.add_argument("--match")
     a.add_argument("--last", type=int, default=0, help="only the last N dispatches of each kernel")
+    a = sub.add_parser("positions")
+    a.add_argument("db")
+    a.add_argument("--match", required=True)
+    a.add_argument("--last", type=int, required=True)
+    a.add_argument("--period", type=int, required=True)
     a = sub.add_parser("pmc")
     a.add_argument("db")
     a.add_argument("--match")
@@ -137,6 +154,8 @@ def main():
     args = ap.parse_args()
     if args.cmd == "stats":
         print(stats(args.db, args.match, args.last))
+    elif args.cmd == "positions":
+        print(by_position(args.db, args.match, args.last, args.period))
     elif args.cmd == "pmc":
         print(pmc(args.db, args.match))
     else:
