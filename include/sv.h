@@ -170,7 +170,16 @@ typedef struct sv_config {
                                   shape); 0 = default (on), 1 = on, -1 = off */
 } sv_config;
 
+/* Fault injection for tests of the error paths: if the environment variable
+ * SV_FAULT_ALLOC=N (N >= 1) is set when sv_init runs, the context's N-th
+ * device allocation (states, scratch buffers, and separately each queue's
+ * own allocations) fails as if HBM were exhausted, and the call that made
+ * it returns SV_ENOMEM with nothing leaked. */
 int sv_init(sv_ctx **out, int device, const sv_config *cfg);
+/* Release the context.  Every state (sv_alloc, sv_wrap) and queue created on
+ * it must have been released first (sv_free, sv_queue_destroy): while any is
+ * alive the call changes nothing and returns SV_EBUSY, so no handle can
+ * outlive the context it references. */
 int sv_shutdown(sv_ctx *ctx);
 
 /* Use the caller's HIP stream (e.g. PyTorch's current stream); NULL = the
@@ -306,7 +315,10 @@ int sv_queue_create(sv_ctx *ctx, size_t hbm_budget_bytes, sv_queue **out);
 int sv_queue_submit(sv_queue *q, const sv_request *req, uint64_t *ticket);
 /* Wait up to timeout_ms (< 0 = forever).  grad may be NULL for energy-only
  * requests; grad_len must be >= the request's n_params otherwise.  The
- * ticket is released once a final status (OK or error) is returned. */
+ * ticket is released once a final status (OK or error) is returned.  If the
+ * scheduler thread stops on an internal error, every request it had not
+ * finished completes with that error (SV_EDEVICE unless the error carries
+ * its own status) and later submissions return it too. */
 int sv_queue_wait(sv_queue *q, uint64_t ticket, int timeout_ms,
                   double *energy, double *grad, size_t grad_len);
 /* As sv_queue_wait; latency_s (nullable) receives the time from submission

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -13,7 +14,7 @@ struct sv_ctx : sv::Ctx {};
 struct sv_state : sv::State {};
 
 namespace sv {
-void queue_shutdown_all(Ctx *ctx);
+size_t queue_count(Ctx *ctx);
 }
 
 using namespace sv;
@@ -194,6 +195,7 @@ int sv_init(sv_ctx **out, int device, const sv_config *cfg) {
             fail(SV_EDEVICE, "stream creation failed");
         }
         ctx->stream = ctx->own_stream;
+        if (const char *fa = std::getenv("SV_FAULT_ALLOC")) ctx->fault_alloc = std::max(0, std::atoi(fa));
         if (cfg) {
             auto pick = [](int32_t v, int lo, int hi, int &dst) {
                 if (v > 0) dst = std::max(lo, std::min(hi, (int)v));
@@ -214,8 +216,14 @@ int sv_init(sv_ctx **out, int device, const sv_config *cfg) {
 int sv_shutdown(sv_ctx *ctx) {
     return guard([&] {
         need(ctx != nullptr, "ctx is NULL");
+        // states and queues reference the context (its stream, its device):
+        // they must be released first, so that no handle outlives it
+        const int ns = ctx->live_states.load();
+        const size_t nq = queue_count(ctx);
+        if (ns > 0 || nq > 0)
+            fail(SV_EBUSY, "context still has " + std::to_string(ns) + " live state(s) and " +
+                               std::to_string(nq) + " queue(s); free them before sv_shutdown");
         use_device(ctx);
-        queue_shutdown_all(ctx);
         (void)hipStreamSynchronize(ctx->stream);
         release_graph(ctx);
         release_pinned(ctx);
@@ -266,7 +274,7 @@ int sv_alloc(sv_ctx *ctx, int n_qubits, int dtype, sv_state **out) {
         st->ctx = ctx;
         st->n = n_qubits;
         st->dtype = dtype;
-        if (hipMalloc(&st->ptr, st->bytes()) != hipSuccess) {
+        if (dev_malloc(ctx, &st->ptr, st->bytes()) != hipSuccess) {
             (void)hipGetLastError();
             delete st;
             fail(SV_ENOMEM, "device allocation of the state failed");
@@ -278,6 +286,7 @@ int sv_alloc(sv_ctx *ctx, int n_qubits, int dtype, sv_state **out) {
             delete st;
             throw;
         }
+        ctx->live_states.fetch_add(1);
         *out = st;
     });
 }
@@ -295,6 +304,7 @@ int sv_wrap(sv_ctx *ctx, void *dev_ptr, int n_qubits, int dtype, sv_state **out)
         st->dtype = dtype;
         st->ptr = dev_ptr;
         st->owned = false;
+        ctx->live_states.fetch_add(1);
         *out = st;
     });
 }
@@ -307,6 +317,7 @@ int sv_free(sv_state *st) {
             (void)hipStreamSynchronize(st->ctx->stream);
             (void)hipFree(st->ptr);
         }
+        st->ctx->live_states.fetch_sub(1);
         delete st;
     });
 }

@@ -1086,7 +1086,11 @@ inline DevOp<R> to_dev(const Op &op) {
         op.m[3].imag() == 0.0) {
         d.flags |= OPF_REAL;
         const double m0 = op.m[0].real(), m1 = op.m[1].real(), m2 = op.m[2].real(), m3 = op.m[3].real();
-        if (op.cmask == 0 && m0 != 0.0 && m0 == m1 && m0 == m2 && m3 == -m0) {
+        // value-dependent classes (Hadamard, all-ones pattern) are kept from
+        // parameterised ops: a shifted copy of such an op replaces it on the
+        // device without a new plan, and the pass kernel chosen from the
+        // base op's class must still be right for the copy
+        if (!op.param && op.cmask == 0 && m0 != 0.0 && m0 == m1 && m0 == m2 && m3 == -m0) {
             d.flags |= OPF_HAD;
             d.sfac = m0;
         } else if (op.cmask == 0 && m0 == m3 && m1 == -m2 && (m0 != 0.0 || m2 != 0.0)) {
@@ -1106,7 +1110,7 @@ inline DevOp<R> to_dev(const Op &op) {
         d.m[8] = (R)r.real();
         d.m[9] = (R)r.imag();
     }
-    if (op.kind == OP_DIAG) {
+    if (op.kind == OP_DIAG && !op.param) {
         const int last = op.b >= 0 ? 3 : 1;
         bool pat = true;
         for (int k = 0; k < last; ++k) pat &= op.m[k] == cd(1.0);

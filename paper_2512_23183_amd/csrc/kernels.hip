@@ -398,6 +398,15 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uin
 // Host side
 // ===========================================================================
 
+hipError_t dev_malloc(Ctx *ctx, void **p, size_t bytes) {
+    const uint64_t k = ctx->n_allocs.fetch_add(1) + 1;
+    if (ctx->fault_alloc > 0 && k == (uint64_t)ctx->fault_alloc) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
 void *scratch(Ctx *ctx, const std::string &name, size_t bytes) {
     DeviceBuffer &b = ctx->scratch[name];
     if (ctx->record) {
@@ -415,7 +424,7 @@ void *scratch(Ctx *ctx, const std::string &name, size_t bytes) {
             b.bytes = 0;
         }
         size_t want = std::max<size_t>(bytes, 4096);
-        if (hipMalloc(&b.ptr, want) != hipSuccess) {
+        if (dev_malloc(ctx, &b.ptr, want) != hipSuccess) {
             (void)hipGetLastError();
             fail(SV_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
         }

@@ -452,7 +452,7 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
         // pass, where they share stages with that pass's own.
         if (!deferred.empty()) {
             auto is_had = [](const Op &o) {
-                return o.kind == OP_U1 && o.cmask == 0 && o.m[0] == o.m[1] && o.m[0] == o.m[2] &&
+                return o.kind == OP_U1 && !o.param && o.cmask == 0 && o.m[0] == o.m[1] && o.m[0] == o.m[2] &&
                        o.m[3] == -o.m[0] && o.m[0].imag() == 0.0 && o.m[0].real() > 0.0;
             };
             bool only = true;

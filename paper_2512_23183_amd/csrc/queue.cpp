@@ -68,6 +68,11 @@ struct QueueImpl {
     std::map<uint64_t, std::shared_ptr<Req>> all;
     uint64_t next_ticket = 1;
     bool stop = false;
+    // set when the scheduler thread ended on an exception: every request it
+    // left was completed with dead_code, and later submissions fail
+    bool dead = false;
+    int dead_code = SV_OK;
+    std::string dead_msg;
     sv_queue_stats stats{};
     // device energy pool: first-fit ranges
     double *d_pool = nullptr;
@@ -108,6 +113,7 @@ struct QueueImpl {
     }
 
     void run();
+    void fail_all(int code, const std::string &msg);
     void tick(std::vector<std::pair<std::shared_ptr<Req>, std::vector<int>>> &work);
 };
 
@@ -179,6 +185,12 @@ void QueueImpl::run() {
         } catch (const Error &e) {
             err = e.code;
             msg = e.msg;
+        } catch (const std::bad_alloc &) {
+            err = SV_ENOMEM;
+            msg = "host allocation failed";
+        } catch (const std::exception &e) {
+            err = SV_EDEVICE;
+            msg = std::string("internal error: ") + e.what();
         }
         // complete requests whose circuits are all done
         std::vector<std::shared_ptr<Req>> complete;
@@ -218,6 +230,9 @@ void QueueImpl::run() {
                 } catch (const Error &e) {
                     r.status = e.code;
                     r.err = e.msg;
+                } catch (const std::exception &e) {
+                    r.status = SV_EDEVICE;
+                    r.err = std::string("internal error: ") + e.what();
                 }
             }
             std::lock_guard<std::mutex> lk(mu);
@@ -248,6 +263,26 @@ void QueueImpl::run() {
         }
         cv_done.notify_all();
     }
+}
+
+void QueueImpl::fail_all(int code, const std::string &msg) {
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        dead = true;
+        dead_code = code;
+        dead_msg = msg;
+        for (auto &kv : all) {
+            Req &r = *kv.second;
+            if (r.finished) continue;
+            r.finished = true;
+            r.status = code;
+            r.err = "queue scheduler stopped: " + msg;
+            r.t_done = clk::now();
+            stats.failed++;
+        }
+        pending.clear();
+    }
+    cv_done.notify_all();
 }
 
 static std::mutex g_queues_mu;
@@ -281,15 +316,9 @@ void queue_destroy_impl(QueueImpl *q) {
     delete q;
 }
 
-void queue_shutdown_all(Ctx *ctx) {
-    std::vector<QueueImpl *> qs;
-    {
-        std::lock_guard<std::mutex> lk(g_queues_mu);
-        auto r = g_queues.equal_range(ctx);
-        for (auto it = r.first; it != r.second; ++it) qs.push_back(it->second);
-        g_queues.erase(ctx);
-    }
-    for (QueueImpl *q : qs) queue_destroy_impl(q);
+size_t queue_count(Ctx *ctx) {
+    std::lock_guard<std::mutex> lk(g_queues_mu);
+    return g_queues.count(ctx);
 }
 
 }  // namespace sv
@@ -338,6 +367,7 @@ int sv_queue_create(sv_ctx *ctx_, size_t hbm_budget_bytes, sv_queue **out) {
         }
         q->ctx->dense4 = ctx->dense4;
         q->ctx->graphs = ctx->graphs;
+        q->ctx->fault_alloc = ctx->fault_alloc;
         if (hipStreamCreateWithFlags(&q->ctx->own_stream, hipStreamNonBlocking) != hipSuccess) {
             delete q->ctx;
             delete q;
@@ -346,7 +376,7 @@ int sv_queue_create(sv_ctx *ctx_, size_t hbm_budget_bytes, sv_queue **out) {
         q->ctx->stream = q->ctx->own_stream;
         q->budget = hbm_budget_bytes;
         q->pool_cap = 1 << 22;
-        if (hipMalloc(&q->d_pool, (size_t)q->pool_cap * 8) != hipSuccess) {
+        if (dev_malloc(q->ctx, (void **)&q->d_pool, (size_t)q->pool_cap * 8) != hipSuccess) {
             (void)hipGetLastError();
             (void)hipStreamDestroy(q->ctx->own_stream);
             delete q->ctx;
@@ -355,9 +385,16 @@ int sv_queue_create(sv_ctx *ctx_, size_t hbm_budget_bytes, sv_queue **out) {
         }
         q->free_ranges[0] = q->pool_cap;
         q->worker = std::thread([q] {
+            // whatever ends the scheduler completes every waiting request
+            // with an error instead of leaving its waiter blocked
             try {
                 q->run();
+            } catch (const Error &e) {
+                q->fail_all(e.code, e.msg);
+            } catch (const std::exception &e) {
+                q->fail_all(SV_EDEVICE, std::string("internal error: ") + e.what());
             } catch (...) {
+                q->fail_all(SV_EDEVICE, "internal error: unknown exception");
             }
         });
         {
@@ -395,6 +432,7 @@ int sv_queue_submit(sv_queue *q_, const sv_request *req, uint64_t *ticket) {
         if (one > q->budget) fail(SV_EBUSY, "a single state of this request exceeds the queue budget");
         if ((int)r->spec.circuits.size() > q->pool_cap) fail(SV_EBUSY, "request has too many circuits");
         std::lock_guard<std::mutex> lk(q->mu);
+        if (q->dead) fail(q->dead_code, "queue scheduler stopped: " + q->dead_msg);
         r->ticket = q->next_ticket++;
         r->t_submit = std::chrono::steady_clock::now();
         q->all[r->ticket] = r;

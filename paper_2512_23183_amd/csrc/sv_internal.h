@@ -259,6 +259,13 @@ struct Ctx {
     int perm_bits[2] = {12, 11};
     bool dense4 = true;  // complex64 circuits: MFMA stages for dense four-qubit runs
     std::mutex mu;
+    // states created on this context and not yet freed (sv_shutdown refuses
+    // to run while any is alive: they reference the context's stream)
+    std::atomic<int> live_states{0};
+    // fault injection (environment variable SV_FAULT_ALLOC=N at sv_init):
+    // the context's N-th device allocation fails as if HBM were exhausted
+    int fault_alloc = 0;
+    std::atomic<uint64_t> n_allocs{0};
     // scratch buffers reused across calls (grown on demand)
     std::map<std::string, DeviceBuffer> scratch;
     // batched executor: the launches of one batch call are recorded and
@@ -292,6 +299,9 @@ struct State {
     size_t bytes() const { return amp_bytes() << n; }
 };
 
+// Every device allocation of the library goes through here (counted per
+// context, for the fault-injection hook).
+hipError_t dev_malloc(Ctx *ctx, void **p, size_t bytes);
 void *scratch(Ctx *ctx, const std::string &name, size_t bytes);
 // Kernel launches of the batched executor go through here: run now, or
 // appended to ctx->record (no allocation or upload may happen inside f).

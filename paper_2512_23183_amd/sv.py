@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -203,9 +204,14 @@ class Context:
         h = _vp()
         _check(lib().sv_init(ctypes.byref(h), device, ctypes.byref(cfg)))
         self.h = h
+        # states and queues made on this context; close() releases those
+        # still alive first (the library refuses to shut down under them)
+        self._owned = weakref.WeakSet()
 
     def close(self):
         if self.h:
+            for obj in list(self._owned):
+                obj._release()
             _check(lib().sv_shutdown(self.h))
             self.h = None
 
@@ -292,11 +298,14 @@ class State:
     def __init__(self, ctx: Context, n: int, dtype: int = C64, _wrap_ptr: int = 0):
         self.ctx, self.n, self.dtype = ctx, n, dtype
         h = _vp()
+        if not ctx.h:
+            raise SvError(-1, "context is closed")
         if _wrap_ptr:
             _check(lib().sv_wrap(ctx.h, _wrap_ptr, n, dtype, ctypes.byref(h)))
         else:
             _check(lib().sv_alloc(ctx.h, n, dtype, ctypes.byref(h)))
         self.h = h
+        ctx._owned.add(self)
 
     @staticmethod
     def from_torch(ctx: Context, tensor) -> "State":
@@ -315,6 +324,11 @@ class State:
         if self.h:
             _check(lib().sv_free(self.h))
             self.h = None
+
+    def _release(self):
+        # the context is closing: free the handle now; later calls on this
+        # object see a closed state
+        self.free()
 
     def __del__(self):
         try:
@@ -363,9 +377,21 @@ class State:
 class Queue:
     def __init__(self, ctx: Context, budget_bytes: int):
         h = _vp()
+        if not ctx.h:
+            raise SvError(-1, "context is closed")
         _check(lib().sv_queue_create(ctx.h, budget_bytes, ctypes.byref(h)))
         self.h = h
         self._n_params = {}
+        ctx._owned.add(self)
+
+    def _release(self):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def submit(self, circuit: Circuit, params, ham: PauliSum, want_grad: bool,
                dtype: int = C64) -> int:

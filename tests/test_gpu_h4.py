@@ -80,3 +80,41 @@ def test_gradient_with_shifted_cp_in_hadamard_passes(sv, dtype):
     tol = 1e-10 if dtype == C128 else 1e-5
     assert abs(e_b - e_ref) <= tol
     assert np.max(np.abs(g_b - g_ref)) <= tol
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
+def test_gradient_with_zero_angle_rz_between_hadamard_layers(sv, dtype):
+    # RZ(0) lowers to the identity diagonal, whose values alone would class
+    # its pass as Hadamards and all-ones-pattern diagonals; its shifted
+    # copies RZ(+-pi/2) are general diagonals and must still be applied as
+    # such (15 qubits: the batched slab executor, not the LDS-resident one).
+    # H RZ(t) H = RX(t), so <Y_q> = -sin t has derivative -1 at t = 0.
+    n = 15
+    b = I.CircuitBuilder(n)
+    for q in range(n):
+        b.add(I.H, [q])
+    for q in range(n):
+        b.add(I.RZ, [q], params=[q])
+    for q in range(n):
+        b.add(I.H, [q])
+    c = b.build(n)
+    params = np.zeros(n)
+    rng = np.random.default_rng(77)
+    terms = []
+    for q in range(n):
+        terms.append((float(rng.normal()), "I" * q + "Y" + "I" * (n - 1 - q)))
+    for q in range(n - 1):
+        s = ["I"] * n
+        s[q], s[q + 1] = "XY"[q % 2], "Y"
+        terms.append((float(rng.normal()), "".join(s)))
+    ham = I.PauliSum.from_strings(n, terms)
+    with sv.Context(0) as ctx:
+        e_b, g_b = ctx.param_shift_grad(c, params, ham, dtype)
+        e_s, g_s = ctx.param_shift_grad(c, params, ham, dtype, flags=sv.FLAG_SEQUENTIAL)
+    assert e_b == e_s and np.array_equal(g_b, g_s), np.max(np.abs(g_b - g_s))
+    e_ref, g_ref = oracle.param_shift(c, params, ham)
+    tol = 1e-10 if dtype == C128 else 1e-5
+    assert abs(e_b - e_ref) <= tol
+    assert np.max(np.abs(g_b - g_ref)) <= tol
+    # single-Y terms contribute -c_q to their parameter's derivative
+    assert np.max(np.abs(g_ref)) > 0.1

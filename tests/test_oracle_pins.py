@@ -191,6 +191,30 @@ def test_xyz_chain_exact_diagonalisation():
     assert e_theta >= e0 - 1e-12
 
 
+def test_xyz_chain_ground_energy_and_coupling_assignment():
+    # Eq. "xyz_hamiltonian" with Jx = 1.0, Jy = 0.8, Jz = 0.6, h = 0, open
+    # chain of 10 sites: ground energy -9.161997432407 (the value the
+    # configuration's exact diagonalisation is quoted at).  The spectrum is
+    # invariant under any permutation of (Jx, Jy, Jz) (a global spin rotation
+    # maps one onto another), so the product eigenstates of X, Y and Z pin
+    # which coupling sits on which Pauli pair: every bond of |+...+> has
+    # <XX> = 1 and <YY> = <ZZ> = 0, so E = -Jx (n - 1); likewise -Jy (n - 1)
+    # for |+i...+i> and -Jz (n - 1) for |0...0>.
+    n = 10
+    ham = I.xyz_chain(n)
+    e0 = np.linalg.eigvalsh(brute.hamiltonian_matrix(ham))[0]
+    assert abs(e0 - (-9.161997432407)) <= 1e-9, e0
+    N = 1 << n
+    plus = np.full(N, N ** -0.5, dtype=np.complex128)
+    k = np.arange(N)
+    ones = np.array([bin(int(v)).count("1") for v in k])
+    plus_i = (1j ** ones) * N ** -0.5          # (|0> + i|1>)/sqrt 2 on every qubit
+    for psi, want in ((oracle.zero_state(n), -0.6 * (n - 1)), (plus, -1.0 * (n - 1)),
+                      (plus_i, -0.8 * (n - 1))):
+        e, mi = oracle.energy(psi, ham)
+        assert abs(e - want) <= 1e-12 and mi <= 1e-12, (e, want)
+
+
 def test_xyz_chain_sign_reading():
     # the paper writes H = -sum(J XX + ...); with h = 0 and an open chain of
     # 4 sites, the all-Z product state |0000> has energy -Jz * (n-1)
