@@ -219,6 +219,25 @@ int sv_apply_circuit_ex(sv_state *st, const sv_circuit *circuit,
                         const double *params, size_t n_params, uint32_t flags);
 
 /*
+ * For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * fused apply of sv_apply_circuit with no device allocation.  The plan's
+ * device tables (ops, stages, ladder and layout tables) go to a block
+ * preallocated per device when the library is loaded (SV_NOALLOC_BLOCK_BYTES,
+ * held until the process ends) instead of a context buffer.  The state is
+ * the caller's, as in sv_apply_circuit.  Returns SV_EINVAL, before any
+ * device work, when the circuit's tables exceed the block (a plan holds
+ * about 224 bytes per op at complex64, 352 at complex128, so circuits of
+ * roughly 10^4 gates fit).  Every call on a device shares that
+ * device's block: calls that overlap on one device (other streams, other
+ * contexts, other threads) race and must be serialised by the caller; calls
+ * in order on one stream are safe.  Results equal sv_apply_circuit's.
+ */
+#define SV_NOALLOC_BLOCK_BYTES ((size_t)4 << 20)
+int sv_apply_circuit_noalloc(sv_state *st, const sv_circuit *circuit,
+                             const double *params, size_t n_params);
+
+/*
  * Quantum Fourier transform as the gate list of Alg. "Gate-Based QFT"
  * (H, controlled phases CP(pi/2^(j-i)), final swaps) run through the same
  * executor; equals sqrt(N) times the inverse DFT of the amplitudes

@@ -187,6 +187,7 @@ int sv_init(sv_ctx **out, int device, const sv_config *cfg) {
         if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
             fail(SV_ENODEV, std::string("device is ") + prop.gcnArchName + "; this library targets gfx950");
         SV_HIP(hipSetDevice(device));
+        noalloc_setup(device);
         sv_ctx *ctx = new sv_ctx();
         ctx->device = device;
         ctx->cu_count = prop.multiProcessorCount;
@@ -372,6 +373,22 @@ int sv_apply_circuit_ex(sv_state *st, const sv_circuit *circuit, const double *p
 
 int sv_apply_circuit(sv_state *st, const sv_circuit *circuit, const double *params, size_t n_params) {
     return sv_apply_circuit_ex(st, circuit, params, n_params, 0);
+}
+
+int sv_apply_circuit_noalloc(sv_state *st, const sv_circuit *circuit, const double *params, size_t n_params) {
+    return guard([&] {
+        need(st != nullptr, "state is NULL");
+        check_circuit(circuit, params, n_params);
+        need(circuit->n_qubits == st->n, "circuit and state qubit counts differ");
+        Ctx *ctx = st->ctx;
+        use_device(ctx);
+        void *block = noalloc_block(ctx->device);
+        PlanOptions po;
+        po.tile_bits = ctx->tile_bits[st->dtype];
+        po.perm_bits = ctx->perm_bits[st->dtype];
+        po.dense4 = st->dtype == SV_C64 && ctx->dense4;
+        run_plan_in(ctx, st, make_plan(st->n, lower_circuit(circuit, params), po), block, NOALLOC_BLOCK_BYTES);
+    });
 }
 
 int sv_qft_ex(sv_state *st, uint32_t flags) {

@@ -918,14 +918,18 @@ DevPlanHost<R> build_dev_plan(const Plan &plan) {
 template DevPlanHost<float> build_dev_plan<float>(const Plan &);
 template DevPlanHost<double> build_dev_plan<double>(const Plan &);
 
+// Device image of a plan: every table at a 256-byte boundary of one block
+// (dbase null: only the size of that block is computed).
 template <typename R>
-DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const std::string &slot) {
+static size_t place_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, char *dbase, DevPlanDev<R> *out) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t s_ops = al(h.dops.size() * sizeof(DevOp<R>) + 16), s_pass = al(h.dpass.size() * sizeof(DevPass) + 16);
     const size_t s_st = al(h.dstages.size() * sizeof(DevStage) + 16), s_aux = al(h.aux.size() * 8 + 16);
     const size_t s_aux32 = al(h.aux32.size() * 4 + 16), s_lt = al(h.ltab.size() * sizeof(V2<R>) + 16);
     const size_t s_mt = al(h.mtab.size() * 4 + 16);
-    std::vector<unsigned char> host(s_ops + s_pass + s_st + s_aux + s_aux32 + s_lt + s_mt, 0);
+    const size_t total = s_ops + s_pass + s_st + s_aux + s_aux32 + s_lt + s_mt;
+    if (!dbase) return total;
+    std::vector<unsigned char> host(total, 0);
     size_t off = 0;
     auto put = [&](const void *src, size_t bytes, size_t sz) {
         if (bytes) std::memcpy(host.data() + off, src, bytes);
@@ -940,9 +944,8 @@ DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const std::stri
     const size_t o_aux32 = put(h.aux32.data(), h.aux32.size() * 4, s_aux32);
     const size_t o_lt = put(h.ltab.data(), h.ltab.size() * sizeof(V2<R>), s_lt);
     const size_t o_mt = put(h.mtab.data(), h.mtab.size() * 4, s_mt);
-    char *dbase = (char *)scratch(ctx, slot, host.size());
     upload(ctx, dbase, host.data(), host.size());
-    DevPlanDev<R> d;
+    DevPlanDev<R> &d = *out;
     d.ops = (const DevOp<R> *)(dbase + o_ops);
     d.pass = (const DevPass *)(dbase + o_pass);
     d.stages = (const DevStage *)(dbase + o_st);
@@ -950,6 +953,14 @@ DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const std::stri
     d.aux32 = (const uint32_t *)(dbase + o_aux32);
     d.ltab = (const V2<R> *)(dbase + o_lt);
     d.mtab = (const float *)(dbase + o_mt);
+    return total;
+}
+
+template <typename R>
+DevPlanDev<R> upload_dev_plan(Ctx *ctx, const DevPlanHost<R> &h, const std::string &slot) {
+    DevPlanDev<R> d;
+    char *dbase = (char *)scratch(ctx, slot, place_dev_plan<R>(ctx, h, nullptr, nullptr));
+    place_dev_plan<R>(ctx, h, dbase, &d);
     return d;
 }
 template DevPlanDev<float> upload_dev_plan<float>(Ctx *, const DevPlanHost<float> &, const std::string &);
@@ -1045,6 +1056,25 @@ static void run_plan_t(Ctx *ctx, State *st, const Plan &plan) {
 void run_plan(Ctx *ctx, State *st, const Plan &plan) {
     if (st->dtype == SV_C64) run_plan_t<float>(ctx, st, plan);
     else run_plan_t<double>(ctx, st, plan);
+}
+
+// As run_plan, with the plan's device tables in a caller-provided block of
+// cap bytes instead of a context buffer (no device allocation).
+template <typename R>
+static void run_plan_in_t(Ctx *ctx, State *st, const Plan &plan, void *block, size_t cap) {
+    DevPlanHost<R> h = build_dev_plan<R>(plan);
+    const size_t need = place_dev_plan<R>(ctx, h, nullptr, nullptr);
+    if (need > cap)
+        fail(SV_EINVAL, "the circuit's plan needs " + std::to_string(need) + " bytes of device tables; at most " +
+                            std::to_string(cap) + " fit the preallocated block");
+    DevPlanDev<R> d;
+    place_dev_plan<R>(ctx, h, (char *)block, &d);
+    launch_plan<R>(ctx, plan, h, d, reinterpret_cast<V2<R> *>(st->ptr), 1ull << st->n, 1, nullptr, nullptr, false);
+}
+
+void run_plan_in(Ctx *ctx, State *st, const Plan &plan, void *block, size_t cap) {
+    if (st->dtype == SV_C64) run_plan_in_t<float>(ctx, st, plan, block, cap);
+    else run_plan_in_t<double>(ctx, st, plan, block, cap);
 }
 
 void run_unfused(Ctx *ctx, State *st, const std::vector<Op> &ops) {

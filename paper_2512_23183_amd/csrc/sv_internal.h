@@ -332,6 +332,15 @@ void profile_collect(Ctx *ctx);
 
 // Run a plan on one state (ops uploaded per call).
 void run_plan(Ctx *ctx, State *st, const Plan &plan);
+// As run_plan with the plan's device tables in a given block of cap bytes
+// (SV_EINVAL, before any device work, if they do not fit).
+void run_plan_in(Ctx *ctx, State *st, const Plan &plan, void *block, size_t cap);
+
+// The preallocated block of the no-allocation entry point: its size, its
+// per-device set-up (at context creation) and its device address.
+constexpr size_t NOALLOC_BLOCK_BYTES = SV_NOALLOC_BLOCK_BYTES;
+void noalloc_setup(int device);
+void *noalloc_block(int device);
 // One-gate-per-launch sweeps (the plain path).
 void run_unfused(Ctx *ctx, State *st, const std::vector<Op> &ops);
 void set_zero_state(Ctx *ctx, void *psi, int n, int dtype);

@@ -98,6 +98,7 @@ def lib():
             "sv_apply_circuit": [_vp, ctypes.POINTER(_Circuit), _dp, ctypes.c_size_t],
             "sv_apply_circuit_ex": [_vp, ctypes.POINTER(_Circuit), _dp, ctypes.c_size_t,
                                     ctypes.c_uint32],
+            "sv_apply_circuit_noalloc": [_vp, ctypes.POINTER(_Circuit), _dp, ctypes.c_size_t],
             "sv_qft": [_vp],
             "sv_qft_ex": [_vp, ctypes.c_uint32],
             "sv_norm2": [_vp, _dp],
@@ -353,6 +354,12 @@ class State:
         a = _CircArgs(circuit, params)
         _check(lib().sv_apply_circuit_ex(self.h, ctypes.byref(a.c), _dptr(a.params),
                                          a.params.size, flags))
+
+    def apply_noalloc(self, circuit: Circuit, params=None):
+        """sv_apply_circuit_noalloc: the fused apply with its plan tables in
+        the device's preallocated block (no device allocation)."""
+        a = _CircArgs(circuit, params)
+        _check(lib().sv_apply_circuit_noalloc(self.h, ctypes.byref(a.c), _dptr(a.params), a.params.size))
 
     def qft(self, flags: int = 0):
         _check(lib().sv_qft_ex(self.h, flags))
