@@ -354,6 +354,37 @@ int sv_check_circuit(const sv_circuit *circuit, const double *params,
                      size_t n_params);
 int sv_check_pauli_sum(const sv_pauli_sum *ham, int n_qubits);
 
+/*
+ * Host-only inspection of the plan the fused apply would run for a circuit
+ * (the lowering and fusion of Sec. "Circuit Data Structure"'s gate list; the
+ * paper itself applies gates one at a time).  No device is needed: the
+ * circuit is validated, lowered to FP64 gate records, planned into passes
+ * and register stages with the widths of cfg (NULL = the library's
+ * defaults) for dtype, and described.  sv_plan_dump writes a text listing
+ * (one line per pass, stage and device op) into buf, truncated to buf_len
+ * bytes including the terminating NUL; *needed (nullable) receives the full
+ * length.  Errors as sv_apply_circuit's validation.
+ */
+typedef struct sv_plan_stats {
+    int32_t tile_passes;       /* passes over the state through LDS tiles */
+    int32_t perm_passes;       /* bit-relabelling passes (absorbed SWAPs) */
+    int32_t sweep_passes;      /* one-gate sweeps (states of 1-2 qubits) */
+    int32_t stages;            /* register stages over all tile passes */
+    int32_t ops;               /* device ops over all tile passes */
+    int32_t tile_passes_by_engine[4]; /* [0] three-bit stages, four-bit stages:
+                                 [1] general, [2] Hadamard / ladder,
+                                 [3] rotation / diagonal */
+    int32_t dense_blocks;      /* dense 16x16 blocks applied with MFMA */
+    int32_t diagonal_tables;   /* gathered stage diagonals */
+    int32_t reserved;
+    double min_pass_scale, max_pass_scale; /* deferred real factors per pass */
+} sv_plan_stats;
+int sv_plan_info(const sv_circuit *circuit, const double *params, size_t n_params,
+                 int dtype, const sv_config *cfg, sv_plan_stats *out);
+int sv_plan_dump(const sv_circuit *circuit, const double *params, size_t n_params,
+                 int dtype, const sv_config *cfg, char *buf, size_t buf_len,
+                 size_t *needed);
+
 /* Optional per-kernel timing with HIP events recorded on the launching
  * stream around every launch (off by default).  name = kernel family. */
 int sv_profile_enable(sv_ctx *ctx, int on);

@@ -48,6 +48,23 @@ void need(bool cond, const char *msg) {
 
 void use_device(Ctx *ctx) { SV_HIP(hipSetDevice(ctx->device)); }
 
+// Widths and switches of sv_config over the context's defaults (a field of
+// 0 keeps the default; widths are clamped to their ranges).
+void apply_config(Ctx *ctx, const sv_config *cfg) {
+    if (!cfg) return;
+    auto pick = [](int32_t v, int lo, int hi, int &dst) {
+        if (v > 0) dst = std::max(lo, std::min(hi, (int)v));
+    };
+    pick(cfg->tile_bits_c64, 6, TILE_MAX[SV_C64], ctx->tile_bits[SV_C64]);
+    pick(cfg->tile_bits_c128, 6, TILE_MAX[SV_C128], ctx->tile_bits[SV_C128]);
+    pick(cfg->expect_bits_c64, 6, EXPECT_MAX[SV_C64], ctx->expect_bits[SV_C64]);
+    pick(cfg->expect_bits_c128, 6, EXPECT_MAX[SV_C128], ctx->expect_bits[SV_C128]);
+    pick(cfg->perm_bits_c64, 6, PERM_MAX[SV_C64], ctx->perm_bits[SV_C64]);
+    pick(cfg->perm_bits_c128, 6, PERM_MAX[SV_C128], ctx->perm_bits[SV_C128]);
+    if (cfg->dense_fuse != 0) ctx->dense4 = cfg->dense_fuse > 0;
+    if (cfg->graph_batch != 0) ctx->graphs = cfg->graph_batch > 0;
+}
+
 void check_dtype(int dtype) { need(dtype == SV_C64 || dtype == SV_C128, "dtype must be SV_C64 or SV_C128"); }
 
 std::vector<Op> lower_circuit(const sv_circuit *c, const double *params) {
@@ -172,6 +189,57 @@ int sv_check_pauli_sum(const sv_pauli_sum *ham, int n_qubits) {
     return guard([&] { check_pauli_sum(ham, n_qubits); });
 }
 
+namespace {
+// The plan sv_apply_circuit would run for this circuit with these widths
+// (host only: validation, lowering, planning and the device tables' layout).
+PlanSummary plan_for(const sv_circuit *circuit, const double *params, size_t n_params, int dtype,
+                     const sv_config *cfg, std::string *text) {
+    check_circuit(circuit, params, n_params);
+    check_dtype(dtype);
+    Ctx opts;  // the library's default widths, then cfg's
+    apply_config(&opts, cfg);
+    PlanOptions po;
+    po.tile_bits = opts.tile_bits[dtype];
+    po.perm_bits = opts.perm_bits[dtype];
+    po.dense4 = dtype == SV_C64 && opts.dense4;
+    const Plan plan = make_plan(circuit->n_qubits, lower_circuit(circuit, params), po);
+    return dtype == SV_C64 ? summarize_plan<float>(plan, text) : summarize_plan<double>(plan, text);
+}
+}  // namespace
+
+int sv_plan_info(const sv_circuit *circuit, const double *params, size_t n_params, int dtype, const sv_config *cfg,
+                 sv_plan_stats *out) {
+    return guard([&] {
+        need(out != nullptr, "out is NULL");
+        const PlanSummary sm = plan_for(circuit, params, n_params, dtype, cfg, nullptr);
+        std::memset(out, 0, sizeof *out);
+        out->tile_passes = sm.tile_passes;
+        out->perm_passes = sm.perm_passes;
+        out->sweep_passes = sm.sweep_passes;
+        out->stages = sm.stages;
+        out->ops = sm.ops;
+        for (int i = 0; i < 4; ++i) out->tile_passes_by_engine[i] = sm.h4_passes[i];
+        out->dense_blocks = sm.dense_blocks;
+        out->diagonal_tables = sm.tables;
+        out->min_pass_scale = sm.tile_passes ? sm.min_scale : 1.0;
+        out->max_pass_scale = sm.tile_passes ? sm.max_scale : 1.0;
+    });
+}
+
+int sv_plan_dump(const sv_circuit *circuit, const double *params, size_t n_params, int dtype, const sv_config *cfg,
+                 char *buf, size_t buf_len, size_t *needed) {
+    return guard([&] {
+        std::string text;
+        plan_for(circuit, params, n_params, dtype, cfg, &text);
+        if (needed) *needed = text.size() + 1;
+        if (buf && buf_len) {
+            const size_t k = std::min(buf_len - 1, text.size());
+            std::memcpy(buf, text.data(), k);
+            buf[k] = 0;
+        }
+    });
+}
+
 int sv_init(sv_ctx **out, int device, const sv_config *cfg) {
     return guard([&] {
         need(out != nullptr, "out is NULL");
@@ -197,19 +265,7 @@ int sv_init(sv_ctx **out, int device, const sv_config *cfg) {
         }
         ctx->stream = ctx->own_stream;
         if (const char *fa = std::getenv("SV_FAULT_ALLOC")) ctx->fault_alloc = std::max(0, std::atoi(fa));
-        if (cfg) {
-            auto pick = [](int32_t v, int lo, int hi, int &dst) {
-                if (v > 0) dst = std::max(lo, std::min(hi, (int)v));
-            };
-            pick(cfg->tile_bits_c64, 6, TILE_MAX[SV_C64], ctx->tile_bits[SV_C64]);
-            pick(cfg->tile_bits_c128, 6, TILE_MAX[SV_C128], ctx->tile_bits[SV_C128]);
-            pick(cfg->expect_bits_c64, 6, EXPECT_MAX[SV_C64], ctx->expect_bits[SV_C64]);
-            pick(cfg->expect_bits_c128, 6, EXPECT_MAX[SV_C128], ctx->expect_bits[SV_C128]);
-            pick(cfg->perm_bits_c64, 6, PERM_MAX[SV_C64], ctx->perm_bits[SV_C64]);
-            pick(cfg->perm_bits_c128, 6, PERM_MAX[SV_C128], ctx->perm_bits[SV_C128]);
-            if (cfg->dense_fuse != 0) ctx->dense4 = cfg->dense_fuse > 0;
-            if (cfg->graph_batch != 0) ctx->graphs = cfg->graph_batch > 0;
-        }
+        apply_config(ctx, cfg);
         *out = ctx;
     });
 }

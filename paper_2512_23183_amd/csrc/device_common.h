@@ -1110,6 +1110,9 @@ inline DevOp<R> to_dev(const Op &op) {
         d.m[8] = (R)r.real();
         d.m[9] = (R)r.imag();
     }
+    // a parameterised gate whose shifted copies can leave the real-matrix
+    // class (every one but RY and CRY)
+    if (op.param && !op.real_family) d.flags |= OPF_PARAMC;
     if (op.kind == OP_DIAG && !op.param) {
         const int last = op.b >= 0 ? 3 : 1;
         bool pat = true;
@@ -1186,11 +1189,14 @@ inline void localise(DevOp<R> &d, const std::vector<int> &local_bits) {
 // its register slot (or -1) and, in complex slots 0..15 of m, the phase of
 // each element's register-bit offset.
 // 0: not eligible; 1: general four-bit stages; 2: Hadamards, ladders and
-// all-ones-pattern diagonals only (the QFT's passes, a smaller kernel).
+// all-ones-pattern diagonals only (the QFT's passes, a smaller kernel);
+// 3: Hadamards, real rotations and diagonals only.  A parameterised op
+// whose shifted copies may fall outside a class (OPF_PARAMC) keeps its pass
+// general.
 template <typename R>
 inline int h4_kind(const std::vector<DevOp<R>> &ops, int ob, int oe, int m) {
     if (m < 6 || m > 16 || oe <= ob) return 0;
-    bool qft = true;
+    bool qft = true, rot = true;
     for (int o = ob; o < oe; ++o) {
         const DevOp<R> &d = ops[o];
         const bool mix = (d.kind == OP_U1 || d.kind == OP_XPERM) && d.cmask == 0;
@@ -1198,8 +1204,11 @@ inline int h4_kind(const std::vector<DevOp<R>> &ops, int ob, int oe, int m) {
         if ((d.kind == OP_U1 && !(d.flags & OPF_HAD)) || d.kind == OP_XPERM ||
             (d.kind == OP_DIAG && !(d.flags & OPF_PAT)))
             qft = false;
+        if (d.kind == OP_XPERM || d.kind == OP_LADDER ||
+            (d.kind == OP_U1 && (!(d.flags & (OPF_HAD | OPF_ROTC | OPF_ROTS)) || (d.flags & OPF_PARAMC))))
+            rot = false;
     }
-    return qft ? 2 : 1;
+    return qft ? 2 : rot ? 3 : 1;
 }
 
 template <typename R>
@@ -1225,12 +1234,27 @@ inline void build_stages_h4(std::vector<DevOp<R>> &ops, int ob, int oe, const st
             const auto it = std::find(regs.begin(), regs.end(), lb);
             return it == regs.end() ? -1 : (int)(it - regs.begin());
         };
+        uint64_t greg = 0;  // global positions of the register bits
+        for (int r : regs) greg |= 1ull << local_bits[r];
+        S.acc = 0;
         for (int o = start; o < end; ++o) {
             DevOp<R> &d = ops[o];
             d.flags &= ~OPF_PLACEMENT;
             if (d.kind == OP_U1 || d.kind == OP_XPERM) {
                 d.ra = slot(d.la);
                 if (d.ra < 0) fail(SV_EDEVICE, "internal: gate bit outside its stage");
+            } else if (d.kind == OP_DIAG) {
+                // which ops feed the group factor (acc) decides whether the
+                // stage applies it: REG1 ops with d0 != 1, and diagonals
+                // that involve no register bit
+                const uint64_t all = d.cmask | (1ull << d.a) | (d.b >= 0 ? (1ull << d.b) : 0ull);
+                if (d.b < 0 && d.cmask == 0 && d.la >= 0 && slot(d.la) >= 0) {
+                    d.ra = slot(d.la);
+                    d.flags |= OPF_REG1;
+                    if (!(d.flags & OPF_PAT)) S.acc = 1;
+                } else if ((all & greg) == 0) {
+                    S.acc = 1;
+                }
             } else if (d.kind == OP_LADDER) {
                 d.ra = d.la >= 0 ? slot(d.la) : -1;
                 for (int e = 0; e < 16; ++e) {
@@ -1255,6 +1279,162 @@ inline void build_stages_h4(std::vector<DevOp<R>> &ops, int ob, int oe, const st
         regs.push_back(d.la);
     }
     close(oe);
+}
+
+// Diagonal tables for the four-bit stages of a pass of rotations and
+// diagonals (h4 kind 3).  In each stage, every fixed diagonal whose bits are
+// all register bits, and every fixed -1-on-the-all-ones-pattern diagonal
+// (CZ) on one register bit and one bit outside the registers, leaves the op
+// list and is gathered into an OP_DIAG16 op: the product of the factors on
+// the 16 register-bit combinations (FP64, rounded once) and, per register
+// slot, the outside bits whose parity negates the elements with that slot
+// set.  A gathered diagonal may move anywhere between the mixing ops on its
+// register bits that precede and follow it (diagonals commute with each
+// other and with mixing ops on other bits); the tables go to the fewest
+// points between the stage's mixing ops that give every diagonal a point
+// inside its range (interval stabbing: take the ranges by right end, a new
+// point at the right end of the first one not yet covered).
+// pops: the FP64 ops of the pass (pops[i] is ops[ob + i]).  The pass's ops
+// and gate list are rebuilt; stage op ranges and oe follow.
+template <typename R>
+inline void gather_stage_diagonals(std::vector<DevOp<R>> &ops, std::vector<int> &gate, const std::vector<Op> &pops,
+                                   int ob, int &oe, std::vector<DevStage> &stages, int sb,
+                                   const std::vector<int> &local_bits) {
+    std::vector<DevOp<R>> out(ops.begin(), ops.begin() + ob);
+    std::vector<int> gout(gate.begin(), gate.begin() + ob);
+    for (int si = sb; si < (int)stages.size(); ++si) {
+        DevStage &S = stages[si];
+        const int regs[4] = {S.r0, S.r1, S.r2, S.r3};
+        uint64_t greg[4];
+        for (int i = 0; i < 4; ++i) greg[i] = 1ull << local_bits[regs[i]];
+        const uint64_t gall = greg[0] | greg[1] | greg[2] | greg[3];
+        struct Gathered {
+            int o;          // op index
+            uint32_t slots; // register slots it depends on
+            int r;          // sign coupling: its slot (else -1)
+            uint64_t outb;  // sign coupling: the outside bit
+            int lo, hi, at; // allowed gaps and the chosen one
+        };
+        std::vector<Gathered> gd;
+        std::vector<int> mix;           // op indices of the mixing ops, in order
+        std::vector<int> gap_of;        // per op of the stage: mixing ops before it
+        for (int o = S.op_begin; o < S.op_end; ++o) {
+            const DevOp<R> &d = ops[o];
+            const Op &src = pops[o - ob];
+            gap_of.push_back((int)mix.size());
+            if (d.kind == OP_U1 || d.kind == OP_XPERM) {
+                mix.push_back(o);
+                continue;
+            }
+            if (d.kind != OP_DIAG || src.param) continue;
+            const uint64_t all = src.cmask | (1ull << src.a) | (src.b >= 0 ? (1ull << src.b) : 0ull);
+            const uint64_t outb = all & ~gall;
+            Gathered g{o, 0u, -1, 0ull, 0, 0, 0};
+            for (int i = 0; i < 4; ++i)
+                if (all & greg[i]) g.slots |= 1u << i;
+            if (outb != 0) {
+                const bool pat_neg = (d.flags & OPF_PAT) && (d.flags & OPF_NEG);
+                if (!pat_neg || __builtin_popcount(g.slots) != 1 || __builtin_popcountll(outb) != 1) continue;
+                g.r = __builtin_ctz(g.slots);
+                g.outb = outb;
+            }
+            gd.push_back(g);
+        }
+        const int K = (int)mix.size();
+        for (Gathered &g : gd) {
+            const int j = gap_of[g.o - S.op_begin];
+            g.lo = 0;
+            for (int k = j - 1; k >= 0; --k)
+                if ((g.slots >> ops[mix[k]].ra) & 1) { g.lo = k + 1; break; }
+            g.hi = K;
+            for (int k = j; k < K; ++k)
+                if ((g.slots >> ops[mix[k]].ra) & 1) { g.hi = k; break; }
+        }
+        std::vector<int> order(gd.size());
+        for (size_t i = 0; i < gd.size(); ++i) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return gd[a].hi < gd[b].hi; });
+        int point = -1;
+        for (int i : order) {
+            if (point < gd[i].lo) point = gd[i].hi;
+            gd[i].at = point;
+        }
+        std::vector<char> gathered(S.op_end - S.op_begin, 0);
+        for (const Gathered &g : gd) gathered[g.o - S.op_begin] = 1;
+        // emit: per gap, its table, the ops left in place there, its mixing op
+        const int nb = (int)out.size();
+        auto emit_table = [&](int gap) {
+            cd T[16];
+            for (int e = 0; e < 16; ++e) T[e] = 1.0;
+            uint64_t M[4] = {0, 0, 0, 0};
+            bool any = false;
+            for (const Gathered &g : gd) {
+                if (g.at != gap) continue;
+                any = true;
+                if (g.r >= 0) {
+                    M[g.r] ^= g.outb;
+                    continue;
+                }
+                const Op &src = pops[g.o - ob];
+                for (int e = 0; e < 16; ++e) {
+                    uint64_t k = 0;
+                    for (int i = 0; i < 4; ++i)
+                        if ((e >> i) & 1) k |= greg[i];
+                    if ((k & src.cmask) != src.cmask) continue;
+                    const int ba = (k >> src.a) & 1;
+                    T[e] *= src.b >= 0 ? src.m[2 * ba + (int)((k >> src.b) & 1)] : src.m[ba];
+                }
+            }
+            if (!any) return;
+            DevOp<R> t;
+            std::memset(&t, 0, sizeof t);
+            t.kind = OP_DIAG16;
+            t.a = t.b = t.la = t.lb = t.ra = t.rb = -1;
+            t.tab = -1;
+            for (int e = 0; e < 16; ++e) {
+                t.m[2 * e] = (R)T[e].real();
+                t.m[2 * e + 1] = (R)T[e].imag();
+            }
+            t.cmask = M[0];
+            t.lcmask = M[1];
+            t.gcmask = M[2];
+            t.lmask = M[3];
+            if (M[0] | M[1] | M[2] | M[3]) t.flags |= OPF_SGN;
+            out.push_back(t);
+            gout.push_back(-1);
+        };
+        int next = S.op_begin;
+        for (int gap = 0; gap <= K; ++gap) {
+            emit_table(gap);
+            const int stop = gap < K ? mix[gap] : S.op_end;
+            for (; next < stop; ++next)
+                if (!gathered[next - S.op_begin]) {
+                    out.push_back(ops[next]);
+                    gout.push_back(gate[next]);
+                }
+            if (gap < K) {
+                out.push_back(ops[mix[gap]]);
+                gout.push_back(gate[mix[gap]]);
+                next = mix[gap] + 1;
+            }
+        }
+        S.op_begin = nb;
+        S.op_end = (int)out.size();
+        // the group factor is needed only for what feeds it now
+        S.acc = 0;
+        for (int o = S.op_begin; o < S.op_end; ++o) {
+            const DevOp<R> &d = out[o];
+            if (d.kind != OP_DIAG) continue;
+            const uint64_t all = d.cmask | (1ull << d.a) | (d.b >= 0 ? (1ull << d.b) : 0ull);
+            if ((d.flags & OPF_REG1) ? !(d.flags & OPF_PAT) : (all & gall) == 0) S.acc = 1;
+        }
+    }
+    for (int o = oe; o < (int)ops.size(); ++o) {
+        out.push_back(ops[o]);
+        gout.push_back(gate[o]);
+    }
+    oe = (int)out.size() - ((int)ops.size() - oe);
+    ops.swap(out);
+    gate.swap(gout);
 }
 
 template <typename R>

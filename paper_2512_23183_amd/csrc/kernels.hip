@@ -18,6 +18,8 @@
 //    a fixed order, so results are bitwise reproducible.
 //  * small-state batch: one workgroup runs a whole circuit of <= 2^13
 //    amplitudes in LDS and reduces its energy (parameter-shift batches).
+#include <cstdio>
+
 #include "device_common.h"
 
 namespace sv {
@@ -898,9 +900,16 @@ DevPlanHost<R> build_dev_plan(const Plan &plan) {
         // passes of uncontrolled one-qubit gates, ladders and diagonals take
         // four-bit stages
         dp.h4 = ps.kind == PASS_TILE ? h4_kind<R>(h.dops, b, (int)h.dops.size(), ps.m) : 0;
-        if (dp.h4) build_stages_h4<R>(h.dops, b, (int)h.dops.size(), ps.local_bits, h.dstages);
-        else if (ps.kind == PASS_TILE)
+        if (dp.h4) {
+            build_stages_h4<R>(h.dops, b, (int)h.dops.size(), ps.local_bits, h.dstages);
+            if (dp.h4 == 3) {
+                int oe = (int)h.dops.size();
+                gather_stage_diagonals<R>(h.dops, h.gate, ps.ops, b, oe, h.dstages, dp.stage_begin, ps.local_bits);
+                dp.op_end = oe;
+            }
+        } else if (ps.kind == PASS_TILE) {
             build_stages<R>(h.dops, b, (int)h.dops.size(), ps.local_bits, h.dstages, h.aux32, true);
+        }
         dp.stage_end = (int)h.dstages.size();
         dp.paux_count = (int)h.aux32.size() - dp.paux_begin;
         // the layout-map tables go to LDS when the workgroup still fits
@@ -917,6 +926,62 @@ DevPlanHost<R> build_dev_plan(const Plan &plan) {
 }
 template DevPlanHost<float> build_dev_plan<float>(const Plan &);
 template DevPlanHost<double> build_dev_plan<double>(const Plan &);
+
+// Host-side summary and text listing of a device plan (no device work).
+template <typename R>
+PlanSummary summarize_plan(const Plan &plan, std::string *text) {
+    const DevPlanHost<R> h = build_dev_plan<R>(plan);
+    PlanSummary sm;
+    static const char *kname[] = {"U1", "U2", "DIAG", "LADDER", "SWAP", "XPERM", "DENSE4", "DIAG16"};
+    char line[256];
+    for (size_t i = 0; i < plan.passes.size(); ++i) {
+        const Pass &ps = plan.passes[i];
+        const DevPass &dp = h.dpass[i];
+        if (ps.kind == PASS_SWEEP) {
+            ++sm.sweep_passes;
+            if (text) *text += "pass " + std::to_string(i) + " sweep\n";
+            continue;
+        }
+        if (ps.kind == PASS_PERM) {
+            ++sm.perm_passes;
+            if (text) *text += "pass " + std::to_string(i) + " perm m=" + std::to_string(ps.m) + "\n";
+            continue;
+        }
+        ++sm.tile_passes;
+        sm.h4_passes[std::max(0, std::min(3, dp.h4))] += 1;
+        sm.stages += dp.stage_end - dp.stage_begin;
+        sm.ops += dp.op_end - dp.op_begin;
+        sm.min_scale = std::min(sm.min_scale, std::fabs(dp.scale));
+        sm.max_scale = std::max(sm.max_scale, std::fabs(dp.scale));
+        if (text) {
+            std::snprintf(line, sizeof line, "pass %zu tile m=%d l=%d h4=%d ops=%d stages=%d scale=%.17g\n", i, ps.m,
+                          ps.l, dp.h4, dp.op_end - dp.op_begin, dp.stage_end - dp.stage_begin, dp.scale);
+            *text += line;
+        }
+        for (int s = dp.stage_begin; s < dp.stage_end; ++s) {
+            const DevStage &S = h.dstages[s];
+            if (text) {
+                std::snprintf(line, sizeof line, "  stage regs=%d,%d,%d,%d ops=[%d,%d) acc=%d mfma=%d perm=%d\n", S.r0,
+                              S.r1, S.r2, dp.h4 ? S.r3 : -1, S.op_begin, S.op_end, S.acc, S.mfma, S.perm);
+                *text += line;
+            }
+            for (int o = S.op_begin; o < S.op_end; ++o) {
+                const DevOp<R> &op = h.dops[o];
+                if (op.kind == OP_DENSE4) ++sm.dense_blocks;
+                if (op.kind == OP_DIAG16) ++sm.tables;
+                if (text) {
+                    std::snprintf(line, sizeof line, "    %s a=%d b=%d ra=%d flags=%d cmask=%llx gate=%d\n",
+                                  op.kind >= 0 && op.kind < 8 ? kname[op.kind] : "?", op.a, op.b, op.ra, op.flags,
+                                  (unsigned long long)op.cmask, h.gate[o]);
+                    *text += line;
+                }
+            }
+        }
+    }
+    return sm;
+}
+template PlanSummary summarize_plan<float>(const Plan &, std::string *);
+template PlanSummary summarize_plan<double>(const Plan &, std::string *);
 
 // Device image of a plan: every table at a 256-byte boundary of one block
 // (dbase null: only the size of that block is computed).

@@ -165,6 +165,7 @@ Op lower_gate(int n, const sv_gate &g, const double ang[3], const double *mat,
     case SV_RY:
         op.kind = OP_U1; op.a = bitpos(n, g.q[0]);
         set1(c, -s, s, c);
+        op.real_family = true;
         break;
     case SV_RZ:
         op.kind = OP_DIAG; op.a = bitpos(n, g.q[0]); op.b = -1;
@@ -206,6 +207,7 @@ Op lower_gate(int n, const sv_gate &g, const double ang[3], const double *mat,
     case SV_CRY:
         op.kind = OP_U1; op.a = bitpos(n, g.q[1]); op.cmask = 1ull << bitpos(n, g.q[0]);
         set1(c, -s, s, c);
+        op.real_family = true;
         break;
     case SV_CRZ:
         op.kind = OP_DIAG; op.a = bitpos(n, g.q[1]); op.b = -1;

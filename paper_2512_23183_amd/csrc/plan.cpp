@@ -308,6 +308,113 @@ void fuse_dense4(Pass &ps, Plan &plan) {
     ps.ops.swap(out);
 }
 
+// A fixed, uncontrolled one-qubit gate with complex entries is written as
+// diag(p0, p1) R diag(q0, q1) with R = [[c, -s], [s, c]] a real rotation
+// (c = |u00|, s = |u10|): every 2x2 unitary has this form (U3 and RX are
+// the configurations' cases).  Then each fixed uncontrolled one-qubit
+// diagonal is merged into the previous one on the same bit when no op in
+// between mixes that bit (a diagonal commutes with ops that leave its bit
+// unmixed, controls included), and every such diagonal is normalised to
+// diag(1, d1 / d0), its d0 going to one global phase kept on the first of
+// them.  The register stages apply a real rotation in two FMAs per
+// amplitude (its c or s goes to the pass scale) and a diag(1, r) in one
+// complex multiply on half of the amplitudes, where a complex 2x2 costs
+// eight operations per amplitude.  Exact up to rounding of the factors
+// (computed in FP64).
+void split_phases(std::vector<Op> &ops) {
+    auto unitary = [](const Op &o) {
+        const cd a = o.m[0], b = o.m[1], c = o.m[2], d = o.m[3];
+        const double e1 = std::abs(std::norm(a) + std::norm(c) - 1.0);
+        const double e2 = std::abs(std::norm(b) + std::norm(d) - 1.0);
+        const double e3 = std::abs(a * std::conj(b) + c * std::conj(d));
+        return e1 <= 1e-12 && e2 <= 1e-12 && e3 <= 1e-12;
+    };
+    auto diag1 = [](const Op &o) { return o.kind == OP_DIAG && !o.param && o.b < 0 && o.cmask == 0; };
+    std::vector<Op> out;
+    out.reserve(ops.size() + ops.size() / 2);
+    for (const Op &o : ops) {
+        bool real = true;
+        for (int k = 0; k < 4; ++k) real &= o.m[k].imag() == 0.0;
+        if (o.kind != OP_U1 || o.param || o.cmask != 0 || real || !unitary(o)) {
+            out.push_back(o);
+            continue;
+        }
+        const cd u00 = o.m[0], u01 = o.m[1], u10 = o.m[2], u11 = o.m[3];
+        const double c = std::abs(u00), s = std::abs(u10);
+        Op q, r, p;
+        q.kind = p.kind = OP_DIAG;
+        q.a = p.a = r.a = o.a;
+        q.b = p.b = -1;
+        q.gate = p.gate = -1;
+        r.kind = OP_U1;
+        r.gate = o.gate;
+        if (s == 0.0) {  // diagonal already
+            p.m[0] = u00;
+            p.m[1] = u11;
+            p.gate = o.gate;
+            out.push_back(p);
+            continue;
+        }
+        if (c == 0.0) {  // anti-diagonal: R = [[0, -1], [1, 0]]
+            q.m[0] = 1.0;
+            q.m[1] = -u01;
+            p.m[0] = 1.0;
+            p.m[1] = u10;
+        } else {
+            const cd p0 = u00 / c;
+            q.m[0] = 1.0;
+            q.m[1] = -u01 * c / (s * u00);
+            p.m[0] = p0;
+            p.m[1] = u10 / s;
+        }
+        r.m[0] = c;
+        r.m[1] = -s;
+        r.m[2] = s;
+        r.m[3] = c;
+        out.push_back(q);
+        out.push_back(r);
+        out.push_back(p);
+    }
+    // merge and normalise the fixed one-qubit diagonals
+    std::vector<Op> merged;
+    merged.reserve(out.size());
+    std::vector<int> last(64, -1);  // per bit: index in merged of a diagonal that can take the next one
+    cd phase = 1.0;
+    int first = -1;
+    for (const Op &o : out) {
+        if (diag1(o)) {
+            cd d0 = o.m[0], d1 = o.m[1];
+            if (d0 == cd(0.0)) {  // singular: keep as it is
+                merged.push_back(o);
+                last[o.a] = -1;
+                continue;
+            }
+            phase *= d0;
+            d1 /= d0;
+            if (last[o.a] >= 0) {
+                merged[last[o.a]].m[1] *= d1;
+                continue;
+            }
+            Op n = o;
+            n.m[0] = 1.0;
+            n.m[1] = d1;
+            last[o.a] = (int)merged.size();
+            if (first < 0) first = (int)merged.size();
+            merged.push_back(n);
+            continue;
+        }
+        const OpSets st = sets_of(o);
+        if (!st.diag)
+            for (int b : mask_bits(st.target)) last[b] = -1;
+        merged.push_back(o);
+    }
+    if (first >= 0) {
+        merged[first].m[0] *= phase;
+        merged[first].m[1] *= phase;
+    }
+    ops.swap(merged);
+}
+
 }  // namespace
 
 Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
@@ -342,6 +449,9 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
         }
         ops.push_back(remap(op, phys));
     }
+
+    // 1b. phase structure of fixed one-qubit gates (see split_phases)
+    split_phases(ops);
 
     // 2. merge runs of fixed-angle controlled phases with a common control
     //    into ladders when their angles are a common multiple of the

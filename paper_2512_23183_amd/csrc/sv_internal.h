@@ -55,6 +55,11 @@ enum OpKind : int32_t {
     OP_DENSE4 = 6,  // dense 16x16 matrix (Plan::dense[dense]) on the four bits
                     // of lmask, pattern bit k = the k-th lowest of them; made
                     // by the planner from runs of fixed gates (MFMA stages)
+    OP_DIAG16 = 7,  // device only: the gathered diagonals of a four-bit stage,
+                    // element e of a register group *= m[e] (complex), negated
+                    // where the parity of e & c is odd; bit r of c is the
+                    // parity of k & M_r with M_0..3 in cmask, lcmask, gcmask,
+                    // lmask (CZ-like couplings to bits outside the registers)
 };
 
 struct Op {
@@ -68,6 +73,7 @@ struct Op {
     int32_t gate = -1;     // source gate index (-1 = synthesised)
     int32_t dense = -1;    // OP_DENSE4: index of its matrix in Plan::dense
     bool param = false;    // angle depends on the parameter vector
+    bool real_family = false;  // real matrix at every angle (RY, CRY)
     bool diagonal() const { return kind == OP_DIAG || kind == OP_LADDER; }
 };
 
@@ -107,6 +113,9 @@ enum {
     OPF_HAD = 32,  // s [[1, 1], [1, -1]]: sums and differences
     OPF_ROTC = 64, // c [[1, -t], [t, 1]], t = s / c (|t| <= 1) in m[10]
     OPF_ROTS = 128,// s [[u, -1], [1, u]], u = c / s (|u| < 1) in m[10]
+    OPF_PARAMC = 256, // parameterised, and its matrix class may change with
+                      // the parameter (not RY / CRY): decides pass kernels
+    OPF_SGN = 512,    // OP_DIAG16 with sign couplings
 };
 constexpr int OPF_SCALED = OPF_HAD | OPF_ROTC | OPF_ROTS;
 constexpr int OPF_PLACEMENT = OPF_GRP | OPF_REG1;
@@ -332,6 +341,16 @@ void profile_collect(Ctx *ctx);
 
 // Run a plan on one state (ops uploaded per call).
 void run_plan(Ctx *ctx, State *st, const Plan &plan);
+// What a device plan holds (host only: sv_plan_info / sv_plan_dump).
+struct PlanSummary {
+    int sweep_passes = 0, tile_passes = 0, perm_passes = 0, stages = 0, ops = 0;
+    int h4_passes[4] = {0, 0, 0, 0};
+    int dense_blocks = 0, tables = 0;
+    double min_scale = 1e300, max_scale = 0.0;
+};
+template <typename R>
+PlanSummary summarize_plan(const Plan &plan, std::string *text);
+
 // As run_plan with the plan's device tables in a given block of cap bytes
 // (SV_EINVAL, before any device work, if they do not fit).
 void run_plan_in(Ctx *ctx, State *st, const Plan &plan, void *block, size_t cap);

@@ -122,6 +122,41 @@ __device__ __forceinline__ void h4_diag(V2<R> (&v)[16], V2<R> &acc, uint64_t k0,
     });
 }
 
+// Uncontrolled one-qubit diagonal diag(d0, d1) on register slot I: d0 goes
+// to the group factor (nothing to do when it is 1: OPF_PAT), the elements
+// with the bit set are multiplied by d1 / d0 (complex entry 4 of m).
+template <int I, typename R>
+__device__ __forceinline__ void h4_diag1(V2<R> (&v)[16], V2<R> &acc, const DevOp<R> &op) {
+    if (!(op.flags & OPF_PAT)) acc = cmul(acc, mat_at(op, 0));
+    const V2<R> r = mat_at(op, 4);
+    static_for<0, 16>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        if constexpr ((e >> I) & 1) v[e] = cmul(v[e], r);
+    });
+}
+
+// Gathered diagonals of a stage (OP_DIAG16): element e *= m[e], negated
+// where e & c has odd parity, c_r = parity(k0 & M_r).  The parities become a
+// 16-bit mask of the negated elements, xor-ed into the sign bits.
+template <typename R>
+__device__ __forceinline__ void h4_table(V2<R> (&v)[16], uint64_t k0, const DevOp<R> &op) {
+    uint32_t neg = 0;
+    if (op.flags & OPF_SGN) {
+        const uint32_t c0 = __popcll(k0 & op.cmask) & 1, c1 = __popcll(k0 & op.lcmask) & 1,
+                       c2 = __popcll(k0 & op.gcmask) & 1, c3 = __popcll(k0 & op.lmask) & 1;
+        neg = (c0 ? 0xAAAAu : 0u) ^ (c1 ? 0xCCCCu : 0u) ^ (c2 ? 0xF0F0u : 0u) ^ (c3 ? 0xFF00u : 0u);
+    }
+    static_for<0, 16>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        V2<R> t = mat_at(op, e);
+        if ((neg >> e) & 1) {
+            t.x = -t.x;
+            t.y = -t.y;
+        }
+        v[e] = cmul(v[e], t);
+    });
+}
+
 // Ladder: where bit a is set, multiply by exp(2 pi i turns (k & lmask)) =
 // (group phase from the tile-independent tables and the tile factor) x K_e
 // (the phase of element e's register-bit offset, complex slot e of op.m).
@@ -187,12 +222,16 @@ __device__ __forceinline__ void h4_pat(V2<R> (&v)[16], V2<R> &acc, uint64_t k0, 
 // One four-bit stage.  MODE bit 0: read the groups from global memory (or
 // synthesise |0...0>), else from the LDS tile; MODE bit 1: write them to
 // global memory (scaled by the pass scale), else to the LDS tile.
-// GEN: any of the kinds above; else Hadamards, ladders and pattern
-// diagonals only (the QFT's passes: a smaller op loop).
-template <typename R, int TPB, int MODE, bool GEN>
+// KIND 1: any of the kinds above; 2: Hadamards, ladders and pattern
+// diagonals only (the QFT's passes); 3: Hadamards, real rotations and
+// diagonals only (layered circuits once their one-qubit gates are split
+// into rotations and phases).  The smaller op loops of 2 and 3 keep the
+// sixteen amplitudes and the op data in registers without spilling.
+template <typename R, int TPB, int MODE, int KIND>
 __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
                                          const DevStage &S, const DevOp<R> *__restrict__ ops, int ovr_index,
                                          const DevOp<R> *ovr) {
+    constexpr bool GEN = KIND != 2;
     const uint32_t nitems = (1u << tc.m) >> 4;
     const int r[4] = {S.r0, S.r1, S.r2, S.r3};
     const uint32_t L[4] = {1u << r[0], 1u << r[1], 1u << r[2], 1u << r[3]};
@@ -236,6 +275,35 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
         acc.y = (R)0;
         for (int o = S.op_begin; o < S.op_end; ++o) {
             const DevOp<R> &op = (o == ovr_index) ? *ovr : ops[o];
+            if constexpr (KIND == 3) {
+                if (op.kind == OP_DIAG16) {
+                    h4_table(v, k0, op);
+                    continue;
+                }
+                if (op.kind == OP_U1) {
+                    if (op.flags & OPF_HAD) {
+                        if (op.ra == 0) h4_had<0, R>(v);
+                        else if (op.ra == 1) h4_had<1, R>(v);
+                        else if (op.ra == 2) h4_had<2, R>(v);
+                        else h4_had<3, R>(v);
+                    } else if (op.flags & OPF_ROTC) {
+                        h4_u1_at<4>(v, op);
+                    } else {
+                        h4_u1_at<5>(v, op);
+                    }
+                } else if (op.flags & OPF_REG1) {
+                    if (op.ra == 0) h4_diag1<0>(v, acc, op);
+                    else if (op.ra == 1) h4_diag1<1>(v, acc, op);
+                    else if (op.ra == 2) h4_diag1<2>(v, acc, op);
+                    else h4_diag1<3>(v, acc, op);
+                } else if (op.flags & OPF_PAT) {
+                    if (op.flags & OPF_NEG) h4_pat<true, true>(v, acc, k0, G, op);
+                    else h4_pat<false, true>(v, acc, k0, G, op);
+                } else {
+                    h4_diag(v, acc, k0, G, op);
+                }
+                continue;
+            }
             if (op.kind == OP_U1) {
                 if (!GEN || (op.flags & OPF_HAD)) {
                     if (op.ra == 0) h4_had<0, R>(v);
@@ -259,6 +327,11 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
                 else if (op.ra == 2) h4_ladder<2>(v, j0, k0, op, tc);
                 else if (op.ra == 3) h4_ladder<3>(v, j0, k0, op, tc);
                 else h4_ladder<-1>(v, j0, k0, op, tc);
+            } else if (GEN && (op.flags & OPF_REG1)) {
+                if (op.ra == 0) h4_diag1<0>(v, acc, op);
+                else if (op.ra == 1) h4_diag1<1>(v, acc, op);
+                else if (op.ra == 2) h4_diag1<2>(v, acc, op);
+                else h4_diag1<3>(v, acc, op);
             } else if (!GEN || (op.flags & OPF_PAT)) {
                 if (op.flags & OPF_NEG) h4_pat<true, GEN>(v, acc, k0, G, op);
                 else h4_pat<false, GEN>(v, acc, k0, G, op);
@@ -267,10 +340,13 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
             }
         }
         if constexpr (GEN) {
-            static_for<0, 16>([&](auto EC) {
-                constexpr int e = decltype(EC)::value;
-                v[e] = cmul(v[e], acc);
-            });
+            // acc is exactly 1 unless a diagonal of the stage contributed
+            if (S.acc) {
+                static_for<0, 16>([&](auto EC) {
+                    constexpr int e = decltype(EC)::value;
+                    v[e] = cmul(v[e], acc);
+                });
+            }
         }
         if constexpr (MODE & 2) {
             if (tc.scaled) {
@@ -300,17 +376,17 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
     }
 }
 
-template <typename R, int TPB, bool GEN>
+template <typename R, int TPB, int KIND>
 __device__ __forceinline__ void run_stages_h4(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
                                               const DevStage *__restrict__ stages, int sb, int se,
                                               const DevOp<R> *__restrict__ ops, int ovr_index, const DevOp<R> *ovr) {
     for (int s = sb; s < se; ++s) {
         const DevStage &S = stages[s];
         const bool first = s == sb, last = s == se - 1;
-        if (first && last) h4_stage<R, TPB, 3, GEN>(tile, gpsi, tc, S, ops, ovr_index, ovr);
-        else if (first) h4_stage<R, TPB, 1, GEN>(tile, gpsi, tc, S, ops, ovr_index, ovr);
-        else if (last) h4_stage<R, TPB, 2, GEN>(tile, gpsi, tc, S, ops, ovr_index, ovr);
-        else h4_stage<R, TPB, 0, GEN>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        if (first && last) h4_stage<R, TPB, 3, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        else if (first) h4_stage<R, TPB, 1, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        else if (last) h4_stage<R, TPB, 2, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        else h4_stage<R, TPB, 0, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
         __syncthreads();
     }
 }

@@ -16,9 +16,9 @@ namespace sv {
 // the tile (2^m amplitudes, only for multi-stage passes).
 // H4: 0 = three-bit register stages; four-bit stages (tile_h4.h) with
 // 1 = one-qubit gates, ladders and diagonals, 2 = Hadamards, ladders and
-// pattern diagonals only.
+// pattern diagonals only, 3 = Hadamards, real rotations and diagonals only.
 template <typename R, int TPB, int H4>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) void k_tile(V2<R> *__restrict__ slab, uint64_t dim, int nc,
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : (H4 == 3 ? 2 : 1)))) void k_tile(V2<R> *__restrict__ slab, uint64_t dim, int nc,
                                                    const int *__restrict__ ovr_idx,
                                                    const DevOp<R> *__restrict__ ovr,
                                                    const DevPass *__restrict__ passes, int pidx,
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
         tc.scale = (R)sc;
         tc.scaled = sc != 1.0;
         if constexpr (H4 != 0)
-            run_stages_h4<R, TPB, H4 == 1>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
+            run_stages_h4<R, TPB, H4>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
         else run_stages<R, TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
     }
 }
@@ -100,6 +100,7 @@ void launch_tile_tpb(Ctx *ctx, size_t lds, unsigned grid, V2<R> *slab, uint64_t 
     };
     if (h4 == 1) go(std::integral_constant<int, 1>{});
     else if (h4 == 2) go(std::integral_constant<int, 2>{});
+    else if (h4 == 3) go(std::integral_constant<int, 3>{});
     else go(std::integral_constant<int, 0>{});
     SV_HIP(hipGetLastError());
 }

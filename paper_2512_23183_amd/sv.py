@@ -51,6 +51,14 @@ class _Config(ctypes.Structure):
                 ("dense_fuse", ctypes.c_int32), ("graph_batch", ctypes.c_int32)]
 
 
+class _PlanStats(ctypes.Structure):
+    _fields_ = [("tile_passes", ctypes.c_int32), ("perm_passes", ctypes.c_int32),
+                ("sweep_passes", ctypes.c_int32), ("stages", ctypes.c_int32), ("ops", ctypes.c_int32),
+                ("tile_passes_by_engine", ctypes.c_int32 * 4), ("dense_blocks", ctypes.c_int32),
+                ("diagonal_tables", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("min_pass_scale", ctypes.c_double), ("max_pass_scale", ctypes.c_double)]
+
+
 class _Request(ctypes.Structure):
     _fields_ = [("want_grad", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("circuit", _Circuit), ("params", ctypes.c_void_p),
@@ -99,6 +107,11 @@ def lib():
             "sv_apply_circuit_ex": [_vp, ctypes.POINTER(_Circuit), _dp, ctypes.c_size_t,
                                     ctypes.c_uint32],
             "sv_apply_circuit_noalloc": [_vp, ctypes.POINTER(_Circuit), _dp, ctypes.c_size_t],
+            "sv_plan_info": [ctypes.POINTER(_Circuit), _dp, ctypes.c_size_t, ctypes.c_int,
+                             ctypes.POINTER(_Config), ctypes.POINTER(_PlanStats)],
+            "sv_plan_dump": [ctypes.POINTER(_Circuit), _dp, ctypes.c_size_t, ctypes.c_int,
+                             ctypes.POINTER(_Config), ctypes.c_char_p, ctypes.c_size_t,
+                             ctypes.POINTER(ctypes.c_size_t)],
             "sv_qft": [_vp],
             "sv_qft_ex": [_vp, ctypes.c_uint32],
             "sv_norm2": [_vp, _dp],
@@ -189,6 +202,40 @@ def check_circuit(circuit: Circuit, params=None) -> None:
 def check_pauli_sum(ham: PauliSum, n: int) -> None:
     h = _HamArgs(ham)
     _check(lib().sv_check_pauli_sum(ctypes.byref(h.h), n))
+
+
+def _config(**widths) -> "_Config":
+    names = [k for k, _ in _Config._fields_]
+    for k in widths:
+        if k not in names:
+            raise TypeError(f"unknown config field {k}")
+    return _Config(*[int(widths.get(k, 0)) for k in names])
+
+
+def plan_info(circuit: Circuit, params=None, dtype: int = C64, **widths) -> dict:
+    """sv_plan_info: what the fused apply of this circuit would run (host
+    only, no device): passes, stages, ops per engine."""
+    a = _CircArgs(circuit, params)
+    cfg = _config(**widths)
+    out = _PlanStats()
+    _check(lib().sv_plan_info(ctypes.byref(a.c), _dptr(a.params), a.params.size, dtype,
+                              ctypes.byref(cfg), ctypes.byref(out)))
+    d = {k: getattr(out, k) for k, _ in _PlanStats._fields_ if k != "reserved"}
+    d["tile_passes_by_engine"] = list(out.tile_passes_by_engine)
+    return d
+
+
+def plan_dump(circuit: Circuit, params=None, dtype: int = C64, **widths) -> str:
+    """sv_plan_dump: text listing of the plan (host only)."""
+    a = _CircArgs(circuit, params)
+    cfg = _config(**widths)
+    need = ctypes.c_size_t()
+    _check(lib().sv_plan_dump(ctypes.byref(a.c), _dptr(a.params), a.params.size, dtype,
+                              ctypes.byref(cfg), None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib().sv_plan_dump(ctypes.byref(a.c), _dptr(a.params), a.params.size, dtype,
+                              ctypes.byref(cfg), buf, need.value, None))
+    return buf.value.decode()
 
 
 def _np_dtype(dtype: int):
