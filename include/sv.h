@@ -371,12 +371,11 @@ typedef struct sv_plan_stats {
     int32_t sweep_passes;      /* one-gate sweeps (states of 1-2 qubits) */
     int32_t stages;            /* register stages over all tile passes */
     int32_t ops;               /* device ops over all tile passes */
-    int32_t tile_passes_by_engine[4]; /* [0] three-bit stages, four-bit stages:
+    int32_t tile_passes_by_engine[5]; /* [0] three-bit stages, four-bit stages:
                                  [1] general, [2] Hadamard / ladder,
-                                 [3] rotation / diagonal */
+                                 [3] rotation / diagonal, [4] rotation layers */
     int32_t dense_blocks;      /* dense 16x16 blocks applied with MFMA */
     int32_t diagonal_tables;   /* gathered stage diagonals */
-    int32_t reserved;
     double min_pass_scale, max_pass_scale; /* deferred real factors per pass */
 } sv_plan_stats;
 int sv_plan_info(const sv_circuit *circuit, const double *params, size_t n_params,

@@ -218,7 +218,7 @@ int sv_plan_info(const sv_circuit *circuit, const double *params, size_t n_param
         out->sweep_passes = sm.sweep_passes;
         out->stages = sm.stages;
         out->ops = sm.ops;
-        for (int i = 0; i < 4; ++i) out->tile_passes_by_engine[i] = sm.h4_passes[i];
+        for (int i = 0; i < 5; ++i) out->tile_passes_by_engine[i] = sm.h4_passes[i];
         out->dense_blocks = sm.dense_blocks;
         out->diagonal_tables = sm.tables;
         out->min_pass_scale = sm.tile_passes ? sm.min_scale : 1.0;

@@ -131,6 +131,8 @@ struct TileCtx {
     const SV_LDS R *Gs;       // per-tile ladder factors by op.tslot (re, im pairs), null = 1
     int lsa, lsb;             // ladder table split of the local bits
     bool zero;                // first global read synthesises |0...0>
+    V2<R> tf;                 // kind-4 passes: the tile's diagonal factor times
+    bool has_tf;              // the pass scale, applied by the last store instead
     const uint32_t *paux;     // stage layout-map tables (memory), or
     const SV_LDS uint32_t *pauxl;  // their LDS copy (non-null) holding entries from paux_off
     int paux_off;
@@ -1213,10 +1215,16 @@ inline int h4_kind(const std::vector<DevOp<R>> &ops, int ob, int oe, int m) {
 
 template <typename R>
 inline void build_stages_h4(std::vector<DevOp<R>> &ops, int ob, int oe, const std::vector<int> &local_bits,
-                            std::vector<DevStage> &out) {
+                            std::vector<DevStage> &out, bool layers = false) {
     const int m = (int)local_bits.size();
     int start = ob;
     std::vector<int> regs;
+    // layers: a stage also closes before a second mixing op on one bit, and
+    // before a mixing op on a bit of a diagonal that follows a mixing op of
+    // the stage on another of its bits (rotation-layer stages rotate each
+    // register bit once, with every diagonal before or after the rotations
+    // on its bits)
+    uint64_t rotated = 0, post = 0;
     auto close = [&](int end) {
         if (end <= start) return;
         for (int b = m - 1; b >= 0 && (int)regs.size() < 4; --b)
@@ -1273,10 +1281,24 @@ inline void build_stages_h4(std::vector<DevOp<R>> &ops, int ob, int oe, const st
     };
     for (int o = ob; o < oe; ++o) {
         const DevOp<R> &d = ops[o];
-        if ((d.kind != OP_U1 && d.kind != OP_XPERM) || std::find(regs.begin(), regs.end(), d.la) != regs.end())
+        if (layers && d.kind == OP_DIAG) {
+            const uint64_t bits = d.cmask | (1ull << d.a) | (d.b >= 0 ? (1ull << d.b) : 0ull);
+            if (bits & rotated) post |= bits;
             continue;
-        if ((int)regs.size() == 4) close(o);
-        regs.push_back(d.la);
+        }
+        if (d.kind != OP_U1 && d.kind != OP_XPERM) continue;
+        const bool have = std::find(regs.begin(), regs.end(), d.la) != regs.end();
+        if (layers && ((rotated | post) >> d.a) & 1) {
+            close(o);
+            rotated = post = 0;
+        } else if (have) {
+            continue;
+        } else if ((int)regs.size() == 4) {
+            close(o);
+            rotated = post = 0;
+        }
+        if (std::find(regs.begin(), regs.end(), d.la) == regs.end()) regs.push_back(d.la);
+        rotated |= 1ull << d.a;
     }
     close(oe);
 }
@@ -1435,6 +1457,193 @@ inline void gather_stage_diagonals(std::vector<DevOp<R>> &ops, std::vector<int> 
     oe = (int)out.size() - ((int)ops.size() - oe);
     ops.swap(out);
     gate.swap(gout);
+}
+
+// Rotation-layer stages (h4 kind 4): a pass of fixed real rotations and
+// fixed diagonals whose stages each rotate every register slot at most once
+// is rewritten so that each stage is straight-line code: a table of gathered
+// diagonals (OP_DIAG16), the four rotations (OP_ROT4, each in the form
+// c [[1, -t], [t, 1]] with c going to the pass scale), a second table, and
+// the group factor of the diagonals left on bits outside the registers.
+// Diagonals on bits outside the tile form one factor per tile, applied with
+// the pass scale by the last store.  Every diagonal is placed inside its
+// range: after the last rotation on one of its bits that precedes it and
+// before the first that follows it (diagonals commute with each other and
+// with rotations on other bits); placements that fold it into a table are
+// preferred.  Returns false (nothing changed) when the pass does not have
+// this form: then its stages keep the general loop (gather_stage_diagonals).
+template <typename R>
+inline bool build_rotation_layers(std::vector<DevOp<R>> &ops, std::vector<int> &gate, const std::vector<Op> &pops,
+                                  int ob, int oe, std::vector<DevStage> &stages, int sb,
+                                  const std::vector<int> &local_bits, DevPass &dp) {
+    const int NS = (int)stages.size() - sb;
+    if (NS <= 0) return false;
+    uint64_t localm = 0;
+    for (int b : local_bits) localm |= 1ull << b;
+    std::vector<int> st_of(oe - ob, -1);
+    for (int si = 0; si < NS; ++si)
+        for (int o = stages[sb + si].op_begin; o < stages[sb + si].op_end; ++o) st_of[o - ob] = si;
+    std::vector<uint64_t> regm(NS, 0);
+    for (int si = 0; si < NS; ++si) {
+        const DevStage &S = stages[sb + si];
+        const int regs[4] = {S.r0, S.r1, S.r2, S.r3};
+        for (int i = 0; i < 4; ++i) regm[si] |= 1ull << local_bits[regs[i]];
+    }
+    // rotations: t per (stage, slot), the pass scale and a bound on the growth
+    // of the unscaled amplitudes
+    std::vector<double> tv(4 * NS, 0.0);
+    std::vector<char> used(4 * NS, 0);
+    double scale = 1.0, growth = 1.0;
+    for (int o = ob; o < oe; ++o) {
+        const DevOp<R> &d = ops[o];
+        const Op &src = pops[o - ob];
+        if (st_of[o - ob] < 0 || src.param) return false;
+        if (d.kind == OP_DIAG) continue;
+        if (d.kind != OP_U1 || !(d.flags & (OPF_ROTC | OPF_ROTS))) return false;
+        const double c = src.m[0].real(), sn = src.m[2].real();
+        if (!(std::fabs(c) >= 1.0 / 4096.0 * std::fabs(sn)) || c == 0.0) return false;
+        const int slot = st_of[o - ob] * 4 + d.ra;
+        if (used[slot]) return false;
+        used[slot] = 1;
+        tv[slot] = sn / c;
+        scale *= c;
+        growth *= 1.0 + std::fabs(sn / c);
+    }
+    if (growth > (sizeof(R) == 4 ? 1e30 : 1e290)) return false;
+    // placements of the diagonals: stage, and 0 = table before the
+    // rotations, 1 = after them, 2 = group factor, 3 = tile factor
+    struct Place { int o, stage, where, r; uint64_t outb; };
+    std::vector<Place> pl;
+    auto rot_bits = [&](int o) { return 1ull << ops[o].a; };
+    for (int o = ob; o < oe; ++o) {
+        if (ops[o].kind != OP_DIAG) continue;
+        const Op &src = pops[o - ob];
+        const uint64_t bits = src.cmask | (1ull << src.a) | (src.b >= 0 ? (1ull << src.b) : 0ull);
+        if ((bits & localm) == 0) {
+            pl.push_back({o, -1, 3, -1, 0});
+            continue;
+        }
+        int s_lo = -1, s_hi = NS;
+        for (int q = o - 1; q >= ob; --q)
+            if (ops[q].kind == OP_U1 && (rot_bits(q) & bits)) { s_lo = st_of[q - ob]; break; }
+        for (int q = o + 1; q < oe; ++q)
+            if (ops[q].kind == OP_U1 && (rot_bits(q) & bits)) { s_hi = st_of[q - ob]; break; }
+        if (s_lo >= 0 && s_lo == s_hi) return false;
+        const bool pat_neg = (ops[o].flags & OPF_PAT) && (ops[o].flags & OPF_NEG);
+        auto fold = [&](int si, int &r, uint64_t &outb) {
+            const uint64_t A = bits & regm[si], B = bits & ~regm[si];
+            if (B == 0) { r = -1; outb = 0; return true; }
+            if (pat_neg && __builtin_popcountll(A) == 1 && __builtin_popcountll(B) == 1) {
+                const DevStage &S = stages[sb + si];
+                const int regs[4] = {S.r0, S.r1, S.r2, S.r3};
+                for (int i = 0; i < 4; ++i)
+                    if ((1ull << local_bits[regs[i]]) == A) r = i;
+                outb = B;
+                return true;
+            }
+            return false;
+        };
+        bool done = false;
+        int r = -1;
+        uint64_t outb = 0;
+        // after the stage of its last preceding rotation, before the stage
+        // of its next one, then any other table, then a group factor
+        if (s_lo >= 0 && s_lo < s_hi && fold(s_lo, r, outb)) { pl.push_back({o, s_lo, 1, r, outb}); done = true; }
+        if (!done && s_hi < NS && s_hi > s_lo && fold(s_hi, r, outb)) { pl.push_back({o, s_hi, 0, r, outb}); done = true; }
+        for (int si = std::max(s_lo, 0); !done && si < std::min(s_hi, NS); ++si)
+            if (si >= s_lo && fold(si, r, outb)) { pl.push_back({o, si, 1, r, outb}); done = true; }
+        for (int si = s_lo + 1; !done && si <= std::min(s_hi, NS - 1); ++si)
+            if (fold(si, r, outb)) { pl.push_back({o, si, 0, r, outb}); done = true; }
+        for (int si = s_lo + 1; !done && si < std::min(s_hi, NS); ++si)
+            if ((bits & regm[si]) == 0) { pl.push_back({o, si, 2, -1, 0}); done = true; }
+        if (!done) return false;
+    }
+    // rebuild the pass's ops: per stage its group-factor diagonals, tables
+    // and rotations; then the tile-factor diagonals
+    std::vector<DevOp<R>> out(ops.begin(), ops.begin() + ob);
+    std::vector<int> gout(gate.begin(), gate.begin() + ob);
+    auto table = [&](int si, int where) -> int {
+        cd T[16];
+        for (int e = 0; e < 16; ++e) T[e] = 1.0;
+        uint64_t M[4] = {0, 0, 0, 0};
+        bool any = false;
+        const DevStage &S = stages[sb + si];
+        const int regs[4] = {S.r0, S.r1, S.r2, S.r3};
+        for (const Place &p : pl) {
+            if (p.stage != si || p.where != where) continue;
+            any = true;
+            if (p.r >= 0) {
+                M[p.r] ^= p.outb;
+                continue;
+            }
+            const Op &src = pops[p.o - ob];
+            for (int e = 0; e < 16; ++e) {
+                uint64_t k = 0;
+                for (int i = 0; i < 4; ++i)
+                    if ((e >> i) & 1) k |= 1ull << local_bits[regs[i]];
+                if ((k & src.cmask) != src.cmask) continue;
+                const int ba = (k >> src.a) & 1;
+                T[e] *= src.b >= 0 ? src.m[2 * ba + (int)((k >> src.b) & 1)] : src.m[ba];
+            }
+        }
+        if (!any) return -1;
+        DevOp<R> t;
+        std::memset(&t, 0, sizeof t);
+        t.kind = OP_DIAG16;
+        t.a = t.b = t.la = t.lb = t.ra = t.rb = -1;
+        t.tab = -1;
+        for (int e = 0; e < 16; ++e) {
+            t.m[2 * e] = (R)T[e].real();
+            t.m[2 * e + 1] = (R)T[e].imag();
+        }
+        t.cmask = M[0];
+        t.lcmask = M[1];
+        t.gcmask = M[2];
+        t.lmask = M[3];
+        if (M[0] | M[1] | M[2] | M[3]) t.flags |= OPF_SGN;
+        out.push_back(t);
+        gout.push_back(-1);
+        return (int)out.size() - 1;
+    };
+    for (int si = 0; si < NS; ++si) {
+        DevStage &S = stages[sb + si];
+        S.op_begin = (int)out.size();
+        for (const Place &p : pl)
+            if (p.stage == si && p.where == 2) {
+                out.push_back(ops[p.o]);
+                gout.push_back(gate[p.o]);
+            }
+        S.op_end = (int)out.size();
+        S.acc = S.op_end > S.op_begin ? 1 : 0;
+        S.tpre = table(si, 0);
+        S.tpost = table(si, 1);
+        DevOp<R> q;
+        std::memset(&q, 0, sizeof q);
+        q.kind = OP_ROT4;
+        q.a = q.b = q.la = q.lb = q.ra = q.rb = -1;
+        q.tab = -1;
+        for (int i = 0; i < 4; ++i) q.m[2 * i] = (R)tv[4 * si + i];
+        out.push_back(q);
+        gout.push_back(-1);
+        S.rot = (int)out.size() - 1;
+    }
+    dp.tf_begin = (int)out.size();
+    for (const Place &p : pl)
+        if (p.where == 3) {
+            out.push_back(ops[p.o]);
+            gout.push_back(gate[p.o]);
+        }
+    dp.tf_end = (int)out.size();
+    for (int o = oe; o < (int)ops.size(); ++o) {
+        out.push_back(ops[o]);
+        gout.push_back(gate[o]);
+    }
+    dp.op_end = (int)out.size() - ((int)ops.size() - oe);
+    dp.scale = scale;
+    dp.h4 = 4;
+    ops.swap(out);
+    gate.swap(gout);
+    return true;
 }
 
 template <typename R>

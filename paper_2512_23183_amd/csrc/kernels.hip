@@ -901,8 +901,10 @@ DevPlanHost<R> build_dev_plan(const Plan &plan) {
         // four-bit stages
         dp.h4 = ps.kind == PASS_TILE ? h4_kind<R>(h.dops, b, (int)h.dops.size(), ps.m) : 0;
         if (dp.h4) {
-            build_stages_h4<R>(h.dops, b, (int)h.dops.size(), ps.local_bits, h.dstages);
-            if (dp.h4 == 3) {
+            build_stages_h4<R>(h.dops, b, (int)h.dops.size(), ps.local_bits, h.dstages, dp.h4 == 3);
+            if (dp.h4 == 3 &&
+                !build_rotation_layers<R>(h.dops, h.gate, ps.ops, b, (int)h.dops.size(), h.dstages, dp.stage_begin,
+                                          ps.local_bits, dp)) {
                 int oe = (int)h.dops.size();
                 gather_stage_diagonals<R>(h.dops, h.gate, ps.ops, b, oe, h.dstages, dp.stage_begin, ps.local_bits);
                 dp.op_end = oe;
@@ -948,9 +950,10 @@ PlanSummary summarize_plan(const Plan &plan, std::string *text) {
             continue;
         }
         ++sm.tile_passes;
-        sm.h4_passes[std::max(0, std::min(3, dp.h4))] += 1;
+        sm.h4_passes[std::max(0, std::min(4, dp.h4))] += 1;
         sm.stages += dp.stage_end - dp.stage_begin;
         sm.ops += dp.op_end - dp.op_begin;
+        if (dp.h4 == 4) sm.tile_factor_ops += dp.tf_end - dp.tf_begin;
         sm.min_scale = std::min(sm.min_scale, std::fabs(dp.scale));
         sm.max_scale = std::max(sm.max_scale, std::fabs(dp.scale));
         if (text) {
@@ -964,6 +967,18 @@ PlanSummary summarize_plan(const Plan &plan, std::string *text) {
                 std::snprintf(line, sizeof line, "  stage regs=%d,%d,%d,%d ops=[%d,%d) acc=%d mfma=%d perm=%d\n", S.r0,
                               S.r1, S.r2, dp.h4 ? S.r3 : -1, S.op_begin, S.op_end, S.acc, S.mfma, S.perm);
                 *text += line;
+            }
+            if (dp.h4 == 4) {
+                // rotation layer: tables before and after the four rotations
+                sm.tables += (S.tpre >= 0) + (S.tpost >= 0);
+                if (text) {
+                    const DevOp<R> &q = h.dops[S.rot];
+                    std::snprintf(line, sizeof line, "    layer pre=%d t=(%.4g %.4g %.4g %.4g) post=%d\n",
+                                  S.tpre >= 0 ? (h.dops[S.tpre].flags & OPF_SGN ? 2 : 1) : 0, (double)q.m[0],
+                                  (double)q.m[2], (double)q.m[4], (double)q.m[6],
+                                  S.tpost >= 0 ? (h.dops[S.tpost].flags & OPF_SGN ? 2 : 1) : 0);
+                    *text += line;
+                }
             }
             for (int o = S.op_begin; o < S.op_end; ++o) {
                 const DevOp<R> &op = h.dops[o];

@@ -55,6 +55,10 @@ enum OpKind : int32_t {
     OP_DENSE4 = 6,  // dense 16x16 matrix (Plan::dense[dense]) on the four bits
                     // of lmask, pattern bit k = the k-th lowest of them; made
                     // by the planner from runs of fixed gates (MFMA stages)
+    OP_ROT4 = 8,    // device only: the four real rotations of a rotation-layer
+                    // stage, slot i: (x, y) <- (x - t y, y + t x) with t in the
+                    // real part of complex entry i (0 = none); their cosines are
+                    // in the pass scale
     OP_DIAG16 = 7,  // device only: the gathered diagonals of a four-bit stage,
                     // element e of a register group *= m[e] (complex), negated
                     // where the parity of e & c is odd; bit r of c is the
@@ -184,7 +188,11 @@ struct alignas(16) DevStage {
     int32_t mfma;     // 1: the stage is one OP_DENSE4 op on bits r0 < r1 < r2 < r3
     int32_t r3;
     int32_t wtab;     // MFMA stage: its 32x32 real matrix in the plan's float table
-    int32_t pad[3];
+    // rotation-layer stages (four-bit kind 4): op indices of the table
+    // applied before the rotations, of the one after them, and of the
+    // OP_ROT4 op holding the four rotations (-1 = none); the stage's op
+    // range then lists the diagonals that feed the group factor
+    int32_t tpre, tpost, rot;
     uint16_t pd[8];
 };
 
@@ -205,7 +213,10 @@ struct alignas(16) DevPass {
     int32_t ltab_begin, ltab_count;  // TILE: their phase tables in the plan's table array
     int32_t paux_begin, paux_count;  // TILE: its stages' layout-map tables (32-bit aux array)
     int32_t paux_lds;                // TILE: 1 = those tables are copied to LDS
-    int32_t h4;                      // TILE: four-bit stages (1 general, 2 Hadamard / ladder only)
+    int32_t h4;                      // TILE: four-bit stages (1 general, 2 Hadamard / ladder only,
+                                     // 3 rotation / diagonal, 4 rotation layers)
+    int32_t tf_begin, tf_end;        // kind 4: diagonals on bits outside the tile (one
+                                     // factor per tile, applied with the pass scale)
 };
 
 // ---------------------------------------------------------------------------
@@ -344,8 +355,8 @@ void run_plan(Ctx *ctx, State *st, const Plan &plan);
 // What a device plan holds (host only: sv_plan_info / sv_plan_dump).
 struct PlanSummary {
     int sweep_passes = 0, tile_passes = 0, perm_passes = 0, stages = 0, ops = 0;
-    int h4_passes[4] = {0, 0, 0, 0};
-    int dense_blocks = 0, tables = 0;
+    int h4_passes[5] = {0, 0, 0, 0, 0};
+    int dense_blocks = 0, tables = 0, tile_factor_ops = 0;
     double min_scale = 1e300, max_scale = 0.0;
 };
 template <typename R>

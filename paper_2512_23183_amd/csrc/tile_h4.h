@@ -87,12 +87,15 @@ __device__ __forceinline__ void h4_u1_at(V2<R> (&v)[16], const DevOp<R> &op) {
 // Diagonal amplitude *= d[2 bit_a + bit_b] (d[bit_a] without b) where all
 // control bits are set; each of a, b and the controls is a register slot
 // (taken from e) or a bit of the group (taken from k0).
+// The group-bit conditions differ between the lanes of a wave: they are
+// applied as selects, not branches (a divergent branch around the sixteen
+// amplitudes would make the compiler copy all of them at the join).
 template <typename R>
 __device__ __forceinline__ void h4_diag(V2<R> (&v)[16], V2<R> &acc, uint64_t k0, const uint64_t (&G)[4],
                                         const DevOp<R> &op) {
     const uint64_t regs = G[0] | G[1] | G[2] | G[3];
     const uint64_t gc = op.cmask & ~regs;
-    if ((k0 & gc) != gc) return;
+    const bool gon = (k0 & gc) == gc;
     const uint32_t ec = ((op.cmask & G[0]) ? 1u : 0u) | ((op.cmask & G[1]) ? 2u : 0u) |
                         ((op.cmask & G[2]) ? 4u : 0u) | ((op.cmask & G[3]) ? 8u : 0u);
     auto slot = [&](int bitpos) {
@@ -104,7 +107,7 @@ __device__ __forceinline__ void h4_diag(V2<R> (&v)[16], V2<R> &acc, uint64_t k0,
     const V2<R> d0 = mat_at(op, 0), d1 = mat_at(op, 1), d2 = mat_at(op, 2), d3 = mat_at(op, 3);
     if (sa < 0 && sb < 0 && ec == 0) {
         const V2<R> f = op.b >= 0 ? vsel(ga != 0, vsel(gb != 0, d3, d2), vsel(gb != 0, d1, d0)) : vsel(ga != 0, d1, d0);
-        acc = cmul(acc, f);
+        acc = vsel(gon, cmul(acc, f), acc);
         return;
     }
     static_for<0, 16>([&](auto EC) {
@@ -117,9 +120,42 @@ __device__ __forceinline__ void h4_diag(V2<R> (&v)[16], V2<R> &acc, uint64_t k0,
         } else {
             f = vsel(ba != 0, d1, d0);
         }
-        const bool on = ((uint32_t)e & ec) == ec;
+        const bool on = gon && ((uint32_t)e & ec) == ec;
         v[e] = vsel(on, cmul(v[e], f), v[e]);
     });
+}
+
+// Scaled real rotation on register slot I: (x, y) <- (x - t y, y + t x)
+// (t = 0: identity); the cosine factor is in the pass scale.
+template <int I, typename R>
+__device__ __forceinline__ void h4_rot(V2<R> (&v)[16], R t) {
+    static_for<0, 16>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        if constexpr (!(e & (1 << I))) {
+            constexpr int f = e | (1 << I);
+            const V2<R> x = v[e], y = v[f];
+            v[e].x = x.x - t * y.x;
+            v[e].y = x.y - t * y.y;
+            v[f].x = y.x + t * x.x;
+            v[f].y = y.y + t * x.y;
+        }
+    });
+}
+
+// Factor of a diagonal on bits outside the registers for the group at k0
+// (a select per lane, not a branch).
+template <typename R>
+__device__ __forceinline__ void diag_factor(V2<R> &acc, uint64_t k, const DevOp<R> &op) {
+    const bool on = (k & op.cmask) == op.cmask;
+    const uint32_t ba = (uint32_t)((k >> op.a) & 1);
+    V2<R> f;
+    if (op.b >= 0) {
+        const uint32_t bb = (uint32_t)((k >> op.b) & 1);
+        f = vsel(ba != 0, vsel(bb != 0, mat_at(op, 3), mat_at(op, 2)), vsel(bb != 0, mat_at(op, 1), mat_at(op, 0)));
+    } else {
+        f = vsel(ba != 0, mat_at(op, 1), mat_at(op, 0));
+    }
+    acc = vsel(on, cmul(acc, f), acc);
 }
 
 // Uncontrolled one-qubit diagonal diag(d0, d1) on register slot I: d0 goes
@@ -194,22 +230,22 @@ __device__ __forceinline__ void h4_pat(V2<R> (&v)[16], V2<R> &acc, uint64_t k0, 
                                        const DevOp<R> &op) {
     const uint64_t all = op.cmask | (1ull << op.a) | (op.b >= 0 ? (1ull << op.b) : 0ull);
     const uint64_t gmask = all & ~(G[0] | G[1] | G[2] | G[3]);
-    if ((k0 & gmask) != gmask) return;
+    const bool gon = (k0 & gmask) == gmask;  // per lane: a select, not a branch
     const uint32_t emask = ((all & G[0]) ? 1u : 0u) | ((all & G[1]) ? 2u : 0u) | ((all & G[2]) ? 4u : 0u) |
                            ((all & G[3]) ? 8u : 0u);
     const V2<R> dl = op.b >= 0 ? mat_at(op, 3) : mat_at(op, 1);
     if (ACC && emask == 0) {
         if constexpr (NEG) {
-            acc.x = -acc.x;
-            acc.y = -acc.y;
+            acc.x = gon ? -acc.x : acc.x;
+            acc.y = gon ? -acc.y : acc.y;
         } else {
-            acc = cmul(acc, dl);
+            acc = vsel(gon, cmul(acc, dl), acc);
         }
         return;
     }
     static_for<0, 16>([&](auto EC) {
         constexpr int e = decltype(EC)::value;
-        const bool on = ((uint32_t)e & emask) == emask;
+        const bool on = gon && ((uint32_t)e & emask) == emask;
         if constexpr (NEG) {
             v[e].x = on ? -v[e].x : v[e].x;
             v[e].y = on ? -v[e].y : v[e].y;
@@ -273,7 +309,18 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
         V2<R> acc;
         acc.x = (R)1;
         acc.y = (R)0;
-        for (int o = S.op_begin; o < S.op_end; ++o) {
+        if constexpr (KIND == 4) {
+            // a rotation layer: straight-line code (no op loop)
+            for (int o = S.op_begin; o < S.op_end; ++o) diag_factor(acc, k0, ops[o]);
+            if (S.tpre >= 0) h4_table(v, k0, ops[S.tpre]);
+            const DevOp<R> &q = ops[S.rot];
+            h4_rot<0>(v, q.m[0]);
+            h4_rot<1>(v, q.m[2]);
+            h4_rot<2>(v, q.m[4]);
+            h4_rot<3>(v, q.m[6]);
+            if (S.tpost >= 0) h4_table(v, k0, ops[S.tpost]);
+        }
+        for (int o = S.op_begin; KIND != 4 && o < S.op_end; ++o) {
             const DevOp<R> &op = (o == ovr_index) ? *ovr : ops[o];
             if constexpr (KIND == 3) {
                 if (op.kind == OP_DIAG16) {
@@ -349,7 +396,12 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
             }
         }
         if constexpr (MODE & 2) {
-            if (tc.scaled) {
+            if (KIND == 4 && tc.has_tf) {
+                static_for<0, 16>([&](auto EC) {
+                    constexpr int e = decltype(EC)::value;
+                    v[e] = cmul(v[e], tc.tf);
+                });
+            } else if (tc.scaled) {
                 static_for<0, 16>([&](auto EC) {
                     constexpr int e = decltype(EC)::value;
                     v[e].x *= tc.scale;

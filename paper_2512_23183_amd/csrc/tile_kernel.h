@@ -16,9 +16,10 @@ namespace sv {
 // the tile (2^m amplitudes, only for multi-stage passes).
 // H4: 0 = three-bit register stages; four-bit stages (tile_h4.h) with
 // 1 = one-qubit gates, ladders and diagonals, 2 = Hadamards, ladders and
-// pattern diagonals only, 3 = Hadamards, real rotations and diagonals only.
+// pattern diagonals only, 3 = Hadamards, real rotations and diagonals only,
+// 4 = rotation layers (straight-line stages, see build_rotation_layers).
 template <typename R, int TPB, int H4>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : (H4 == 3 ? 2 : 1)))) void k_tile(V2<R> *__restrict__ slab, uint64_t dim, int nc,
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : (H4 >= 3 ? 2 : 1)))) void k_tile(V2<R> *__restrict__ slab, uint64_t dim, int nc,
                                                    const int *__restrict__ ovr_idx,
                                                    const DevOp<R> *__restrict__ ovr,
                                                    const DevPass *__restrict__ passes, int pidx,
@@ -82,6 +83,20 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
         const double sc = (oi >= P.op_begin && oi < P.op_end) ? ovr[c].pscale : P.scale;
         tc.scale = (R)sc;
         tc.scaled = sc != 1.0;
+        tc.has_tf = false;
+        if constexpr (H4 == 4) {
+            // the tile's factor of the diagonals on bits outside it, times
+            // the pass scale (one complex multiply in the last store)
+            if (P.tf_end > P.tf_begin) {
+                V2<R> f;
+                f.x = (R)1;
+                f.y = (R)0;
+                for (int o = P.tf_begin; o < P.tf_end; ++o) diag_factor(f, tc.base, ops[o]);
+                tc.tf.x = f.x * tc.scale;
+                tc.tf.y = f.y * tc.scale;
+                tc.has_tf = true;
+            }
+        }
         if constexpr (H4 != 0)
             run_stages_h4<R, TPB, H4>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
         else run_stages<R, TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
@@ -101,6 +116,7 @@ void launch_tile_tpb(Ctx *ctx, size_t lds, unsigned grid, V2<R> *slab, uint64_t 
     if (h4 == 1) go(std::integral_constant<int, 1>{});
     else if (h4 == 2) go(std::integral_constant<int, 2>{});
     else if (h4 == 3) go(std::integral_constant<int, 3>{});
+    else if (h4 == 4) go(std::integral_constant<int, 4>{});
     else go(std::integral_constant<int, 0>{});
     SV_HIP(hipGetLastError());
 }

@@ -54,8 +54,8 @@ class _Config(ctypes.Structure):
 class _PlanStats(ctypes.Structure):
     _fields_ = [("tile_passes", ctypes.c_int32), ("perm_passes", ctypes.c_int32),
                 ("sweep_passes", ctypes.c_int32), ("stages", ctypes.c_int32), ("ops", ctypes.c_int32),
-                ("tile_passes_by_engine", ctypes.c_int32 * 4), ("dense_blocks", ctypes.c_int32),
-                ("diagonal_tables", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tile_passes_by_engine", ctypes.c_int32 * 5), ("dense_blocks", ctypes.c_int32),
+                ("diagonal_tables", ctypes.c_int32),
                 ("min_pass_scale", ctypes.c_double), ("max_pass_scale", ctypes.c_double)]
 
 
@@ -220,7 +220,7 @@ def plan_info(circuit: Circuit, params=None, dtype: int = C64, **widths) -> dict
     out = _PlanStats()
     _check(lib().sv_plan_info(ctypes.byref(a.c), _dptr(a.params), a.params.size, dtype,
                               ctypes.byref(cfg), ctypes.byref(out)))
-    d = {k: getattr(out, k) for k, _ in _PlanStats._fields_ if k != "reserved"}
+    d = {k: getattr(out, k) for k, _ in _PlanStats._fields_}
     d["tile_passes_by_engine"] = list(out.tile_passes_by_engine)
     return d
 
