@@ -1617,6 +1617,20 @@ inline bool build_rotation_layers(std::vector<DevOp<R>> &ops, std::vector<int> &
         S.acc = S.op_end > S.op_begin ? 1 : 0;
         S.tpre = table(si, 0);
         S.tpost = table(si, 1);
+        if (S.tpost < 0) {
+            // every layer ends with a table (its code has no branch on it)
+            DevOp<R> t;
+            std::memset(&t, 0, sizeof t);
+            t.kind = OP_DIAG16;
+            t.a = t.b = t.la = t.lb = t.ra = t.rb = -1;
+            t.tab = -1;
+            for (int e = 0; e < 16; ++e) t.m[2 * e] = (R)1;
+            out.push_back(t);
+            gout.push_back(-1);
+            S.tpost = (int)out.size() - 1;
+        }
+        const bool sgn = (out[S.tpost].flags & OPF_SGN) || (S.tpre >= 0 && (out[S.tpre].flags & OPF_SGN));
+        S.rl = (S.tpre >= 0 ? 1 : 0) | (sgn ? 2 : 0) | (S.acc ? 4 : 0);
         DevOp<R> q;
         std::memset(&q, 0, sizeof q);
         q.kind = OP_ROT4;

@@ -193,6 +193,9 @@ struct alignas(16) DevStage {
     // OP_ROT4 op holding the four rotations (-1 = none); the stage's op
     // range then lists the diagonals that feed the group factor
     int32_t tpre, tpost, rot;
+    int32_t rl;       // rotation-layer code variant: 1 = a table before the
+                      // rotations, 2 = sign couplings in its tables, 4 = a
+                      // group factor
     uint16_t pd[8];
 };
 

@@ -5,6 +5,8 @@
 // of h mixing gates' bits takes ceil(h / 4) stages and ceil(h / 4) - 1 LDS
 // round trips, and the op loop knows only these kinds.
 #pragma once
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace sv {
@@ -193,6 +195,29 @@ __device__ __forceinline__ void h4_table(V2<R> (&v)[16], uint64_t k0, const DevO
     });
 }
 
+// The same with the sign variant fixed at compile time; the signs go to
+// the sign bits of the products (no select on the table entries).
+template <bool SGN, typename R>
+__device__ __forceinline__ void rl_table(V2<R> (&v)[16], uint64_t k0, const DevOp<R> &op) {
+    using U = typename std::conditional<sizeof(R) == 4, uint32_t, uint64_t>::type;
+    uint32_t neg = 0;
+    if constexpr (SGN) {
+        const uint32_t c0 = __popcll(k0 & op.cmask) & 1, c1 = __popcll(k0 & op.lcmask) & 1,
+                       c2 = __popcll(k0 & op.gcmask) & 1, c3 = __popcll(k0 & op.lmask) & 1;
+        neg = (c0 ? 0xAAAAu : 0u) ^ (c1 ? 0xCCCCu : 0u) ^ (c2 ? 0xF0F0u : 0u) ^ (c3 ? 0xFF00u : 0u);
+    }
+    static_for<0, 16>([&](auto EC) {
+        constexpr int e = decltype(EC)::value;
+        V2<R> w = cmul(v[e], mat_at(op, e));
+        if constexpr (SGN) {
+            const U sb = (U)((neg >> e) & 1u) << (8 * sizeof(R) - 1);
+            w.x = __builtin_bit_cast(R, __builtin_bit_cast(U, w.x) ^ sb);
+            w.y = __builtin_bit_cast(R, __builtin_bit_cast(U, w.y) ^ sb);
+        }
+        v[e] = w;
+    });
+}
+
 // Ladder: where bit a is set, multiply by exp(2 pi i turns (k & lmask)) =
 // (group phase from the tile-independent tables and the tile factor) x K_e
 // (the phase of element e's register-bit offset, complex slot e of op.m).
@@ -263,7 +288,7 @@ __device__ __forceinline__ void h4_pat(V2<R> (&v)[16], V2<R> &acc, uint64_t k0, 
 // diagonals only (layered circuits once their one-qubit gates are split
 // into rotations and phases).  The smaller op loops of 2 and 3 keep the
 // sixteen amplitudes and the op data in registers without spilling.
-template <typename R, int TPB, int MODE, int KIND>
+template <typename R, int TPB, int MODE, int KIND, int RL = 0>
 __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
                                          const DevStage &S, const DevOp<R> *__restrict__ ops, int ovr_index,
                                          const DevOp<R> *ovr) {
@@ -310,15 +335,17 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
         acc.x = (R)1;
         acc.y = (R)0;
         if constexpr (KIND == 4) {
-            // a rotation layer: straight-line code (no op loop)
-            for (int o = S.op_begin; o < S.op_end; ++o) diag_factor(acc, k0, ops[o]);
-            if (S.tpre >= 0) h4_table(v, k0, ops[S.tpre]);
+            // a rotation layer: straight-line code, its variant (RL) fixed at
+            // compile time
+            if constexpr (RL & 4)
+                for (int o = S.op_begin; o < S.op_end; ++o) diag_factor(acc, k0, ops[o]);
+            if constexpr (RL & 1) rl_table<(RL & 2) != 0>(v, k0, ops[S.tpre]);
             const DevOp<R> &q = ops[S.rot];
             h4_rot<0>(v, q.m[0]);
             h4_rot<1>(v, q.m[2]);
             h4_rot<2>(v, q.m[4]);
             h4_rot<3>(v, q.m[6]);
-            if (S.tpost >= 0) h4_table(v, k0, ops[S.tpost]);
+            rl_table<(RL & 2) != 0>(v, k0, ops[S.tpost]);
         }
         for (int o = S.op_begin; KIND != 4 && o < S.op_end; ++o) {
             const DevOp<R> &op = (o == ovr_index) ? *ovr : ops[o];
@@ -386,7 +413,14 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
                 h4_diag(v, acc, k0, G, op);
             }
         }
-        if constexpr (GEN) {
+        if constexpr (KIND == 4) {
+            if constexpr (RL & 4) {
+                static_for<0, 16>([&](auto EC) {
+                    constexpr int e = decltype(EC)::value;
+                    v[e] = cmul(v[e], acc);
+                });
+            }
+        } else if constexpr (GEN) {
             // acc is exactly 1 unless a diagonal of the stage contributed
             if (S.acc) {
                 static_for<0, 16>([&](auto EC) {
@@ -435,10 +469,32 @@ __device__ __forceinline__ void run_stages_h4(V2<R> *tile, V2<R> *__restrict__ g
     for (int s = sb; s < se; ++s) {
         const DevStage &S = stages[s];
         const bool first = s == sb, last = s == se - 1;
-        if (first && last) h4_stage<R, TPB, 3, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
-        else if (first) h4_stage<R, TPB, 1, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
-        else if (last) h4_stage<R, TPB, 2, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
-        else h4_stage<R, TPB, 0, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        if constexpr (KIND == 4) {
+            // one straight-line body per (first, last, variant): the choice
+            // is made here, outside the loop over register groups
+            auto go = [&](auto MC) {
+                constexpr int MODE = decltype(MC)::value;
+                switch (S.rl) {
+                case 0: h4_stage<R, TPB, MODE, 4, 0>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                case 1: h4_stage<R, TPB, MODE, 4, 1>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                case 2: h4_stage<R, TPB, MODE, 4, 2>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                case 3: h4_stage<R, TPB, MODE, 4, 3>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                case 4: h4_stage<R, TPB, MODE, 4, 4>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                case 5: h4_stage<R, TPB, MODE, 4, 5>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                case 6: h4_stage<R, TPB, MODE, 4, 6>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                default: h4_stage<R, TPB, MODE, 4, 7>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                }
+            };
+            if (first && last) go(std::integral_constant<int, 3>{});
+            else if (first) go(std::integral_constant<int, 1>{});
+            else if (last) go(std::integral_constant<int, 2>{});
+            else go(std::integral_constant<int, 0>{});
+        } else {
+            if (first && last) h4_stage<R, TPB, 3, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+            else if (first) h4_stage<R, TPB, 1, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+            else if (last) h4_stage<R, TPB, 2, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+            else h4_stage<R, TPB, 0, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+        }
         __syncthreads();
     }
 }
