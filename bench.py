@@ -1,31 +1,35 @@
 """Benchmark: state-vector hot path on one MI355X.
 
-Headline workload (one "step"): the gate-based QFT (H, controlled phases,
-final swaps; 420 logical gates) applied to a resident 28-qubit complex64
-state with i.i.d. complex Gaussian amplitudes (seed 2).  Metric: amplitude
-updates per second = logical gates x 2^n per step / time.
-
-roofline also carries a measured streaming ceiling (read + write GB/s of the
-faster of a plain 2 GiB device copy and an out-of-place negation) and the
-tile pass's fraction of it.
+Headline workload (one "step"): the deep random circuit of 40 layers (U3
+with angles U[0, 2 pi)^3 on each of 30 qubits, then CZ on a fresh random
+perfect matching; 1800 logical gates, seed 4) applied to a resident
+30-qubit complex128 state (16 GiB, the paper's FP64 complex amplitudes),
+reset to |0...0> at the start of every step.  Metric: amplitude updates per
+second = logical gates x 2^n per step / time.  The roofline block describes
+the fused tile pass that carries the whole circuit: algorithmic bytes (one
+read and one write of the state per pass) over its average launch time
+(HIP events on its stream), against 8 TB/s HBM; the arithmetic it issues
+per amplitude and its fraction of the FP64 vector peak go beside it.
 
 Extras in the same JSON line (each bounded in time):
-  headline   touched amplitude-updates/s (2^n per H, 2^(n-2) per CP,
-             2^(n-1) per SWAP), permutation pass time, GB/s over all passes
-  qft        20/24/28 qubits at complex64 and complex128, fused and one
-             launch per gate, GB/s per pass (states of at most 256 MiB
-             stay in the Infinity Cache: marked cache_resident)
-  grad10     10-qubit complex128 VQE gradient (161 circuits): batched vs one
-             circuit at a time
-  vqe10      the same ansatz and Hamiltonian minimised by Adam (lr 1e-2, at
-             most 350 iterations, tolerance 1e-7), one gradient per iteration
-  grad20     20-qubit complex64 gradient, 8 layers (641 circuits), 200-term
-             random 2-local Hamiltonian: batched vs one circuit at a time
-  sweeps     single-gate sweeps on an 8 GiB state: GB/s per gate and bit
-  trotter    26-qubit XYZ-chain time evolution (20 first-order Trotter steps)
-  deep30     30-qubit complex64 depth-40 U3 + CZ circuit: fused vs unfused
-  serving    Poisson stream of mixed requests through the serving queue
-             (bounded sample), p50/p99 latency vs a serial loop
+  deep30_c64      the same circuit on a complex64 state (the precision the
+                  configuration names): fused and one launch per gate, with
+                  the fused pass's roofline block
+  qft28_c64/c128  gate-based QFT of the seeded 28-qubit Gaussian state: time,
+                  passes and the tile pass's roofline block
+  qft             20/24/28 qubits at complex64 and complex128, fused and one
+                  launch per gate, GB/s per pass (states of at most 256 MiB
+                  stay in the Infinity Cache: marked cache_resident)
+  grad10          10-qubit complex128 VQE gradient (161 circuits): batched vs one
+                  circuit at a time
+  vqe10           the same ansatz and Hamiltonian minimised by Adam (lr 1e-2, at
+                  most 350 iterations, tolerance 1e-7), one gradient per iteration
+  grad20          20-qubit complex64 gradient, 8 layers (641 circuits), 200-term
+                  random 2-local Hamiltonian: batched vs one circuit at a time
+  sweeps          single-gate sweeps on an 8 GiB state: GB/s per gate and bit
+  trotter         26-qubit XYZ-chain time evolution (20 first-order Trotter steps)
+  serving         Poisson stream of mixed requests through the serving queue
+                  (bounded sample), p50/p99 latency vs a serial loop
   cpu_oracle_1thread  the oracle QFT at 24 qubits on one host thread
 """
 from __future__ import annotations
@@ -44,6 +48,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz)
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector with packed FP32 (the library does not emit packed FP32)
+DEEP_N, DEEP_DEPTH, DEEP_SEED = 30, 40, 4
 
 
 def log(*a):
@@ -90,27 +97,91 @@ def time_qft(ctx, sv, n, dtype, steps, warmup, flags=0, psi=None, profile=False)
     return st, dt, prof
 
 
-def bench_qft_headline(ctx, sv, inputs, args):
+def deep_pass_profile(ctx, st, c):
+    """One more application with per-kernel HIP-event timing: tile and
+    permutation passes (count, total ms)."""
+    ctx.synchronize()
+    ctx.profile_reset()
+    ctx.profile(True)
+    st.reset()
+    st.apply(c)
+    ctx.synchronize()
+    out = {k: ctx.profile_get(k) for k in ("tile", "perm")}
+    ctx.profile(False)
+    ctx.profile_reset()
+    return out
+
+
+def roofline_block(S, prof, kernel, steps_passes=None):
+    """HBM roofline of a fused tile pass: 2S algorithmic bytes per launch
+    over its average HIP-event duration."""
+    tile_ms, tile_n, _ = prof["tile"]
+    avg_ms = tile_ms / max(tile_n, 1)
+    achieved = 2.0 * S / (avg_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+            "bytes_per_launch": 2.0 * S, "avg_launch_ms": avg_ms, "launches_per_step": tile_n}
+
+
+def bench_deep_headline(ctx, sv, inputs, args, tuned, dtype=None):
+    """Config 4 (30 qubits, depth 40) at complex128: reset + fused apply per
+    step on a resident state."""
+    dtype = sv.C128 if dtype is None else dtype
+    n = DEEP_N
+    c = inputs.deep_random_circuit(n, DEEP_DEPTH, DEEP_SEED)
+    log(f"[bench] headline: deep random circuit n={n} depth={DEEP_DEPTH} {'c128' if dtype == sv.C128 else 'c64'}")
+    st = ctx.alloc(n, dtype)
+    for _ in range(args.warmup):
+        st.reset()
+        st.apply(c)
+    sync_all(ctx)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st.reset()
+        st.apply(c)
+    sync_all(ctx)
+    dt = time.perf_counter() - t0
+    prof = deep_pass_profile(ctx, st, c)
+    norm_err = st.norm2() - 1.0
+    st.free()
+    amp = 16 if dtype == sv.C128 else 8
+    S = float(amp << n)
+    G = c.n_gates
+    info = sv.plan_info(c, dtype=dtype, **(tuned or {}))
+    return {"value": G * float(1 << n) * args.steps / dt, "ms_per_step": dt / args.steps * 1e3, "n": n,
+            "gates": G, "S": S, "prof": prof, "norm2_minus_1": norm_err, "plan": info}
+
+
+def bench_qft_headline(ctx, sv, inputs, args, dtype=None, steps=None, warmup=None):
     n = 28
-    log(f"[bench] headline: QFT n={n} complex64, generating input")
-    psi = inputs.gaussian_state(n, 2).astype(np.complex64)
-    st, dt, prof = time_qft(ctx, sv, n, sv.C64, args.steps, args.warmup, psi=psi, profile=True)
+    dtype = sv.C64 if dtype is None else dtype
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    log(f"[bench] QFT n={n} {'c64' if dtype == sv.C64 else 'c128'}, generating input")
+    psi = inputs.gaussian_state(n, 2)
+    if dtype == sv.C64:
+        psi = psi.astype(np.complex64)
+    st, dt, prof = time_qft(ctx, sv, n, dtype, steps, warmup, psi=psi, profile=True)
     del psi
     G = qft_gates(n)
-    au = G * float(1 << n) * args.steps
-    S = 8.0 * (1 << n)
+    au = G * float(1 << n) * steps
+    S = (8.0 if dtype == sv.C64 else 16.0) * (1 << n)
     tile_ms, tile_n, tile_bytes = prof["tile"]
     perm_ms, perm_n, _ = prof["perm"]
     avg_tile_s = tile_ms / 1e3 / max(tile_n, 1)
     achieved = (2.0 * S) / avg_tile_s / 1e9
     st.free()
     return {
-        "value": au / dt, "ms_per_step": dt / args.steps * 1e3, "n": n, "gates": G,
-        "touched_au_per_s": qft_touched(n) * float(args.steps) / dt,
-        "passes_per_step": (tile_n + perm_n) / args.steps,
+        "value": au / dt, "ms_per_step": dt / steps * 1e3, "n": n, "gates": G,
+        "touched_au_per_s": qft_touched(n) * float(steps) / dt,
+        "passes_per_step": (tile_n + perm_n) / steps,
         "tile_avg_ms": tile_ms / max(tile_n, 1), "perm_avg_ms": perm_ms / max(perm_n, 1),
         "tile_launches": tile_n, "achieved_gbs": achieved, "S": S,
         "pass_gbs": 2.0 * S * (tile_n + perm_n) / (dt) / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_tile (fused LDS tile pass; four-bit Hadamard/ladder stages)",
+                     "bytes_per_launch": 2.0 * S, "avg_launch_ms": tile_ms / max(tile_n, 1)},
     }
 
 
@@ -210,8 +281,8 @@ def bench_grad(ctx, sv, inputs, n, layers, dtype, ham, reps, seq_reps=1, seq_fla
     return rec, (c, params, e, g)
 
 
-def bench_deep30(ctx, sv, inputs, n=30, depth=40):
-    c = inputs.deep_random_circuit(n, depth, 4)
+def bench_deep30(ctx, sv, inputs, n=DEEP_N, depth=DEEP_DEPTH):
+    c = inputs.deep_random_circuit(n, depth, DEEP_SEED)
     rec = {"n": n, "depth": depth, "gates": c.n_gates}
     st = ctx.alloc(n, sv.C64)
     for name, fl in (("fused", 0), ("unfused", sv.FLAG_UNFUSED)):
@@ -235,6 +306,12 @@ def bench_deep30(ctx, sv, inputs, n=30, depth=40):
         rec[name] = {"ms": dt * 1e3, "au_per_s": c.n_gates * float(1 << n) / dt, "launches": int(nl),
                      "kernel_ms": ms, "algorithmic_gbs": by / (ms / 1e3) / 1e9 if ms else None,
                      "norm2_minus_1": st.norm2() - 1.0}
+        if fl == 0 and nl:
+            achieved = by / (ms / 1e3) / 1e9
+            rec[name]["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                                     "kernel": "k_tile (rotation-layer stages)",
+                                     "bytes_per_launch": 2.0 * 8 * (1 << n), "avg_launch_ms": ms / nl}
         log(f"[bench] deep30 {name}: {dt*1e3:.1f} ms")
     st.free()
     return rec
@@ -361,9 +438,11 @@ def bench_serving(ctx, sv, inputs, count, seed=5):
     return out
 
 
-# Sources that decide what the headline tile kernel reads and writes; the
-# recorded counter traffic is reported only while they are unchanged.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_qft28_c64_traffic.md")
+# Sources that decide what the headline tile kernel reads, writes and
+# issues; recorded counter figures are reported only while they are
+# unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_deep30_c128_traffic.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_tile_deep30_c128_counters.md")
 TRAFFIC_SOURCES = ["paper_2512_23183_amd/csrc/kernels.hip", "paper_2512_23183_amd/csrc/tile_kernel.h",
                    "paper_2512_23183_amd/csrc/device_common.h", "paper_2512_23183_amd/csrc/plan.cpp",
                    "paper_2512_23183_amd/csrc/lower.cpp", "paper_2512_23183_amd/csrc/sv_internal.h",
@@ -379,22 +458,32 @@ def traffic_sources_sha():
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """HBM bytes per headline tile launch from the committed FETCH_SIZE /
-    WRITE_SIZE summary, or None when it is missing or stale."""
+def _recorded(path, key):
+    """A figure from a committed counter summary, or None when the summary
+    is missing or was taken from other sources than the current ones."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             text = f.read()
     except OSError:
         return None
     vals = dict(line.split(":", 1) for line in text.splitlines()
-                if line.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+                if line.startswith((key + ":", "source_sha256:")))
     if vals.get("source_sha256", "").strip() != traffic_sources_sha():
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def recorded_traffic(path):
+    """HBM bytes per tile launch (FETCH_SIZE + WRITE_SIZE, calibrated)."""
+    return _recorded(path, "traffic_bytes_per_launch")
+
+
+def recorded_valu(path):
+    """VALU wave instructions per tile launch (SQ_INSTS_VALU)."""
+    return _recorded(path, "valu_wave_instr_per_launch")
 
 
 def copy_ceiling_gbs(nbytes=2 << 30, reps=5):
@@ -432,19 +521,23 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "dispatches": 3}), flush=True)
 
 
-def cpu_baseline(oracle_mod, inputs):
-    # the headline workload itself (one QFT of the 28-qubit input), about
-    # ten seconds of FP64 oracle work on the host's cores
-    n = 28
-    psi = inputs.gaussian_state(n, 2)
+def cpu_baseline(oracle_mod, inputs, layers=3):
+    """The oracle on a bounded sample of the headline workload: the first
+    `layers` layers (U3 on every qubit, CZ matching) of the 30-qubit depth-40
+    circuit from |0...0>, FP64 complex, on the host's cores (about ten
+    seconds)."""
+    c = inputs.deep_random_circuit(DEEP_N, DEEP_DEPTH, DEEP_SEED)
+    per_layer = DEEP_N + DEEP_N // 2
+    sub = inputs.Circuit(c.n, c.gates[: layers * per_layer].copy(), c.mats, 0)
     t0 = time.perf_counter()
-    oracle_mod.qft(psi)
+    psi = oracle_mod.run_circuit(sub)
     dt = time.perf_counter() - t0
+    del psi
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": qft_gates(n) * float(1 << n) / dt, "unit": "amplitude-updates/s", "cores": cores,
+    return {"value": sub.n_gates * float(1 << DEEP_N) / dt, "unit": "amplitude-updates/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"FP64 oracle gate-by-gate QFT on one {n}-qubit Gaussian state "
-                      f"({qft_gates(n)} gates, {dt:.1f} s)"}
+            "sample": f"FP64 oracle gate by gate, first {layers} of {DEEP_DEPTH} layers ({sub.n_gates} gates) "
+                      f"of the {DEEP_N}-qubit circuit from |0...0> ({dt:.1f} s)"}
 
 
 def cpu_baseline_1thread(n=24):
@@ -473,7 +566,7 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain streaming kernel used to scale HBM byte counters")
-    ap.add_argument("--only", choices=["grad10", "grad20", "vqe10", "trotter", "deep30"],
+    ap.add_argument("--only", choices=["grad10", "grad20", "vqe10", "trotter", "deep30", "deep30_once"],
                     help="profiling aid: run only this extra (no headline) and print its record")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -504,18 +597,48 @@ def main():
             rec = bench_vqe(ctx, sv, inputs)
         elif args.only == "trotter":
             rec = bench_trotter(ctx, sv, inputs)
+        elif args.only == "deep30_once":
+            # one fused application at complex128 (counter collection)
+            c = inputs.deep_random_circuit(DEEP_N, DEEP_DEPTH, DEEP_SEED)
+            st = ctx.alloc(DEEP_N, sv.C128)
+            st.apply(c)
+            ctx.synchronize()
+            st.free()
+            rec = {"n": DEEP_N, "dtype": "c128", "gates": c.n_gates}
         else:
             rec = bench_deep30(ctx, sv, inputs)
         ctx.close()
         print(json.dumps({"only": args.only, "record": rec}), flush=True)
         return
-    head = bench_qft_headline(ctx, sv, inputs, args)
-    extras = {"headline": {"touched_au_per_s": head["touched_au_per_s"], "perm_avg_ms": head["perm_avg_ms"],
-                           "pass_gbs": head["pass_gbs"]}}
+    head = bench_deep_headline(ctx, sv, inputs, args, tuned)
+    roof = roofline_block(head["S"], head["prof"], "k_tile (fused LDS tile pass; rotation-layer stages)")
+    roof["traffic"] = recorded_traffic(TRAFFIC_FILE)
+    valu = recorded_valu(COUNTERS_FILE)
+    if valu is not None:
+        # VALU issue: wave instructions x 4 cycles (wave64 on 16 lanes) over
+        # the SIMD cycles of one launch (1024 SIMDs at 2.4 GHz); FP64 FMA
+        # issues at the full rate, so this is the fraction of the FP64
+        # vector peak the pass's instruction stream could use
+        roof["valu_wave_instr_per_launch"] = valu
+        roof["valu_issue_frac"] = valu * 4.0 / (1024 * 2.4e9 * roof["avg_launch_ms"] / 1e3)
+        roof["fp64_vector_peak_tflops"] = FP64_PEAK_TFLOPS
+    extras = {"headline": {"passes_per_step": head["prof"]["tile"][1] + head["prof"]["perm"][1],
+                           "perm_launches": head["prof"]["perm"][1], "norm2_minus_1": head["norm2_minus_1"],
+                           "plan": head["plan"]}}
     copy_gbs = copy_kernel = None
     if not args.quick:
         copy_gbs, copy_kernel = copy_ceiling_gbs()
         log(f"[bench] device stream ceiling: {copy_gbs:.0f} GB/s ({copy_kernel})")
+        roof["copy_ceiling_gbs"] = copy_gbs
+        roof["copy_ceiling_kernel"] = copy_kernel
+        roof["frac_of_copy_ceiling"] = roof["achieved"] / copy_gbs
+        extras["deep30_c64"] = bench_deep30(ctx, sv, inputs)
+        for dt, nm in ((sv.C64, "qft28_c64"), (sv.C128, "qft28_c128")):
+            q = bench_qft_headline(ctx, sv, inputs, args, dt, steps=10, warmup=2)
+            extras[nm] = {"au_per_s": q["value"], "ms_per_step": q["ms_per_step"],
+                          "touched_au_per_s": q["touched_au_per_s"], "passes_per_step": q["passes_per_step"],
+                          "perm_avg_ms": q["perm_avg_ms"], "pass_gbs": q["pass_gbs"], "roofline": q["roofline"]}
+            log(f"[bench] {nm}: {q['ms_per_step']:.2f} ms")
         extras["qft"] = bench_qft_table(ctx, sv, inputs, oracle)
         direct = sv.Context(0, graph_batch=-1, **tuned)
         rec10, _ = bench_grad(ctx, sv, inputs, 10, 4, sv.C128, inputs.xyz_chain(10), 20, 3,
@@ -533,27 +656,24 @@ def main():
         direct.close()
         extras["sweeps"] = bench_sweeps(ctx, sv, inputs)
         extras["trotter_xyz_c64"] = bench_trotter(ctx, sv, inputs)
-        extras["deep30_c64"] = bench_deep30(ctx, sv, inputs)
         if args.serving > 0:
             extras["serving"] = bench_serving(ctx, sv, inputs, args.serving)
     cpu = cpu_baseline(oracle, inputs) if rank == 0 and not args.skip_cpu else None
     if cpu is not None and not args.quick:
         extras["cpu_oracle_1thread"] = cpu_baseline_1thread()
     ctx.close()
-    frac = head["achieved_gbs"] / HBM_PEAK_GBS
     line = {
         "metric": "amplitude-updates/s", "value": head["value"], "unit": "amplitude-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "qft_gate_based_n28_complex64", "n_qubits": 28, "logical_gates": head["gates"],
-                   "input": "iid complex Gaussian, normalised (seed 2)",
-                   "passes_per_step": head["passes_per_step"], "autotuned_widths": tuned},
-        "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": frac, "traffic": recorded_traffic(), "kernel": "k_tile (fused LDS tile pass; the QFT's passes in four-bit Hadamard/ladder stages)",
-                     "bytes_per_launch": 2 * head["S"], "avg_launch_ms": head["tile_avg_ms"],
-                     "copy_ceiling_gbs": copy_gbs, "copy_ceiling_kernel": copy_kernel,
-                     "frac_of_copy_ceiling": head["achieved_gbs"] / copy_gbs if copy_gbs else None},
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"deep_random_circuit_n{DEEP_N}_depth{DEEP_DEPTH}_complex128",
+                   "n_qubits": DEEP_N, "depth": DEEP_DEPTH, "logical_gates": head["gates"],
+                   "circuit": "per layer U3(theta, phi, lambda) on every qubit, angles U[0, 2 pi)^3, "
+                              "then CZ on a fresh random perfect matching (seed 4)",
+                   "input": "|0...0>, reset every step", "state_bytes": head["S"],
+                   "autotuned_widths": tuned},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "extras": extras,
     }

@@ -33,17 +33,25 @@ def test_qft_touched_matches_brute_force():
         assert bench.qft_gates(n) == n + n * (n - 1) // 2 + n // 2
 
 
-def test_recorded_traffic_requires_matching_sources(tmp_path, monkeypatch):
+def test_recorded_figures_require_matching_sources(tmp_path):
     good = tmp_path / "good.md"
-    good.write_text("x\ntraffic_bytes_per_launch: 1.5e+09\nsource_sha256: %s\n" % bench.traffic_sources_sha())
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(good))
-    assert bench.recorded_traffic() == 1.5e9
+    good.write_text("x\ntraffic_bytes_per_launch: 1.5e+09\nvalu_wave_instr_per_launch: 2.5e+08\n"
+                    "source_sha256: %s\n" % bench.traffic_sources_sha())
+    assert bench.recorded_traffic(str(good)) == 1.5e9
+    assert bench.recorded_valu(str(good)) == 2.5e8
     stale = tmp_path / "stale.md"
     stale.write_text("traffic_bytes_per_launch: 1.5e+09\nsource_sha256: %s\n" % ("0" * 64))
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(stale))
-    assert bench.recorded_traffic() is None
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.md"))
-    assert bench.recorded_traffic() is None
+    assert bench.recorded_traffic(str(stale)) is None
+    assert bench.recorded_traffic(str(tmp_path / "missing.md")) is None
+
+
+def test_roofline_block_from_launch_times():
+    # two launches of 4 ms each moving 2 x 16 GiB: 8.59 TB/s algorithmic
+    S = 16.0 * 2 ** 30
+    r = bench.roofline_block(S, {"tile": (8.0, 2, 0.0), "perm": (0.0, 0, 0.0)}, "k")
+    assert abs(r["avg_launch_ms"] - 4.0) < 1e-12
+    assert abs(r["achieved"] - 2 * S / 4e-3 / 1e9) < 1e-6
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-12 and r["bound"] == "hbm"
 
 
 def test_more_than_one_gpu_is_refused():
