@@ -255,7 +255,12 @@ __device__ __forceinline__ void h4_pat(V2<R> (&v)[16], V2<R> &acc, uint64_t k0, 
                                        const DevOp<R> &op) {
     const uint64_t all = op.cmask | (1ull << op.a) | (op.b >= 0 ? (1ull << op.b) : 0ull);
     const uint64_t gmask = all & ~(G[0] | G[1] | G[2] | G[3]);
-    const bool gon = (k0 & gmask) == gmask;  // per lane: a select, not a branch
+    // per lane: a select in the stages with a group factor (ACC), a branch in
+    // the Hadamard / ladder stages (measured faster there)
+    if constexpr (!ACC) {
+        if ((k0 & gmask) != gmask) return;
+    }
+    const bool gon = !ACC || (k0 & gmask) == gmask;
     const uint32_t emask = ((all & G[0]) ? 1u : 0u) | ((all & G[1]) ? 2u : 0u) | ((all & G[2]) ? 4u : 0u) |
                            ((all & G[3]) ? 8u : 0u);
     const V2<R> dl = op.b >= 0 ? mat_at(op, 3) : mat_at(op, 1);
