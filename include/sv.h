@@ -156,7 +156,7 @@ enum {
  */
 typedef struct sv_config {
     int32_t tile_bits_c64;     /* gate tile pass width (bits), complex64: 6..14, 0 = default 12 */
-    int32_t tile_bits_c128;    /* same for complex128: 6..13, 0 = default 12 */
+    int32_t tile_bits_c128;    /* same for complex128: 6..12, 0 = default 12 */
     int32_t expect_bits_c64;   /* expectation pass tile width, complex64: 6..14, 0 = default 13 */
     int32_t expect_bits_c128;  /* same for complex128: 6..13, 0 = default 12 */
     int32_t perm_bits_c64;     /* permutation pass tile width, complex64: 6..12, 0 = default 12 */

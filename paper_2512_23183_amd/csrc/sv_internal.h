@@ -265,7 +265,7 @@ struct DeviceBuffer {
 // Largest tile widths whose LDS footprint fits one workgroup (160 KiB):
 // gate tiles hold 2^m amplitudes plus up to four ladder tables, expectation
 // tiles 2^m amplitudes plus term accumulators, permutation passes two tiles.
-constexpr int TILE_MAX[2] = {14, 13};
+constexpr int TILE_MAX[2] = {14, 12};
 constexpr int EXPECT_MAX[2] = {14, 13};
 constexpr int PERM_MAX[2] = {12, 11};
 
