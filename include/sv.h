@@ -383,6 +383,15 @@ int sv_plan_info(const sv_circuit *circuit, const double *params, size_t n_param
 int sv_plan_dump(const sv_circuit *circuit, const double *params, size_t n_params,
                  int dtype, const sv_config *cfg, char *buf, size_t buf_len,
                  size_t *needed);
+/* Host-only: the batch that sv_param_shift_grad runs for these arguments
+ * (Eq. "parameter_shift", one shifted pair per occurrence of a parameter;
+ * the four-term rule for CRX / CRY / CRZ parameters): *circuits_out = 1 +
+ * the shifted circuits; shifts_out (nullable, n_params entries) receives
+ * how many shifted circuits each parameter's derivative combines (2 per
+ * two-term occurrence, 4 per four-term one).  Errors as the gradient's
+ * validation. */
+int sv_psr_info(const sv_circuit *circuit, const double *params, size_t n_params,
+                const sv_pauli_sum *ham, size_t *circuits_out, int32_t *shifts_out);
 
 /* Optional per-kernel timing with HIP events recorded on the launching
  * stream around every launch (off by default).  name = kernel family. */

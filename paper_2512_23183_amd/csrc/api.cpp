@@ -226,6 +226,20 @@ int sv_plan_info(const sv_circuit *circuit, const double *params, size_t n_param
     });
 }
 
+int sv_psr_info(const sv_circuit *circuit, const double *params, size_t n_params, const sv_pauli_sum *ham,
+                size_t *circuits_out, int32_t *shifts_out) {
+    return guard([&] {
+        need(circuits_out != nullptr, "circuits_out is NULL");
+        check_circuit(circuit, params, n_params);
+        check_pauli_sum(ham, circuit->n_qubits);
+        const BatchSpec spec = psr_spec(circuit, params, n_params, ham, SV_C128, true);
+        *circuits_out = spec.circuits.size();
+        if (shifts_out)
+            for (size_t i = 0; i < n_params; ++i)
+                shifts_out[i] = spec.comb_begin.size() > i + 1 ? spec.comb_begin[i + 1] - spec.comb_begin[i] : 0;
+    });
+}
+
 int sv_plan_dump(const sv_circuit *circuit, const double *params, size_t n_params, int dtype, const sv_config *cfg,
                  char *buf, size_t buf_len, size_t *needed) {
     return guard([&] {

@@ -15,7 +15,9 @@ import numpy as np
 from .inputs import GATE_DTYPE, Circuit, PauliSum
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsv.so")
+# SV_LIBRARY names another build of the same library (the sanitizer build
+# of the host code, for CPU checks); by default the in-tree libsv.so
+LIB_PATH = os.environ.get("SV_LIBRARY") or os.path.join(_HERE, "libsv.so")
 
 C64, C128 = 0, 1
 FLAG_UNFUSED = 1
@@ -109,6 +111,8 @@ def lib():
             "sv_apply_circuit_noalloc": [_vp, ctypes.POINTER(_Circuit), _dp, ctypes.c_size_t],
             "sv_plan_info": [ctypes.POINTER(_Circuit), _dp, ctypes.c_size_t, ctypes.c_int,
                              ctypes.POINTER(_Config), ctypes.POINTER(_PlanStats)],
+            "sv_psr_info": [ctypes.POINTER(_Circuit), _dp, ctypes.c_size_t, ctypes.POINTER(_PauliSum),
+                            ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int32)],
             "sv_plan_dump": [ctypes.POINTER(_Circuit), _dp, ctypes.c_size_t, ctypes.c_int,
                              ctypes.POINTER(_Config), ctypes.c_char_p, ctypes.c_size_t,
                              ctypes.POINTER(ctypes.c_size_t)],
@@ -223,6 +227,17 @@ def plan_info(circuit: Circuit, params=None, dtype: int = C64, **widths) -> dict
     d = {k: getattr(out, k) for k, _ in _PlanStats._fields_}
     d["tile_passes_by_engine"] = list(out.tile_passes_by_engine)
     return d
+
+
+def psr_info(circuit: Circuit, params, ham: PauliSum) -> Tuple[int, np.ndarray]:
+    """sv_psr_info: (circuits of the gradient batch, shifted circuits per
+    parameter) -- host only."""
+    a, h = _CircArgs(circuit, params), _HamArgs(ham)
+    nc = ctypes.c_size_t()
+    sh = np.zeros(max(a.params.size, 1), dtype=np.int32)
+    _check(lib().sv_psr_info(ctypes.byref(a.c), _dptr(a.params), a.params.size, ctypes.byref(h.h),
+                             ctypes.byref(nc), sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return nc.value, sh[:a.params.size].copy()
 
 
 def plan_dump(circuit: Circuit, params=None, dtype: int = C64, **widths) -> str:
