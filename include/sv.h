@@ -346,6 +346,15 @@ int sv_queue_wait_timed(sv_queue *q, uint64_t ticket, int timeout_ms,
                         double *energy, double *grad, size_t grad_len,
                         double *latency_s);
 int sv_queue_cancel(sv_queue *q, uint64_t ticket);
+/* Bound on the work of one scheduler tick, in amplitude updates (2^n x ops
+ * per circuit; default 5e11, about 0.15 s of device work; 0 = no bound).  A
+ * request whose remaining work exceeds an eighth of the bound is admitted
+ * in pieces of at most the bound, after the small requests waiting at that
+ * tick, so requests that arrive behind a large gradient wait for at most
+ * one piece; each later piece of a gradient reruns its unshifted circuit
+ * so that the piece's shifted circuits share that circuit's prefix.
+ * SV_EINVAL for a negative or non-finite value. */
+int sv_queue_set_tick_budget(sv_queue *q, double amplitude_updates);
 int sv_queue_get_stats(sv_queue *q, sv_queue_stats *out);
 int sv_queue_destroy(sv_queue *q);
 

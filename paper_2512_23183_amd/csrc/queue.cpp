@@ -14,6 +14,7 @@
 // its launch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -61,6 +62,10 @@ struct QueueImpl {
     Ctx *parent = nullptr;   // the context the queue was created on
     Ctx *ctx = nullptr;      // the queue's own stream and scratch buffers
     size_t budget = 0;
+    // work per tick, in amplitude updates (2^n x ops per circuit; 0 = no
+    // bound): a large gradient is admitted in pieces of about this much, so
+    // requests that arrive meanwhile wait for at most one piece
+    double tick_budget = 5e11;
     std::thread worker;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -112,6 +117,12 @@ struct QueueImpl {
         return n <= small_batch_max_qubits(dtype) ? 4096 : (amp << n);
     }
 
+    // work of one circuit of r in amplitude updates (state size x ops)
+    static double circuit_cost(const Req &r) {
+        const double ops = r.spec.op_sets.empty() ? 1.0 : (double)std::max<size_t>(1, r.spec.op_sets[0].size());
+        return std::ldexp(ops, r.circ.n_qubits);
+    }
+
     void run();
     void fail_all(int code, const std::string &msg);
     void tick(std::vector<std::pair<std::shared_ptr<Req>, std::vector<int>>> &work);
@@ -132,6 +143,17 @@ void QueueImpl::tick(std::vector<std::pair<std::shared_ptr<Req>, std::vector<int
             const int set = (int)b.op_sets.size();
             b.op_sets.push_back(r.spec.op_sets[0]);
             b.hams.push_back(r.spec.hams[0]);
+            // a later piece of a gradient runs the unshifted circuit again
+            // (its energy, bitwise the same, rewrites its own slot) so that
+            // the piece's shifted circuits share its prefix
+            if (w.second.size() > 1 && r.spec.circuits[0].ovr_index < 0 &&
+                std::find(w.second.begin(), w.second.end(), 0) == w.second.end()) {
+                BatchCircuit bc = r.spec.circuits[0];
+                bc.op_set = set;
+                bc.ham = set;
+                bc.out_slot = r.e_off;
+                b.circuits.push_back(bc);
+            }
             for (int ci : w.second) {
                 BatchCircuit bc = r.spec.circuits[ci];
                 bc.op_set = set;
@@ -153,27 +175,48 @@ void QueueImpl::run() {
             std::unique_lock<std::mutex> lk(mu);
             cv_work.wait(lk, [&] { return stop || !pending.empty(); });
             if (stop) return;
-            // admission in arrival order, piecewise, within the budget
+            // admission within the HBM budget and the tick's work bound:
+            // first every request whose remaining work is small (an eighth
+            // of the bound), in arrival order, then pieces of the large ones
+            // in arrival order; a tick always takes at least one circuit
             size_t used = 0;
             size_t n_circ = 0;
+            double cost = 0.0;
             const size_t max_circ = 1 << 14;
-            for (auto &rp : pending) {
-                Req &r = *rp;
-                if (r.cancelled || r.finished) continue;
-                if (r.e_off < 0) {
-                    r.e_off = pool_alloc((int)r.spec.circuits.size());
-                    if (r.e_off < 0) break;  // pool full: wait for completions
+            const double small = tick_budget > 0.0 ? tick_budget / 8.0 : 0.0;
+            bool full = false;
+            for (int phase = 0; phase < 2 && !full; ++phase) {
+                for (auto &rp : pending) {
+                    Req &r = *rp;
+                    if (r.cancelled || r.finished || r.next >= r.spec.circuits.size()) continue;
+                    const double each = circuit_cost(r);
+                    const double rest = each * (double)(r.spec.circuits.size() - r.next);
+                    const bool is_small = tick_budget > 0.0 && rest <= small;
+                    if ((phase == 0) != is_small) continue;
+                    if (r.e_off < 0) {
+                        r.e_off = pool_alloc((int)r.spec.circuits.size());
+                        if (r.e_off < 0) {  // pool full: wait for completions
+                            full = true;
+                            break;
+                        }
+                    }
+                    std::vector<int> take;
+                    while (r.next < r.spec.circuits.size() && n_circ < max_circ) {
+                        const size_t b = circuit_bytes(r.spec.circuits[r.next].n, r.dtype);
+                        const bool first = n_circ == 0;
+                        if (!first && used + b > budget) break;
+                        if (!first && tick_budget > 0.0 && cost + each > tick_budget) break;
+                        used += b;
+                        cost += each;
+                        take.push_back((int)r.next++);
+                        ++n_circ;
+                    }
+                    if (!take.empty()) work.push_back({rp, std::move(take)});
+                    if (used >= budget || n_circ >= max_circ || (tick_budget > 0.0 && cost >= tick_budget)) {
+                        full = true;
+                        break;
+                    }
                 }
-                std::vector<int> take;
-                while (r.next < r.spec.circuits.size() && n_circ < max_circ) {
-                    const size_t b = circuit_bytes(r.spec.circuits[r.next].n, r.dtype);
-                    if (used + b > budget && !(used == 0 && take.empty())) break;
-                    used += b;
-                    take.push_back((int)r.next++);
-                    ++n_circ;
-                }
-                if (!take.empty()) work.push_back({rp, std::move(take)});
-                if (used >= budget || n_circ >= max_circ) break;
             }
             if (used > stats.peak_bytes) stats.peak_bytes = used;
         }
@@ -480,6 +523,17 @@ int sv_queue_cancel(sv_queue *q_, uint64_t ticket) {
         if (it == q->all.end()) fail(SV_EINVAL, "unknown ticket");
         it->second->cancelled = true;
         q->cv_work.notify_one();
+    });
+}
+
+int sv_queue_set_tick_budget(sv_queue *q_, double amplitude_updates) {
+    return qguard([&] {
+        QueueImpl *q = Q(q_);
+        if (!q) fail(SV_EINVAL, "queue is NULL");
+        if (!(amplitude_updates >= 0.0) || !std::isfinite(amplitude_updates))
+            fail(SV_EINVAL, "tick budget must be finite and >= 0");
+        std::lock_guard<std::mutex> lk(q->mu);
+        q->tick_budget = amplitude_updates;
     });
 }
 

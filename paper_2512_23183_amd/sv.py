@@ -134,6 +134,7 @@ def lib():
             "sv_queue_wait_timed": [_vp, ctypes.c_uint64, ctypes.c_int, _dp, _dp,
                                     ctypes.c_size_t, _dp],
             "sv_queue_cancel": [_vp, ctypes.c_uint64],
+            "sv_queue_set_tick_budget": [_vp, ctypes.c_double],
             "sv_queue_get_stats": [_vp, ctypes.POINTER(_QStats)],
             "sv_queue_destroy": [_vp],
             "sv_check_circuit": [ctypes.POINTER(_Circuit), _dp, ctypes.c_size_t],
@@ -486,6 +487,10 @@ class Queue:
 
     def cancel(self, ticket: int):
         _check(lib().sv_queue_cancel(self.h, ticket))
+
+    def set_tick_budget(self, amplitude_updates: float):
+        """Bound the work of one scheduler tick (0 = no bound)."""
+        _check(lib().sv_queue_set_tick_budget(self.h, float(amplitude_updates)))
 
     def stats(self) -> dict:
         s = _QStats()

@@ -123,3 +123,51 @@ def test_queue_cancel(ctx, sv):
     assert outcomes[0] == "ok"
     assert outcomes[-1] in ("ok", "SV_ECANCELED")
     q.close()
+
+
+def test_queue_200_request_sample_matches_oracle_c64(ctx):
+    # the same seeded 200-request sample at complex64, the precision the
+    # serving configuration names: energies and gradients within 1e-5
+    reqs = I.serving_requests(200, 5, rate_per_s=0.0, n_range=(8, 10), depth_range=(2, 4),
+                              terms_range=(20, 60))
+    q = ctx.queue(8 << 20)
+    tickets = [q.submit(r.circuit, r.params, r.hamiltonian, r.grad, C64) for r in reqs]
+    got = [q.wait(t, 120000) for t in tickets]
+    st = q.stats()
+    q.close()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    for r, (e, g, _) in zip(reqs, got):
+        if r.grad:
+            e_ref, g_ref = oracle.param_shift(r.circuit, r.params, r.hamiltonian)
+            assert np.max(np.abs(g - g_ref)) <= 1e-5, r.rid
+        else:
+            e_ref = oracle.circuit_energy(r.circuit, r.params, r.hamiltonian)
+        assert abs(e - e_ref) <= 1e-5, r.rid
+
+
+def test_small_requests_overtake_a_large_gradient(ctx):
+    # a 20-qubit gradient (2 x 80 + 1 circuits) admitted in pieces of a
+    # bounded tick; energy requests submitted right after it complete
+    # before it does, with the results they have alone
+    big = I.hea_circuit(20, 2)
+    bp = I.uniform_params(big.n_params, 8)
+    ham = I.random_2local(20, 30, 8)
+    small = [I.hea_circuit(10, 2) for _ in range(4)]
+    sp = [I.uniform_params(c.n_params, 20 + i) for i, c in enumerate(small)]
+    sh = I.xyz_chain(10)
+    q = ctx.queue(1 << 30)
+    q.set_tick_budget(2e9)
+    alone = []
+    for c, p in zip(small, sp):
+        t = q.submit(c, p, sh, False, C64)
+        alone.append(q.wait(t, 60000)[0])
+    tb = q.submit(big, bp, ham, True, C64)
+    ts = [q.submit(c, p, sh, False, C64) for c, p in zip(small, sp)]
+    res = [q.wait(t, 60000) for t in ts]
+    eb, gb, lb = q.wait(tb, 120000)
+    q.close()
+    for (e, _, l), a in zip(res, alone):
+        assert e == a
+        assert l < lb
+    e_ref = oracle.circuit_energy(big, bp, ham)
+    assert abs(eb - e_ref) <= 1e-5
