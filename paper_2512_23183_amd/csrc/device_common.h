@@ -1030,7 +1030,8 @@ struct DevPlanDev {
 // Tile-pass launch with TPB threads per workgroup (tile_t<TPB>.hip).
 template <typename R, int TPB>
 void launch_tile_tpb(Ctx *ctx, size_t lds, unsigned grid, V2<R> *slab, uint64_t dim, int nc, const int *ovr_idx,
-                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero, int h4);
+                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero, int h4,
+                     bool one);
 
 // Workgroup size of a tile pass of m local bits: two 8-amplitude groups per
 // thread per stage (measured fastest at every width: more independent
@@ -1040,12 +1041,13 @@ inline int tile_tpb(int m) { return std::max(64, std::min(512, 1 << std::max(0, 
 template <typename R>
 inline void launch_tile(Ctx *ctx, int tpb, size_t lds, unsigned grid, V2<R> *slab, uint64_t dim, int nc,
                         const int *ovr_idx, const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles,
-                        bool from_zero, int h4) {
+                        bool from_zero, int h4, int m) {
+    const bool one = (1u << m) / 16 <= (unsigned)tpb;
     switch (tpb) {
-    case 64: launch_tile_tpb<R, 64>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4); break;
-    case 128: launch_tile_tpb<R, 128>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4); break;
-    case 256: launch_tile_tpb<R, 256>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4); break;
-    default: launch_tile_tpb<R, 512>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4); break;
+    case 64: launch_tile_tpb<R, 64>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4, one); break;
+    case 128: launch_tile_tpb<R, 128>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4, one); break;
+    case 256: launch_tile_tpb<R, 256>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4, one); break;
+    default: launch_tile_tpb<R, 512>(ctx, lds, grid, slab, dim, nc, ovr_idx, ovr, d, pidx, tiles, from_zero, h4, one); break;
     }
 }
 

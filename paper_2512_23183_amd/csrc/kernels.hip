@@ -1097,7 +1097,7 @@ void launch_plan(Ctx *ctx, const Plan &plan, const DevPlanHost<R> &h, const DevP
             if (dp.stage_end - dp.stage_begin > 1) lds += sizeof(V2<R>) << ps.m;
             LaunchScope ls(ctx, "tile", 2.0 * S);
             launch_tile<R>(ctx, tile_tpb(ps.m), lds, grid, slab, dim, nc, ovr_idx, ovr, d, (int)i, tiles,
-                           from_zero && i == 0, dp.h4);
+                           from_zero && i == 0, dp.h4, ps.m);
         } else {
             if (from_zero && i == 0) fail(SV_EDEVICE, "internal: plan starts with a permutation");
             // k_perm moves at most 4 accesses per thread per tile

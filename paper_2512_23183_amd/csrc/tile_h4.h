@@ -293,7 +293,11 @@ __device__ __forceinline__ void h4_pat(V2<R> (&v)[16], V2<R> &acc, uint64_t k0, 
 // diagonals only (layered circuits once their one-qubit gates are split
 // into rotations and phases).  The smaller op loops of 2 and 3 keep the
 // sixteen amplitudes and the op data in registers without spilling.
-template <typename R, int TPB, int MODE, int KIND, int RL = 0>
+// ONE: the caller guarantees at most one group per thread (2^m / 16 <= TPB);
+// the body then runs once with no loop around it, so nothing of the stage
+// (its tables, rotation slopes and masks) is hoisted and kept live in
+// scalar registers across iterations that never come.
+template <typename R, int TPB, int MODE, int KIND, int RL = 0, bool ONE = false>
 __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
                                          const DevStage &S, const DevOp<R> *__restrict__ ops, int ovr_index,
                                          const DevOp<R> *ovr) {
@@ -464,10 +468,11 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
                 tile[j0 | loff4<e>(L)] = v[e];
             });
         }
+        if constexpr (ONE) break;
     }
 }
 
-template <typename R, int TPB, int KIND>
+template <typename R, int TPB, int KIND, bool ONE = false>
 __device__ __forceinline__ void run_stages_h4(V2<R> *tile, V2<R> *__restrict__ gpsi, const TileCtx<R> &tc,
                                               const DevStage *__restrict__ stages, int sb, int se,
                                               const DevOp<R> *__restrict__ ops, int ovr_index, const DevOp<R> *ovr) {
@@ -480,14 +485,14 @@ __device__ __forceinline__ void run_stages_h4(V2<R> *tile, V2<R> *__restrict__ g
             auto go = [&](auto MC) {
                 constexpr int MODE = decltype(MC)::value;
                 switch (S.rl) {
-                case 0: h4_stage<R, TPB, MODE, 4, 0>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
-                case 1: h4_stage<R, TPB, MODE, 4, 1>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
-                case 2: h4_stage<R, TPB, MODE, 4, 2>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
-                case 3: h4_stage<R, TPB, MODE, 4, 3>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
-                case 4: h4_stage<R, TPB, MODE, 4, 4>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
-                case 5: h4_stage<R, TPB, MODE, 4, 5>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
-                case 6: h4_stage<R, TPB, MODE, 4, 6>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
-                default: h4_stage<R, TPB, MODE, 4, 7>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                case 0: h4_stage<R, TPB, MODE, 4, 0, ONE>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                case 1: h4_stage<R, TPB, MODE, 4, 1, ONE>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                case 2: h4_stage<R, TPB, MODE, 4, 2, ONE>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                case 3: h4_stage<R, TPB, MODE, 4, 3, ONE>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                case 4: h4_stage<R, TPB, MODE, 4, 4, ONE>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                case 5: h4_stage<R, TPB, MODE, 4, 5, ONE>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                case 6: h4_stage<R, TPB, MODE, 4, 6, ONE>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
+                default: h4_stage<R, TPB, MODE, 4, 7, ONE>(tile, gpsi, tc, S, ops, ovr_index, ovr); break;
                 }
             };
             if (first && last) go(std::integral_constant<int, 3>{});
@@ -495,10 +500,10 @@ __device__ __forceinline__ void run_stages_h4(V2<R> *tile, V2<R> *__restrict__ g
             else if (last) go(std::integral_constant<int, 2>{});
             else go(std::integral_constant<int, 0>{});
         } else {
-            if (first && last) h4_stage<R, TPB, 3, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
-            else if (first) h4_stage<R, TPB, 1, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
-            else if (last) h4_stage<R, TPB, 2, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
-            else h4_stage<R, TPB, 0, KIND>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+            if (first && last) h4_stage<R, TPB, 3, KIND, 0, ONE>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+            else if (first) h4_stage<R, TPB, 1, KIND, 0, ONE>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+            else if (last) h4_stage<R, TPB, 2, KIND, 0, ONE>(tile, gpsi, tc, S, ops, ovr_index, ovr);
+            else h4_stage<R, TPB, 0, KIND, 0, ONE>(tile, gpsi, tc, S, ops, ovr_index, ovr);
         }
         __syncthreads();
     }

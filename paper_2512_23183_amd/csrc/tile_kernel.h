@@ -18,7 +18,8 @@ namespace sv {
 // 1 = one-qubit gates, ladders and diagonals, 2 = Hadamards, ladders and
 // pattern diagonals only, 3 = Hadamards, real rotations and diagonals only,
 // 4 = rotation layers (straight-line stages, see build_rotation_layers).
-template <typename R, int TPB, int H4>
+// ONE (four-bit stages): at most one group per thread, see h4_stage.
+template <typename R, int TPB, int H4, bool ONE = false>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : (H4 >= 3 ? 2 : 1)))) void k_tile(V2<R> *__restrict__ slab, uint64_t dim, int nc,
                                                    const int *__restrict__ ovr_idx,
                                                    const DevOp<R> *__restrict__ ovr,
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
             }
         }
         if constexpr (H4 != 0)
-            run_stages_h4<R, TPB, H4>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
+            run_stages_h4<R, TPB, H4, ONE>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
         else run_stages<R, TPB>(tile, slab + c * dim, tc, stages, sb, se, ops, oi, ovr ? ovr + c : nullptr);
     }
 }
@@ -106,12 +107,26 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
 
 template <typename R, int TPB>
 void launch_tile_tpb(Ctx *ctx, size_t lds, unsigned grid, V2<R> *slab, uint64_t dim, int nc, const int *ovr_idx,
-                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero, int h4) {
+                     const DevOp<R> *ovr, const DevPlanDev<R> &d, int pidx, uint64_t tiles, bool from_zero, int h4,
+                     bool one) {
+    // one: 2^m / 16 <= TPB (four-bit stages: true at every width with
+    // fewer than 512 threads; at 512 threads up to m = 13)
     auto go = [&](auto H) {
         constexpr int H4 = decltype(H)::value;
-        set_lds_limit((const void *)k_tile<R, TPB, H4>, lds);
-        hipLaunchKernelGGL((k_tile<R, TPB, H4>), dim3(grid), dim3(TPB), lds, ctx->stream, slab, dim, nc, ovr_idx, ovr,
-                           d.pass, pidx, d.stages, d.ops, d.aux, d.aux32, d.ltab, d.mtab, tiles, from_zero ? 1 : 0);
+        auto run = [&](auto O) {
+            constexpr bool ONE = decltype(O)::value;
+            set_lds_limit((const void *)k_tile<R, TPB, H4, ONE>, lds);
+            hipLaunchKernelGGL((k_tile<R, TPB, H4, ONE>), dim3(grid), dim3(TPB), lds, ctx->stream, slab, dim, nc,
+                               ovr_idx, ovr, d.pass, pidx, d.stages, d.ops, d.aux, d.aux32, d.ltab, d.mtab, tiles,
+                               from_zero ? 1 : 0);
+        };
+        if constexpr (H4 == 0) run(std::false_type{});
+        else if constexpr (TPB < 512) {
+            if (!one) fail(SV_EDEVICE, "internal: more than one group per thread below 512 threads");
+            run(std::true_type{});
+        }
+        else if (one) run(std::true_type{});
+        else run(std::false_type{});
     };
     if (h4 == 1) go(std::integral_constant<int, 1>{});
     else if (h4 == 2) go(std::integral_constant<int, 2>{});
@@ -124,9 +139,9 @@ void launch_tile_tpb(Ctx *ctx, size_t lds, unsigned grid, V2<R> *slab, uint64_t 
 #define SV_TILE_INSTANTIATE(TPB)                                                                              \
     template void launch_tile_tpb<float, TPB>(Ctx *, size_t, unsigned, V2<float> *, uint64_t, int, const int *, \
                                               const DevOp<float> *, const DevPlanDev<float> &, int, uint64_t,   \
-                                              bool, int);                                                      \
+                                              bool, int, bool);                                                \
     template void launch_tile_tpb<double, TPB>(Ctx *, size_t, unsigned, V2<double> *, uint64_t, int,           \
                                                const int *, const DevOp<double> *, const DevPlanDev<double> &,  \
-                                               int, uint64_t, bool, int);
+                                               int, uint64_t, bool, int, bool);
 
 }  // namespace sv
