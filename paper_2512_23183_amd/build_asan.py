@@ -44,6 +44,15 @@ def _compile(src: str) -> str:
     return obj
 
 
+def stale() -> bool:
+    """True when the library is missing or older than a source or header."""
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    deps = glob.glob(os.path.join(_b.CSRC, "*")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+    return any(os.path.getmtime(f) > t for f in deps)
+
+
 def build() -> str:
     os.makedirs(OUT, exist_ok=True)
     srcs = _b.sources()

@@ -1215,6 +1215,38 @@ inline int h4_kind(const std::vector<DevOp<R>> &ops, int ob, int oe, int m) {
     return qft ? 2 : rot ? 3 : 1;
 }
 
+// Lane order of a four-bit stage.  The h4 engines keep the LDS tile
+// XOR-swizzled: element j sits at j ^ (j >> 4 & 15) ^ (j >> 8 & 15) ^
+// (j >> 12 & 15) (a bijection that folds the higher 4-bit digits onto the
+// lowest), so local bit b lands on bank slot b mod 4.  A 16-byte access of
+// 16 consecutive lanes then meets 16 distinct 16-byte bank slots when the
+// four lowest bits of the group index take local bits of residues 0, 1, 2
+// and 3 mod 4; the stage gives them the lowest non-register bits of those
+// residues (where one exists), and the other bits follow in increasing
+// order.  Packed 4 bits per index bit, from index bit 0.
+inline uint64_t h4_lane_order(const DevStage &S, int m) {
+    const int reg[4] = {S.r0, S.r1, S.r2, S.r3};
+    std::vector<int> free_bits, order;
+    for (int b = 0; b < m; ++b)
+        if (std::find(reg, reg + 4, b) == reg + 4) free_bits.push_back(b);
+    std::vector<char> used(free_bits.size(), 0);
+    for (int res = 0; res < 4 && res < (int)free_bits.size(); ++res) {
+        int pick = -1;
+        for (size_t i = 0; i < free_bits.size() && pick < 0; ++i)
+            if (!used[i] && free_bits[i] % 4 == res) pick = (int)i;
+        for (size_t i = 0; i < free_bits.size() && pick < 0; ++i)
+            if (!used[i]) pick = (int)i;
+        used[pick] = 1;
+        order.push_back(free_bits[pick]);
+    }
+    for (size_t i = 0; i < free_bits.size(); ++i)
+        if (!used[i]) order.push_back(free_bits[i]);
+    if (order.size() > 12) fail(SV_EDEVICE, "internal: four-bit stage wider than 16 bits");
+    uint64_t lp = 0;
+    for (size_t k = 0; k < order.size(); ++k) lp |= (uint64_t)order[k] << (4 * k);
+    return lp;
+}
+
 template <typename R>
 inline void build_stages_h4(std::vector<DevOp<R>> &ops, int ob, int oe, const std::vector<int> &local_bits,
                             std::vector<DevStage> &out, bool layers = false) {

@@ -909,6 +909,8 @@ DevPlanHost<R> build_dev_plan(const Plan &plan) {
                 gather_stage_diagonals<R>(h.dops, h.gate, ps.ops, b, oe, h.dstages, dp.stage_begin, ps.local_bits);
                 dp.op_end = oe;
             }
+            for (size_t si = dp.stage_begin; si < h.dstages.size(); ++si)
+                h.dstages[si].lane_pos = h4_lane_order(h.dstages[si], ps.m);
         } else if (ps.kind == PASS_TILE) {
             build_stages<R>(h.dops, b, (int)h.dops.size(), ps.local_bits, h.dstages, h.aux32, true);
         }

@@ -197,6 +197,9 @@ struct alignas(16) DevStage {
                       // rotations, 2 = sign couplings in its tables, 4 = a
                       // group factor
     uint16_t pd[8];
+    // four-bit stages: the local bit taken by each bit of a thread's group
+    // index, 4 bits per entry from index bit 0 (see h4_lane_order)
+    uint64_t lane_pos;
 };
 
 // Device pass descriptor.  Per-pass tables live in an auxiliary array:

@@ -12,8 +12,20 @@
 namespace sv {
 
 template <int E>
-__device__ __forceinline__ uint32_t loff4(const uint32_t (&L)[4]) {
-    return ((E & 1) ? L[0] : 0u) | ((E & 2) ? L[1] : 0u) | ((E & 4) ? L[2] : 0u) | ((E & 8) ? L[3] : 0u);
+__device__ __forceinline__ uint32_t loffx4(const uint32_t (&L)[4]) {
+    return ((E & 1) ? L[0] : 0u) ^ ((E & 2) ? L[1] : 0u) ^ ((E & 4) ? L[2] : 0u) ^ ((E & 8) ? L[3] : 0u);
+}
+// LDS position of tile element j (the swizzle of h4_lane_order); linear
+// over XOR, so the position of j0 | loff(e) is h4_swz(j0) ^ h4_swz(loff(e)).
+__device__ __forceinline__ uint32_t h4_swz(uint32_t j) {
+    return j ^ ((j >> 4) & 15u) ^ ((j >> 8) & 15u) ^ ((j >> 12) & 15u);
+}
+// Tile index of group index it: bit k of it goes to local bit lp[k].
+__device__ __forceinline__ uint32_t h4_deposit(uint32_t it, uint64_t lp) {
+    uint32_t j = 0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) j |= ((it >> k) & 1u) << ((uint32_t)(lp >> (4 * k)) & 15u);
+    return j;
 }
 template <int E>
 __device__ __forceinline__ uint64_t goff4(const uint64_t (&G)[4]) {
@@ -304,14 +316,16 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
     constexpr bool GEN = KIND != 2;
     const uint32_t nitems = (1u << tc.m) >> 4;
     const int r[4] = {S.r0, S.r1, S.r2, S.r3};
-    const uint32_t L[4] = {1u << r[0], 1u << r[1], 1u << r[2], 1u << r[3]};
+    // LDS positions of the register-bit offsets (swizzled tile)
+    const uint32_t L[4] = {h4_swz(1u << r[0]), h4_swz(1u << r[1]), h4_swz(1u << r[2]), h4_swz(1u << r[3])};
     const uint64_t G[4] = {gbit(tc, r[0]), gbit(tc, r[1]), gbit(tc, r[2]), gbit(tc, r[3])};
     // complex64 with global bit 0 as register slot 0: elements 2i, 2i + 1
     // are adjacent in HBM and move as one 16-byte access
     const bool pairg = sizeof(R) == 4 && G[0] == 1ull;
     using P = typename Pair<R>::T;
     for (uint32_t it = threadIdx.x; it < nitems; it += TPB) {
-        const uint32_t j0 = ins0(ins0(ins0(ins0(it, r[0]), r[1]), r[2]), r[3]);
+        const uint32_t j0 = h4_deposit(it, S.lane_pos);
+        const uint32_t p0 = h4_swz(j0);
         const uint64_t k0 = gaddr(tc, j0);
         V2<R> v[16];
         if constexpr (MODE & 1) {
@@ -337,7 +351,7 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
         } else {
             static_for<0, 16>([&](auto EC) {
                 constexpr int e = decltype(EC)::value;
-                v[e] = tile[j0 | loff4<e>(L)];
+                v[e] = tile[p0 ^ loffx4<e>(L)];
             });
         }
         V2<R> acc;
@@ -465,7 +479,7 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
         } else {
             static_for<0, 16>([&](auto EC) {
                 constexpr int e = decltype(EC)::value;
-                tile[j0 | loff4<e>(L)] = v[e];
+                tile[p0 ^ loffx4<e>(L)] = v[e];
             });
         }
         if constexpr (ONE) break;

@@ -80,7 +80,7 @@ def test_host_driver_regular_library():
 def test_host_driver_under_sanitizers():
     sys.path.insert(0, os.path.join(ROOT, "paper_2512_23183_amd"))
     import build_asan
-    if not os.path.exists(build_asan.LIB):
+    if build_asan.stale():
         build_asan.build()
     env = dict(os.environ, LD_PRELOAD=build_asan.runtime(), SV_LIBRARY=build_asan.LIB,
                ASAN_OPTIONS="detect_leaks=0:verify_asan_link_order=0:halt_on_error=1",
