@@ -579,7 +579,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain streaming kernel used to scale HBM byte counters")
-    ap.add_argument("--only", choices=["grad10", "grad20", "vqe10", "trotter", "deep30", "deep30_once"],
+    ap.add_argument("--only", choices=["grad10", "grad20", "vqe10", "trotter", "deep30", "deep30_once",
+                                       "qft28_once"],
                     help="profiling aid: run only this extra (no headline) and print its record")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -618,6 +619,15 @@ def main():
             ctx.synchronize()
             st.free()
             rec = {"n": DEEP_N, "dtype": "c128", "gates": c.n_gates}
+        elif args.only == "qft28_once":
+            # one fused QFT of a 28-qubit state at each precision (counter
+            # collection; the kernels' work does not depend on the values)
+            for dt in (sv.C64, sv.C128):
+                st = ctx.alloc(28, dt)
+                st.qft()
+                ctx.synchronize()
+                st.free()
+            rec = {"n": 28, "dtype": ["c64", "c128"]}
         else:
             rec = bench_deep30(ctx, sv, inputs)
         ctx.close()

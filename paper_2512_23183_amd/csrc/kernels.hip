@@ -277,6 +277,12 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uin
     }
     const uint64_t fmask = P.free_mask;
     const int nfp = P.nfp;
+    // the free bit pairs, as 32-bit words held in scalar registers (byte
+    // loads inside the item loop would be vector loads, each waited out)
+    uint32_t fpw[12];
+    const uint32_t *fw = reinterpret_cast<const uint32_t *>(P.fpa);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) fpw[i] = __builtin_amdgcn_readfirstlane(fw[i]);
     __syncthreads();
     // 16-byte register images of the accesses (two complex64 / one complex128)
     typedef float PT __attribute__((ext_vector_type(4)));
@@ -315,9 +321,13 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uin
         it.psi = slab + c * dim;
         it.bv = deposit(t, fmask);
         it.bw = it.bv;
-        for (int i = 0; i < nfp; ++i) {
-            const int a = P.fpa[i], b = P.fpb[i];
-            if (((it.bv >> a) ^ (it.bv >> b)) & 1) it.bw ^= (1ull << a) | (1ull << b);
+#pragma unroll
+        for (int i = 0; i < 24; ++i) {
+            if (i < nfp) {
+                const int a = (int)((fpw[i >> 2] >> (8 * (i & 3))) & 255u);
+                const int b = (int)((fpw[6 + (i >> 2)] >> (8 * (i & 3))) & 255u);
+                if (((it.bv >> a) ^ (it.bv >> b)) & 1) it.bw ^= (1ull << a) | (1ull << b);
+            }
         }
         return it.bw >= it.bv;
     };

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <cstddef>
 #include <complex>
 #include <cstdint>
 #include <functional>
@@ -224,6 +225,9 @@ struct alignas(16) DevPass {
     int32_t tf_begin, tf_end;        // kind 4: diagonals on bits outside the tile (one
                                      // factor per tile, applied with the pass scale)
 };
+// k_perm reads fpa and fpb as twelve consecutive 32-bit words
+static_assert(offsetof(DevPass, fpa) % 4 == 0 && offsetof(DevPass, fpb) == offsetof(DevPass, fpa) + 24,
+              "DevPass pair arrays must be word-aligned and adjacent");
 
 // ---------------------------------------------------------------------------
 // Pauli sums lowered to masks (bit positions).
