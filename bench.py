@@ -314,7 +314,34 @@ def bench_deep30(ctx, sv, inputs, n=DEEP_N, depth=DEEP_DEPTH):
                                      "bytes_per_launch": 2.0 * 8 * (1 << n), "avg_launch_ms": ms / nl}
         log(f"[bench] deep30 {name}: {dt*1e3:.1f} ms")
     st.free()
+    rec["dense_blocks"] = bench_deep30_blocks(sv, c, n)
     return rec
+
+
+def bench_deep30_blocks(sv, c, n):
+    """The same complex64 circuit with every run of at least two fixed gates
+    on at most k qubits forced into a dense block (dense_fuse = k, MFMA
+    16 x 16 stages), k = 2, 3, 4: one warm-up and one timed application
+    each.  The default policy forms no blocks on these layers."""
+    out = {}
+    for k in (2, 3, 4):
+        info = sv.plan_info(c, dtype=sv.C64, dense_fuse=k)
+        kc = sv.Context(0, dense_fuse=k)
+        try:
+            st = kc.alloc(n, sv.C64)
+            st.apply(c)
+            kc.synchronize()
+            t0 = time.perf_counter()
+            st.apply(c)
+            kc.synchronize()
+            dt = time.perf_counter() - t0
+            st.free()
+        finally:
+            kc.close()
+        out[f"k{k}"] = {"ms": dt * 1e3, "blocks": info["dense_blocks"], "stages": info["stages"],
+                        "tile_passes": info["tile_passes"]}
+        log(f"[bench] deep30 c64 forced k={k} blocks: {dt*1e3:.1f} ms ({info['dense_blocks']} blocks)")
+    return out
 
 
 def bench_vqe(ctx, sv, inputs):
@@ -580,7 +607,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain streaming kernel used to scale HBM byte counters")
     ap.add_argument("--only", choices=["grad10", "grad20", "vqe10", "trotter", "deep30", "deep30_once",
-                                       "qft28_once"],
+                                       "qft28_once", "deep30_dense4_once"],
                     help="profiling aid: run only this extra (no headline) and print its record")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -619,6 +646,17 @@ def main():
             ctx.synchronize()
             st.free()
             rec = {"n": DEEP_N, "dtype": "c128", "gates": c.n_gates}
+        elif args.only == "deep30_dense4_once":
+            # one fused complex64 application with forced four-qubit dense
+            # blocks (MFMA counter collection)
+            c = inputs.deep_random_circuit(DEEP_N, DEEP_DEPTH, DEEP_SEED)
+            kc = sv.Context(0, dense_fuse=4)
+            st = kc.alloc(DEEP_N, sv.C64)
+            st.apply(c)
+            kc.synchronize()
+            st.free()
+            kc.close()
+            rec = {"n": DEEP_N, "dtype": "c64", "dense_fuse": 4}
         elif args.only == "qft28_once":
             # one fused QFT of a 28-qubit state at each precision (counter
             # collection; the kernels' work does not depend on the values)

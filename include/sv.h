@@ -163,7 +163,10 @@ typedef struct sv_config {
     int32_t perm_bits_c128;    /* same for complex128: 6..11, 0 = default 11 */
     int32_t dense_fuse;        /* complex64 apply: runs of fixed gates on four qubits become
                                   one dense 16x16 block applied with MFMA; 0 = default (on),
-                                  1 = on, -1 = off */
+                                  1 = on, -1 = off; 2..4 = measurement mode: every run of at
+                                  least two fixed gates on at most k = dense_fuse qubits
+                                  becomes a block (padded to four qubits), whatever its cost;
+                                  other values are SV_EINVAL */
     int32_t graph_batch;       /* gradients, batch energies and queue ticks: record the batch's
                                   launches and replay them as one hipGraph launch (the
                                   instantiated graph is reused while the batch keeps its

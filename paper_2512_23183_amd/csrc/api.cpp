@@ -61,7 +61,10 @@ void apply_config(Ctx *ctx, const sv_config *cfg) {
     pick(cfg->expect_bits_c128, 6, EXPECT_MAX[SV_C128], ctx->expect_bits[SV_C128]);
     pick(cfg->perm_bits_c64, 6, PERM_MAX[SV_C64], ctx->perm_bits[SV_C64]);
     pick(cfg->perm_bits_c128, 6, PERM_MAX[SV_C128], ctx->perm_bits[SV_C128]);
+    need(cfg->dense_fuse >= -1 && cfg->dense_fuse <= 4,
+         "dense_fuse must be -1 (off), 0 (default), 1 (on) or 2..4 (forced block width)");
     if (cfg->dense_fuse != 0) ctx->dense4 = cfg->dense_fuse > 0;
+    ctx->dense_force = cfg->dense_fuse >= 2 ? cfg->dense_fuse : 0;
     if (cfg->graph_batch != 0) ctx->graphs = cfg->graph_batch > 0;
 }
 
@@ -89,6 +92,7 @@ void apply_ops(State *st, const std::vector<Op> &ops, uint32_t flags) {
         po.tile_bits = ctx->tile_bits[st->dtype];
         po.perm_bits = ctx->perm_bits[st->dtype];
         po.dense4 = st->dtype == SV_C64 && ctx->dense4;
+        po.dense_force = ctx->dense_force;
         run_plan(ctx, st, make_plan(st->n, ops, po));
     }
     if (ctx->profile) {
@@ -202,6 +206,7 @@ PlanSummary plan_for(const sv_circuit *circuit, const double *params, size_t n_p
     po.tile_bits = opts.tile_bits[dtype];
     po.perm_bits = opts.perm_bits[dtype];
     po.dense4 = dtype == SV_C64 && opts.dense4;
+    po.dense_force = opts.dense_force;
     const Plan plan = make_plan(circuit->n_qubits, lower_circuit(circuit, params), po);
     return dtype == SV_C64 ? summarize_plan<float>(plan, text) : summarize_plan<double>(plan, text);
 }
@@ -258,6 +263,10 @@ int sv_init(sv_ctx **out, int device, const sv_config *cfg) {
     return guard([&] {
         need(out != nullptr, "out is NULL");
         *out = nullptr;
+        {
+            Ctx check;  // the configuration is validated before anything is created
+            apply_config(&check, cfg);
+        }
         int count = 0;
         if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
             (void)hipGetLastError();
@@ -457,6 +466,7 @@ int sv_apply_circuit_noalloc(sv_state *st, const sv_circuit *circuit, const doub
         po.tile_bits = ctx->tile_bits[st->dtype];
         po.perm_bits = ctx->perm_bits[st->dtype];
         po.dense4 = st->dtype == SV_C64 && ctx->dense4;
+        po.dense_force = ctx->dense_force;
         run_plan_in(ctx, st, make_plan(st->n, lower_circuit(circuit, params), po), block, NOALLOC_BLOCK_BYTES);
     });
 }
@@ -654,7 +664,7 @@ int sv_autotune(sv_ctx *ctx, int dtype, int n_qubits, const char *cache_path, sv
             chosen->expect_bits_c128 = ctx->expect_bits[SV_C128];
             chosen->perm_bits_c64 = ctx->perm_bits[SV_C64];
             chosen->perm_bits_c128 = ctx->perm_bits[SV_C128];
-            chosen->dense_fuse = ctx->dense4 ? 1 : -1;
+            chosen->dense_fuse = ctx->dense4 ? (ctx->dense_force ? ctx->dense_force : 1) : -1;
         }
     });
 }

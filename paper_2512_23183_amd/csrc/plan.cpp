@@ -242,7 +242,11 @@ void apply_op16(const Op &op, const int (&pos)[64], cd *v) {
 // Least total op cost for which a block is replaced by a dense op.
 constexpr double DENSE4_MIN_COST = 24.0;
 
-void fuse_dense4(Pass &ps, Plan &plan) {
+// force (2..4): every run of at least two fusible ops on at most force bits
+// becomes a block, whatever its cost and gate kinds (a measurement mode:
+// blocks of k = force qubits, each still applied as a padded 16 x 16).
+void fuse_dense4(Pass &ps, Plan &plan, int force) {
+    const int kmax = force >= 2 && force <= 4 ? force : 4;
     uint64_t local = 0;
     for (int b : ps.local_bits) local |= bit(b);
     for (const Op &o : ps.ops)
@@ -262,7 +266,7 @@ void fuse_dense4(Pass &ps, Plan &plan) {
         }
         // runs of one-qubit gates and diagonals alone are left to the
         // four-bit register stages (measured faster than the block)
-        if (two && blk.size() >= 2 && cost >= DENSE4_MIN_COST) {
+        if (force ? blk.size() >= 2 : (two && blk.size() >= 2 && cost >= DENSE4_MIN_COST)) {
             // pad to four bits with the lowest local bits not in the block
             for (int b : ps.local_bits)
                 if (__builtin_popcountll(B) < 4 && !(B & bit(b))) B |= bit(b);
@@ -291,7 +295,7 @@ void fuse_dense4(Pass &ps, Plan &plan) {
     for (const Op &o : ps.ops) {
         if (fusible(o)) {
             const uint64_t nb = B | op_bits(o);
-            if (__builtin_popcountll(nb) <= 4) {
+            if (__builtin_popcountll(nb) <= kmax) {
                 blk.push_back(o);
                 B = nb;
                 continue;
@@ -616,7 +620,7 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
             if (!(S & bit(b))) { S |= bit(b); ++nS; }
         finish_tile_pass(n, ps, S);
         if (ps.ops.empty()) fail(SV_EDEVICE, "internal: planner made no progress");
-        if (opt.dense4 && ps.m >= 4) fuse_dense4(ps, plan);
+        if (opt.dense4 && ps.m >= 4) fuse_dense4(ps, plan, opt.dense_force);
         plan.passes.push_back(std::move(ps));
         rest.swap(deferred);
         rsets.swap(dsets);

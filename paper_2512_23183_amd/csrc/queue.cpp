@@ -409,6 +409,7 @@ int sv_queue_create(sv_ctx *ctx_, size_t hbm_budget_bytes, sv_queue **out) {
             q->ctx->perm_bits[d] = ctx->perm_bits[d];
         }
         q->ctx->dense4 = ctx->dense4;
+        q->ctx->dense_force = ctx->dense_force;
         q->ctx->graphs = ctx->graphs;
         q->ctx->fault_alloc = ctx->fault_alloc;
         if (hipStreamCreateWithFlags(&q->ctx->own_stream, hipStreamNonBlocking) != hipSuccess) {

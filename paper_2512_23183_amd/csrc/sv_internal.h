@@ -160,6 +160,8 @@ struct PlanOptions {
     int perm_bits = 11;    // tile width of permutation passes
     bool fuse = true;      // false: one sweep op per gate
     bool dense4 = false;   // fuse runs of fixed gates on four bits into OP_DENSE4
+    int dense_force = 0;   // 2..4: every run of >= 2 fixed gates on <= k bits becomes a
+                           // block (padded to four bits), whatever its cost
 };
 
 struct Plan {
@@ -288,6 +290,7 @@ struct Ctx {
     int expect_bits[2] = {13, 12};
     int perm_bits[2] = {12, 11};
     bool dense4 = true;  // complex64 circuits: MFMA stages for dense four-qubit runs
+    int dense_force = 0; // 2..4: blocks of width <= k on every run (measurement mode)
     std::mutex mu;
     // states created on this context and not yet freed (sv_shutdown refuses
     // to run while any is alive: they reference the context's stream)

@@ -482,3 +482,23 @@ def test_dense_mfma_blocks_match_oracle(sv, n, depth, kind):
             c.close()
         ok, err = amp_tol_ok(got, want, C64, circ.n_gates)
         assert ok, (fuse, err)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_forced_dense_blocks_of_each_width_match_oracle(sv, k):
+    # dense_fuse = k: every run of at least two fixed gates on at most k
+    # qubits becomes a dense block (padded to four qubits, MFMA), here on
+    # layers of U3 and CZ, which the default policy leaves to the register
+    # stages; 14 qubits (several tiles per pass), depth 6
+    n = 14
+    circ = I.deep_random_circuit(n, 6, 70 + k)
+    assert sv.plan_info(circ, dtype=C64, dense_fuse=k)["dense_blocks"] > 0
+    psi0 = I.gaussian_state(n, 71 + k)
+    want = oracle.run_circuit(circ, None, psi0)
+    c = sv.Context(0, dense_fuse=k)
+    try:
+        got = run_gpu(c, circ, None, psi0, C64)
+    finally:
+        c.close()
+    ok, err = amp_tol_ok(got, want, C64, circ.n_gates)
+    assert ok, (k, err)

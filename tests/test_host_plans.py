@@ -45,6 +45,33 @@ def test_deep_circuit_plans_as_rotation_layers(sv):
         assert "acc=1" not in dump  # every diagonal folded into a table or a tile factor
 
 
+def test_forced_dense_block_widths(sv):
+    # dense_fuse = k in 2..4 (a measurement mode): every run of >= 2 fixed
+    # gates on <= k qubits becomes a dense block; the default policy forms
+    # none on U3 + CZ layers; complex128 never forms blocks; other values
+    # are rejected before anything is planned or any device is touched
+    c = I.deep_random_circuit(16, 8, 4)
+    assert sv.plan_info(c, dtype=sv.C64)["dense_blocks"] == 0
+    counts = {}
+    for k in (2, 3, 4):
+        info = sv.plan_info(c, dtype=sv.C64, dense_fuse=k)
+        counts[k] = info["dense_blocks"]
+        assert counts[k] > 0, k
+        dump = sv.plan_dump(c, dtype=sv.C64, dense_fuse=k)
+        assert "DENSE4" in dump
+        assert sv.plan_info(c, dtype=sv.C128, dense_fuse=k)["dense_blocks"] == 0
+    # wider blocks swallow more gates each: fewer of them
+    assert counts[2] > counts[3] > counts[4], counts
+    for bad in (5, -2):
+        with pytest.raises(sv.SvError) as ei:
+            sv.plan_info(c, dtype=sv.C64, dense_fuse=bad)
+        assert ei.value.code == -1
+        h = sv._vp()
+        cfg = sv._config(dense_fuse=bad)
+        assert sv.lib().sv_init(sv.ctypes.byref(h), 0, sv.ctypes.byref(cfg)) == -1
+        assert not h
+
+
 def test_qft_and_ansatz_engines(sv):
     from paper_2512_23183_amd import sv as S
     qft = I.CircuitBuilder(20)
