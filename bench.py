@@ -218,12 +218,30 @@ def bench_qft_table(ctx, sv, inputs, oracle_mod):
                    "gbs_per_pass": 2 * S * (tile_n + perm_n) / ((tile_ms + perm_ms) / 1e3) / 1e9
                    if tile_n + perm_n else None,
                    "rel_l2_vs_inverse_dft": rel}
-            if n <= 24:
-                # one launch per gate: GB/s per gate sweep
-                st, dt1, _ = time_qft(ctx, sv, n, dtype, 1, 0, flags=sv.FLAG_UNFUSED)
-                st.free()
-                rec["unfused_ms"] = dt1 * 1e3
-                rec["unfused_au_per_s"] = G * float(1 << n) / dt1
+            # one launch per gate (every size): GB/s per gate sweep, from the
+            # algorithmic bytes and HIP-event times of the sweep launches
+            st = ctx.alloc(n, dtype)
+            sync_all(ctx)
+            ctx.profile_reset()
+            ctx.profile(True)
+            t0 = time.perf_counter()
+            st.qft(sv.FLAG_UNFUSED)
+            sync_all(ctx)
+            dt1 = time.perf_counter() - t0
+            st.free()
+            sw_ms = sw_n = sw_b = 0.0
+            for k in ("sweep_u1", "sweep_phase", "sweep_xperm", "sweep_diag", "sweep_u2", "sweep_swap",
+                      "sweep_ladder"):
+                a, b, cb = ctx.profile_get(k)
+                sw_ms += a
+                sw_n += b
+                sw_b += cb
+            ctx.profile(False)
+            ctx.profile_reset()
+            rec["unfused_ms"] = dt1 * 1e3
+            rec["unfused_au_per_s"] = G * float(1 << n) / dt1
+            rec["unfused_sweeps"] = int(sw_n)
+            rec["unfused_gbs_per_sweep"] = sw_b / (sw_ms / 1e3) / 1e9 if sw_ms else None
             out[f"n{n}_{name}"] = rec
             log(f"[bench] qft n={n} {name}: {rec['ms']:.3f} ms, {rec['au_per_s']:.3e} AU/s")
     return out

@@ -15,7 +15,23 @@ struct sv_state : sv::State {};
 
 namespace sv {
 size_t queue_count(Ctx *ctx);
+
+static std::vector<uint32_t (*)()> &bound_flag_readers() {
+    static std::vector<uint32_t (*)()> r;
+    return r;
 }
+
+bool register_bound_flag_reader(uint32_t (*reader)()) {
+    bound_flag_readers().push_back(reader);
+    return true;
+}
+
+uint32_t take_bound_flags() {
+    uint32_t f = 0;
+    for (auto r : bound_flag_readers()) f |= r();
+    return f;
+}
+}  // namespace sv
 
 using namespace sv;
 
@@ -25,6 +41,15 @@ template <class F>
 int guard(F &&f) {
     try {
         f();
+#ifdef SV_DEBUG_BOUNDS
+        // debug build: wait for the call's kernels and report any index
+        // that fell outside its array
+        if (hipDeviceSynchronize() != hipSuccess) (void)hipGetLastError();
+        if (const uint32_t fl = take_bound_flags())
+            fail(SV_EDEVICE, std::string("debug build: out-of-range index in a kernel (") +
+                                 ((fl & 1) ? "HBM" : "") + ((fl & 3) == 3 ? ", " : "") + ((fl & 2) ? "LDS" : "") +
+                                 ")");
+#endif
         set_last_error("");
         return SV_OK;
     } catch (const Error &e) {
@@ -289,6 +314,15 @@ int sv_init(sv_ctx **out, int device, const sv_config *cfg) {
         ctx->stream = ctx->own_stream;
         if (const char *fa = std::getenv("SV_FAULT_ALLOC")) ctx->fault_alloc = std::max(0, std::atoi(fa));
         apply_config(ctx, cfg);
+#ifdef SV_DEBUG_BOUNDS
+        try {
+            debug_bounds_probe(ctx);
+        } catch (...) {
+            (void)hipStreamDestroy(ctx->own_stream);
+            delete ctx;
+            throw;
+        }
+#endif
         *out = ctx;
     });
 }

@@ -15,6 +15,40 @@
 namespace sv {
 
 
+// Index checks of the debug kernel build (SV_DEBUG_BOUNDS, see
+// build_debug.py): an index outside its array sets a bit in this
+// translation unit's flag word and is replaced by 0, so the access stays
+// inside the array (nothing traps); the API call that ran the kernel
+// returns SV_EDEVICE.  In the regular build the checks are the index itself.
+#ifdef SV_DEBUG_BOUNDS
+static __device__ unsigned int sv_debug_bound_flags;
+template <typename T>
+__device__ __forceinline__ T dbg_idx(T i, T n, unsigned int bit) {
+    if (i >= n) {
+        atomicOr(&sv_debug_bound_flags, bit);
+        return (T)0;
+    }
+    return i;
+}
+#define SV_GIDX(i, n) ::sv::dbg_idx<uint64_t>((uint64_t)(i), (uint64_t)(n), 1u)
+#define SV_LIDX(i, n) ::sv::dbg_idx<uint32_t>((uint32_t)(i), (uint32_t)(n), 2u)
+namespace {
+uint32_t take_bound_flags_here() {
+    uint32_t v = 0, z = 0;
+    if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(sv_debug_bound_flags), sizeof v) != hipSuccess ||
+        hipMemcpyToSymbol(HIP_SYMBOL(sv_debug_bound_flags), &z, sizeof z) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return v;
+}
+[[maybe_unused]] const bool bound_flags_registered = register_bound_flag_reader(&take_bound_flags_here);
+}  // namespace
+#else
+#define SV_GIDX(i, n) (i)
+#define SV_LIDX(i, n) (i)
+#endif
+
 template <typename R> struct VecOf;
 template <> struct VecOf<float> { using T = float2; };
 template <> struct VecOf<double> { using T = double2; };
@@ -137,6 +171,7 @@ struct TileCtx {
     const SV_LDS uint32_t *pauxl;  // their LDS copy (non-null) holding entries from paux_off
     int paux_off;
     const float *mtab;        // MFMA stage matrices
+    uint64_t dim;             // amplitudes per state (debug index checks)
     R scale;                  // pass scale (OPF_SCALED factors), applied
     bool scaled;              // by the store of the pass's last stage
 };
@@ -612,9 +647,9 @@ __device__ __forceinline__ void mfma_stage(V2<R> *tile, V2<R> *__restrict__ gpsi
                 if (live) {
                     if constexpr (MODE & 1) {
                         if (tc.zero) v.x = (k0 | goff(a)) == 0 ? (R)1 : (R)0;
-                        else v = gpsi[k0 | goff(a)];
+                        else v = gpsi[SV_GIDX(k0 | goff(a), tc.dim)];
                     } else {
-                        v = tile[j0 | loff(a)];
+                        v = tile[SV_LIDX(j0 | loff(a), 1u << tc.m)];
                     }
                 }
                 bre[s] = v.x;
@@ -638,9 +673,9 @@ __device__ __forceinline__ void mfma_stage(V2<R> *tile, V2<R> *__restrict__ gpsi
                             v.x *= tc.scale;
                             v.y *= tc.scale;
                         }
-                        gpsi[k0 | goff(a)] = v;
+                        gpsi[SV_GIDX(k0 | goff(a), tc.dim)] = v;
                     } else {
-                        tile[j0 | loff(a)] = v;
+                        tile[SV_LIDX(j0 | loff(a), 1u << tc.m)] = v;
                     }
                 }
             }
@@ -664,18 +699,20 @@ __device__ __forceinline__ double2 pair_join(double2 a, double2) { return a; }
 // offsets of its register bits: G) into d.
 template <typename R>
 __device__ __forceinline__ void load_group(V2<R> (&d)[8], const V2<R> *__restrict__ gpsi, uint64_t k0,
-                                           const uint64_t (&G)[3], bool pairg) {
+                                           const uint64_t (&G)[3], bool pairg, uint64_t dim) {
+    (void)dim;  // read by the debug build's index checks
     if (pairg) {
         static_for<0, 4>([&](auto IC) {
             constexpr int e = 2 * decltype(IC)::value;
-            const typename Pair<R>::T v = *reinterpret_cast<const typename Pair<R>::T *>(gpsi + (k0 | goff<e>(G)));
+            const typename Pair<R>::T v =
+                *reinterpret_cast<const typename Pair<R>::T *>(gpsi + SV_GIDX(k0 | goff<e>(G), dim));
             d[e] = pair_lo(v);
             d[e + 1] = pair_hi(v);
         });
     } else {
         static_for<0, 8>([&](auto EC) {
             constexpr int e = decltype(EC)::value;
-            d[e] = gpsi[k0 | goff<e>(G)];
+            d[e] = gpsi[SV_GIDX(k0 | goff<e>(G), dim)];
         });
     }
 }
@@ -739,19 +776,19 @@ __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi,
             if (pairg) {
                 static_for<0, 4>([&](auto IC) {
                     constexpr int e = 2 * decltype(IC)::value;
-                    *reinterpret_cast<typename Pair<R>::T *>(gpsi + (g.k0 | goff<e>(G))) =
+                    *reinterpret_cast<typename Pair<R>::T *>(gpsi + SV_GIDX(g.k0 | goff<e>(G), tc.dim)) =
                         pair_join(el<e>(g), el<e + 1>(g));
                 });
             } else {
                 static_for<0, 8>([&](auto EC) {
                     constexpr int e = decltype(EC)::value;
-                    gpsi[g.k0 | goff<e>(G)] = el<e>(g);
+                    gpsi[SV_GIDX(g.k0 | goff<e>(G), tc.dim)] = el<e>(g);
                 });
             }
         } else {
             static_for<0, 8>([&](auto EC) {
                 constexpr int e = decltype(EC)::value;
-                tile[lpos(pos0, EC)] = el<e>(g);
+                tile[SV_LIDX(lpos(pos0, EC), 1u << tc.m)] = el<e>(g);
             });
         }
     };
@@ -769,7 +806,7 @@ __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi,
                 });
             } else {
                 V2<R> d[8];
-                load_group<R>(d, gpsi, g.k0, G, pairg);
+                load_group<R>(d, gpsi, g.k0, G, pairg, tc.dim);
                 static_for<0, 8>([&](auto EC) {
                     constexpr int e = decltype(EC)::value;
                     el<e>(g) = d[e];
@@ -778,7 +815,7 @@ __device__ __forceinline__ void run_stage(V2<R> *tile, V2<R> *__restrict__ gpsi,
         } else {
             static_for<0, 8>([&](auto EC) {
                 constexpr int e = decltype(EC)::value;
-                el<e>(g) = tile[lpos(pos0, EC)];
+                el<e>(g) = tile[SV_LIDX(lpos(pos0, EC), 1u << tc.m)];
             });
         }
         finish(g, pos0);

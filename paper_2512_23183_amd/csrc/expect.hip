@@ -72,7 +72,7 @@ __global__ __launch_bounds__(EXPT_TPB) void k_expect_tile(const V2<R> *__restric
     __syncthreads();
     for (uint64_t t = b; t < P.ntiles; t += vb) {
         const uint64_t base = deposit(t, P.free_mask);
-        for (uint32_t j = threadIdx.x; j < T; j += EXPT_TPB) tile[j] = psi[base | hi_off[j >> l] | (j & lowm)];
+        for (uint32_t j = threadIdx.x; j < T; j += EXPT_TPB) tile[j] = psi[SV_GIDX(base | hi_off[j >> l] | (j & lowm), dim)];
         __syncthreads();
         for (int g = g0; g < P.g_end; g += gstep) {
             const EGroup G = groups[g];
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(EXPT_TPB) void k_expect_wide(const V2<R> *__restric
         for (int q = 0; q < EXPT_CHUNK; ++q) acc[q] = 0.0;
         for (uint64_t it = i0 + lane; it < i1; it += 64) {
             const uint64_t k = ((it & ~below) << 1) | (it & below);
-            const V2<R> a = psi[k], bb = psi[k ^ G.x];
+            const V2<R> a = psi[SV_GIDX(k, dim)], bb = psi[SV_GIDX(k ^ G.x, dim)];
             const double ax = a.x, ay = a.y, bx = bb.x, by = bb.y;
             const double u = G.pim ? bx * ay - by * ax : bx * ax + by * ay;
 #pragma unroll

@@ -47,6 +47,7 @@ struct SweepArgs {
     uint64_t flip, lmask;
     double turns;
     int a, b;
+    uint64_t dim;  // amplitudes of the state (debug index checks)
 };
 
 constexpr int sweep_nidx(int kind) {
@@ -138,6 +139,9 @@ __device__ __forceinline__ void sweep_index(uint64_t (&idx)[sweep_nidx(KIND)], u
         idx[2] = k | (1ull << A.a);
         idx[3] = k | (1ull << A.a) | (1ull << A.b);
     }
+#ifdef SV_DEBUG_BOUNDS
+    for (int i = 0; i < sweep_nidx(KIND); ++i) idx[i] = SV_GIDX(idx[i], A.dim);
+#endif
 }
 
 // One gate over the whole state: thread t handles reduced index t (two
@@ -181,7 +185,7 @@ __global__ __launch_bounds__(SWEEP_TPB) void k_sweep(V2<R> *__restrict__ psi, ui
     const uint64_t t = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x;
     if (t >= threads) return;
     if constexpr (MODE == SWM_PAIR) {
-        const uint64_t k = expand(t, in);  // bit 0 inserted as 0: the pair is (k, k + 1)
+        const uint64_t k = SV_GIDX(expand(t, in), A.dim);  // bit 0 inserted as 0: the pair is (k, k + 1)
         V2<R> v[2];
         sw_ld2<NT>(psi + k, v[0], v[1]);
         sweep_apply<KIND, R>(v, k, A);
@@ -339,8 +343,8 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uin
             if (q < nacc) {
                 const uint32_t j = q * EPA;
                 const uint64_t off = hi_off[j >> l] | (j & lowm);
-                x[a] = *reinterpret_cast<const PT *>(it.psi + (it.bv | off));
-                if (two) y[a] = *reinterpret_cast<const PT *>(it.psi + (it.bw | off));
+                x[a] = *reinterpret_cast<const PT *>(it.psi + SV_GIDX(it.bv | off, dim));
+                if (two) y[a] = *reinterpret_cast<const PT *>(it.psi + SV_GIDX(it.bw | off, dim));
             }
         }
     };
@@ -362,11 +366,11 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uin
             const uint32_t q = threadIdx.x + (uint32_t)a * TILE_TPB;
             if (q < nacc) {
                 const uint32_t j = q * EPA;
-                A[swz<R>(j)] = half(xc[a], 0);
-                if (two) B[swz<R>(j)] = half(yc[a], 0);
+                A[SV_LIDX(swz<R>(j), T)] = half(xc[a], 0);
+                if (two) B[SV_LIDX(swz<R>(j), T)] = half(yc[a], 0);
                 if constexpr (EPA == 2) {
-                    A[swz<R>(j + 1)] = half(xc[a], 1);
-                    if (two) B[swz<R>(j + 1)] = half(yc[a], 1);
+                    A[SV_LIDX(swz<R>(j + 1), T)] = half(xc[a], 1);
+                    if (two) B[SV_LIDX(swz<R>(j + 1), T)] = half(yc[a], 1);
                 }
             }
         }
@@ -378,9 +382,9 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uin
                 const uint32_t j = q * EPA;
                 const uint64_t off = hi_off[j >> l] | (j & lowm);
                 PT x, y;
-                const uint32_t s0 = swz<R>(plo[j & 63] ^ phi[j >> 6]);
+                const uint32_t s0 = SV_LIDX(swz<R>(plo[j & 63] ^ phi[j >> 6]), T);
                 if constexpr (EPA == 2) {
-                    const uint32_t s1 = swz<R>(plo[(j + 1) & 63] ^ phi[(j + 1) >> 6]);
+                    const uint32_t s1 = SV_LIDX(swz<R>(plo[(j + 1) & 63] ^ phi[(j + 1) >> 6]), T);
                     x = join(A[s0], A[s1]);
                     if (two) y = join(B[s0], B[s1]);
                 } else {
@@ -388,10 +392,10 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uin
                     if (two) y = join(B[s0], B[s0]);
                 }
                 if (two) {
-                    *reinterpret_cast<PT *>(cur.psi + (cur.bw | off)) = x;
-                    *reinterpret_cast<PT *>(cur.psi + (cur.bv | off)) = y;
+                    *reinterpret_cast<PT *>(cur.psi + SV_GIDX(cur.bw | off, dim)) = x;
+                    *reinterpret_cast<PT *>(cur.psi + SV_GIDX(cur.bv | off, dim)) = y;
                 } else {
-                    *reinterpret_cast<PT *>(cur.psi + (cur.bv | off)) = x;
+                    *reinterpret_cast<PT *>(cur.psi + SV_GIDX(cur.bv | off, dim)) = x;
                 }
             }
         }
@@ -674,7 +678,7 @@ __global__ __launch_bounds__(SWEEP_TPB) void k_sweep_shfl(V2<R> *__restrict__ ps
     const uint64_t t = (uint64_t)blockIdx.x * SWEEP_TPB + threadIdx.x;
     if (t >= threads) return;  // whole wavefronts only
     constexpr int W = sizeof(R) == 4 ? 2 : 1;
-    const uint64_t k = expand(t * W, in);
+    const uint64_t k = SV_GIDX(expand(t * W, in), A.dim);
     V2<R> own[W], par[W];
     if constexpr (W == 2) sw_ld2<true>(psi + k, own[0], own[1]);
     else own[0] = sw_ld1<true, R>(psi + k);
@@ -790,6 +794,7 @@ void sweep_one(Ctx *ctx, V2<R> *psi, int n, const Op &op) {
     A.op = to_dev<R>(op);
     A.a = op.a;
     A.b = op.b;
+    A.dim = 1ull << n;
     std::vector<int> cb = bits_of(op.cmask);
     switch (op.kind) {
     case OP_U1:
@@ -1185,6 +1190,26 @@ void set_zero_state(Ctx *ctx, void *psi, int n, int dtype) {
         hipLaunchKernelGGL(k_zero<double>, dim3(g), dim3(SWEEP_TPB), 0, ctx->stream, (V2<double> *)psi, dim);
     SV_HIP(hipGetLastError());
 }
+
+#ifdef SV_DEBUG_BOUNDS
+// Debug build: one thread forms index 1 of a one-element buffer; the check
+// replaces it by 0 (the store stays in bounds) and must raise the HBM flag.
+__global__ void k_debug_bounds_probe(unsigned int *p) { p[SV_GIDX(1, 1)] = 7u; }
+
+void debug_bounds_probe(Ctx *ctx) {
+    unsigned int *p = nullptr;
+    if (hipMalloc(&p, sizeof *p) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(SV_ENOMEM, "debug probe buffer");
+    }
+    (void)take_bound_flags();
+    hipLaunchKernelGGL(k_debug_bounds_probe, dim3(1), dim3(1), 0, ctx->stream, p);
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(p);
+    if (e != hipSuccess) fail(SV_EDEVICE, std::string("debug probe: ") + hipGetErrorString(e));
+    if (!(take_bound_flags() & 1u)) fail(SV_EDEVICE, "debug build: index checks do not report");
+}
+#endif
 
 void device_scale(Ctx *ctx, void *psi, int n, int dtype, double s) {
     const uint64_t dim = 1ull << n;

@@ -30,6 +30,15 @@ struct Error {
     std::string msg;
 };
 [[noreturn]] void fail(int code, const std::string &msg);
+// Debug kernel build (SV_DEBUG_BOUNDS): each translation unit with kernels
+// registers a reader that returns and clears its out-of-range flags
+// (bit 0: an HBM index, bit 1: an LDS index); the API reports them.
+bool register_bound_flag_reader(uint32_t (*reader)());
+uint32_t take_bound_flags();
+#ifdef SV_DEBUG_BOUNDS
+struct Ctx;
+void debug_bounds_probe(Ctx *ctx);  // at context creation: the checks must report
+#endif
 void set_last_error(const std::string &msg);
 
 #define SV_HIP(call)                                                          \

@@ -338,20 +338,20 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
             } else if (pairg) {
                 static_for<0, 8>([&](auto IC) {
                     constexpr int e = 2 * decltype(IC)::value;
-                    const P w = *reinterpret_cast<const P *>(gpsi + (k0 | goff4<e>(G)));
+                    const P w = *reinterpret_cast<const P *>(gpsi + SV_GIDX(k0 | goff4<e>(G), tc.dim));
                     v[e] = pair_lo(w);
                     v[e + 1] = pair_hi(w);
                 });
             } else {
                 static_for<0, 16>([&](auto EC) {
                     constexpr int e = decltype(EC)::value;
-                    v[e] = gpsi[k0 | goff4<e>(G)];
+                    v[e] = gpsi[SV_GIDX(k0 | goff4<e>(G), tc.dim)];
                 });
             }
         } else {
             static_for<0, 16>([&](auto EC) {
                 constexpr int e = decltype(EC)::value;
-                v[e] = tile[p0 ^ loffx4<e>(L)];
+                v[e] = tile[SV_LIDX(p0 ^ loffx4<e>(L), 1u << tc.m)];
             });
         }
         V2<R> acc;
@@ -468,18 +468,18 @@ __device__ __forceinline__ void h4_stage(V2<R> *tile, V2<R> *__restrict__ gpsi, 
             if (pairg) {
                 static_for<0, 8>([&](auto IC) {
                     constexpr int e = 2 * decltype(IC)::value;
-                    *reinterpret_cast<P *>(gpsi + (k0 | goff4<e>(G))) = pair_join(v[e], v[e + 1]);
+                    *reinterpret_cast<P *>(gpsi + SV_GIDX(k0 | goff4<e>(G), tc.dim)) = pair_join(v[e], v[e + 1]);
                 });
             } else {
                 static_for<0, 16>([&](auto EC) {
                     constexpr int e = decltype(EC)::value;
-                    gpsi[k0 | goff4<e>(G)] = v[e];
+                    gpsi[SV_GIDX(k0 | goff4<e>(G), tc.dim)] = v[e];
                 });
             }
         } else {
             static_for<0, 16>([&](auto EC) {
                 constexpr int e = decltype(EC)::value;
-                tile[p0 ^ loffx4<e>(L)] = v[e];
+                tile[SV_LIDX(p0 ^ loffx4<e>(L), 1u << tc.m)] = v[e];
             });
         }
         if constexpr (ONE) break;

@@ -40,6 +40,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
     tc.zero = from_zero != 0;
     tc.paux = aux32;
     tc.mtab = mtab;
+    tc.dim = dim;
     const uint32_t nhi = 1u << (P.m - P.l);
     uint64_t *hi_off = reinterpret_cast<uint64_t *>(smem);
     tc.hi_off = (const SV_LDS uint64_t *)hi_off;
