@@ -620,7 +620,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="headline only")
-    ap.add_argument("--serving", type=int, default=600, help="serving sample size at 2x and in a burst (0 = skip)")
+    ap.add_argument("--serving", type=int, default=1000, help="serving sample size at 2x and in a burst (0 = skip)")
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain streaming kernel used to scale HBM byte counters")

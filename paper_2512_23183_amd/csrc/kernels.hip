@@ -281,6 +281,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uin
     }
     const uint64_t fmask = P.free_mask;
     const int nfp = P.nfp;
+    const int lt = __builtin_ctzll(ntiles);
     // the free bit pairs, as 32-bit words held in scalar registers (byte
     // loads inside the item loop would be vector loads, each waited out)
     uint32_t fpw[12];
@@ -321,17 +322,18 @@ __global__ __launch_bounds__(TILE_TPB) void k_perm(V2<R> *__restrict__ slab, uin
     };
     // the item's tiles; false when the partner tile's workgroup owns it
     auto meta = [&](uint64_t w, Item &it) __attribute__((always_inline)) {
-        const uint64_t c = w / ntiles, t = w - c * ntiles;
+        // ntiles is a power of two: shift and mask (a 64-bit division is a
+        // long scalar routine, run by every wave for every candidate item)
+        const uint64_t c = w >> lt, t = w & (ntiles - 1);
         it.psi = slab + c * dim;
         it.bv = deposit(t, fmask);
         it.bw = it.bv;
 #pragma unroll
         for (int i = 0; i < 24; ++i) {
-            if (i < nfp) {
-                const int a = (int)((fpw[i >> 2] >> (8 * (i & 3))) & 255u);
-                const int b = (int)((fpw[6 + (i >> 2)] >> (8 * (i & 3))) & 255u);
-                if (((it.bv >> a) ^ (it.bv >> b)) & 1) it.bw ^= (1ull << a) | (1ull << b);
-            }
+            if (i >= nfp) break;  // unrolled: the words stay in scalar registers
+            const int a = (int)((fpw[i >> 2] >> (8 * (i & 3))) & 255u);
+            const int b = (int)((fpw[6 + (i >> 2)] >> (8 * (i & 3))) & 255u);
+            if (((it.bv >> a) ^ (it.bv >> b)) & 1) it.bw ^= (1ull << a) | (1ull << b);
         }
         return it.bw >= it.bv;
     };

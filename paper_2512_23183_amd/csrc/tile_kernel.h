@@ -67,8 +67,9 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
     const int sb = P.stage_begin, se = P.stage_end;
     __syncthreads();
     const uint64_t nw = (uint64_t)nc * ntiles;
+    const int lt = __builtin_ctzll(ntiles);
     for (uint64_t w = blockIdx.x; w < nw; w += gridDim.x) {
-        const uint64_t c = w / ntiles, t = w - c * ntiles;
+        const uint64_t c = w >> lt, t = w & (ntiles - 1);  // ntiles: a power of two
         tc.base = deposit(t, fmask);
         if (P.nlad) {
             // the tile's factor of every ladder: the phase of its fixed bits
