@@ -82,6 +82,8 @@ void apply_config(Ctx *ctx, const sv_config *cfg) {
     };
     pick(cfg->tile_bits_c64, 6, TILE_MAX[SV_C64], ctx->tile_bits[SV_C64]);
     pick(cfg->tile_bits_c128, 6, TILE_MAX[SV_C128], ctx->tile_bits[SV_C128]);
+    pick(cfg->tile_bits_layers_c64, 6, TILE_MAX[SV_C64], ctx->tile_bits_layers[SV_C64]);
+    pick(cfg->tile_bits_layers_c128, 6, TILE_MAX[SV_C128], ctx->tile_bits_layers[SV_C128]);
     pick(cfg->expect_bits_c64, 6, EXPECT_MAX[SV_C64], ctx->expect_bits[SV_C64]);
     pick(cfg->expect_bits_c128, 6, EXPECT_MAX[SV_C128], ctx->expect_bits[SV_C128]);
     pick(cfg->perm_bits_c64, 6, PERM_MAX[SV_C64], ctx->perm_bits[SV_C64]);
@@ -115,6 +117,7 @@ void apply_ops(State *st, const std::vector<Op> &ops, uint32_t flags) {
     } else {
         PlanOptions po;
         po.tile_bits = ctx->tile_bits[st->dtype];
+        po.tile_bits_layers = ctx->tile_bits_layers[st->dtype];
         po.perm_bits = ctx->perm_bits[st->dtype];
         po.dense4 = st->dtype == SV_C64 && ctx->dense4;
         po.dense_force = ctx->dense_force;
@@ -229,6 +232,7 @@ PlanSummary plan_for(const sv_circuit *circuit, const double *params, size_t n_p
     apply_config(&opts, cfg);
     PlanOptions po;
     po.tile_bits = opts.tile_bits[dtype];
+    po.tile_bits_layers = opts.tile_bits_layers[dtype];
     po.perm_bits = opts.perm_bits[dtype];
     po.dense4 = dtype == SV_C64 && opts.dense4;
     po.dense_force = opts.dense_force;
@@ -498,6 +502,7 @@ int sv_apply_circuit_noalloc(sv_state *st, const sv_circuit *circuit, const doub
         void *block = noalloc_block(ctx->device);
         PlanOptions po;
         po.tile_bits = ctx->tile_bits[st->dtype];
+        po.tile_bits_layers = ctx->tile_bits_layers[st->dtype];
         po.perm_bits = ctx->perm_bits[st->dtype];
         po.dense4 = st->dtype == SV_C64 && ctx->dense4;
         po.dense_force = ctx->dense_force;
@@ -694,6 +699,8 @@ int sv_autotune(sv_ctx *ctx, int dtype, int n_qubits, const char *cache_path, sv
             std::memset(chosen, 0, sizeof *chosen);
             chosen->tile_bits_c64 = ctx->tile_bits[SV_C64];
             chosen->tile_bits_c128 = ctx->tile_bits[SV_C128];
+            chosen->tile_bits_layers_c64 = ctx->tile_bits_layers[SV_C64];
+            chosen->tile_bits_layers_c128 = ctx->tile_bits_layers[SV_C128];
             chosen->expect_bits_c64 = ctx->expect_bits[SV_C64];
             chosen->expect_bits_c128 = ctx->expect_bits[SV_C128];
             chosen->perm_bits_c64 = ctx->perm_bits[SV_C64];

@@ -407,6 +407,7 @@ void run_large_batched(Ctx *ctx, const BatchSpec &spec, const std::vector<int> &
         const int n = spec.circuits[G->cs[0]].n;
         PlanOptions po;
         po.tile_bits = ctx->tile_bits[spec.dtype];
+        po.tile_bits_layers = ctx->tile_bits_layers[spec.dtype];
         po.perm_bits = ctx->perm_bits[spec.dtype];
         G->plan = make_plan(n, spec.op_sets[kv.first.first], po);
         G->E = make_eplan(n, expect_tile_bits(ctx, spec.dtype), build_dev_terms(spec.hams[kv.first.second]));
@@ -566,6 +567,7 @@ void run_large_sequential(Ctx *ctx, const BatchSpec &spec, const std::vector<int
         } else {
             PlanOptions po;
             po.tile_bits = ctx->tile_bits[spec.dtype];
+            po.tile_bits_layers = ctx->tile_bits_layers[spec.dtype];
             po.perm_bits = ctx->perm_bits[spec.dtype];
             run_plan(ctx, &st, make_plan(bc.n, ops, po));
         }

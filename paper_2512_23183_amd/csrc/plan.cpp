@@ -438,9 +438,6 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
         return plan;
     }
 
-    const int m = std::min(opt.tile_bits, n);
-    const int l = std::min(opt.low_bits, m);
-
     // 1. absorb SWAPs into a relabelling
     std::vector<int> phys(n);
     std::iota(phys.begin(), phys.end(), 0);
@@ -517,47 +514,97 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
     }
 
     // 3. greedy tile passes with commutation-aware deferral
-    const uint64_t low = (l >= 64) ? ~0ull : (bit(l) - 1);
     std::vector<Op> rest = ops;
     std::vector<OpSets> rsets(rest.size());
     for (size_t i = 0; i < rest.size(); ++i) rsets[i] = sets_of(rest[i]);
-    while (!rest.empty()) {
-        Pass ps;
-        uint64_t S = low;
-        int nS = l;
+    // Circuits of uncontrolled one-qubit gates and diagonals only (layers of
+    // rotations and CZ / CP: the deep random circuits, the QFT) take their
+    // own tile width and search each pass's tile.  Elsewhere the search is
+    // not used: in a batched gradient a shifted circuit runs the whole pass
+    // of its shifted gate, so larger passes repeat more work, and passes of
+    // two-qubit mixing gates (the Trotter rotations) measured slower when
+    // denser.
+    bool layered = true;
+    for (const OpSets &st : rsets) {
+        if (st.diag) continue;
+        layered = layered && st.control == 0 && __builtin_popcountll(st.target) == 1;
+    }
+    for (const Op &o : rest) layered = layered && !(o.kind != OP_DIAG && o.kind != OP_LADDER && o.param);
+    const int m = std::min(layered && opt.tile_bits_layers > 0 ? opt.tile_bits_layers : opt.tile_bits, n);
+    const int l = std::min(opt.low_bits, m);
+    const uint64_t low = (l >= 64) ? ~0ull : (bit(l) - 1);
+    const uint64_t all = (n >= 64) ? ~0ull : (bit(n) - 1);
+    // One pass over the remaining ops in order: an op joins when no deferred
+    // op before it conflicts with it and (mixing ops) its target bits are in
+    // the tile, which grows to m bits in program order (grow) or is the
+    // fixed set S.  Returns the number of mixing ops that join; taken marks
+    // the joining ops.  Stops once every bit is blocked for mixing.
+    auto scan = [&](uint64_t &S, bool grow, std::vector<char> *taken) {
+        int nS = __builtin_popcountll(S), mixing = 0;
         uint64_t DT = 0, DC = 0, DZ = 0;
-        std::vector<Op> deferred;
-        std::vector<OpSets> dsets;
-        const uint64_t all = (n >= 64) ? ~0ull : (bit(n) - 1);
-        std::vector<char> taken(rest.size(), 0);
         for (size_t i = 0; i < rest.size(); ++i) {
-            const Op &o = rest[i];
             const OpSets &s = rsets[i];
             bool can;
             if (s.diag) can = (s.touch & DT) == 0;
             else can = (s.target & (DT | DC | DZ)) == 0 && (s.control & DT) == 0;
             if (can && !s.diag) {
-                uint64_t need = s.target & ~S;
-                int add = __builtin_popcountll(need);
-                if (nS + add <= m) { S |= need; nS += add; }
+                const uint64_t need = s.target & ~S;
+                const int add = __builtin_popcountll(need);
+                if (!grow) can = add == 0;
+                else if (nS + add <= m) { S |= need; nS += add; }
                 else can = false;
             }
             if (can) {
-                ps.ops.push_back(o);
-                taken[i] = 1;
+                if (taken) (*taken)[i] = 1;
+                if (!s.diag) ++mixing;
             } else {
-                deferred.push_back(o);
-                dsets.push_back(s);
                 if (s.diag) DZ |= s.touch;
                 else { DT |= s.target; DC |= s.control; }
-                // once every bit is blocked for mixing, nothing else can join
-                if ((DT & all) == all) {
-                    for (size_t j = i + 1; j < rest.size(); ++j) {
-                        deferred.push_back(rest[j]);
-                        dsets.push_back(rsets[j]);
+                if ((DT & all) == all) break;
+            }
+        }
+        return mixing;
+    };
+    while (!rest.empty()) {
+        Pass ps;
+        // the tile: grown in program order, then (layered circuits) improved
+        // by swapping one chosen bit (the low l stay) for an outside one
+        // while that lets more mixing ops join the pass (diagonals never
+        // need the tile)
+        uint64_t S = low;
+        int best = scan(S, true, nullptr);
+        if (layered && n > m && m > l) {
+            for (int round = 0; round < 32; ++round) {
+                int gain = 0;
+                uint64_t bestS = S;
+                for (int out = l; out < n; ++out) {
+                    if (!(S & bit(out))) continue;
+                    for (int in = l; in < n; ++in) {
+                        if (S & bit(in)) continue;
+                        uint64_t T = (S & ~bit(out)) | bit(in);
+                        const int c = scan(T, false, nullptr);
+                        if (c - best > gain) { gain = c - best; bestS = T; }
                     }
-                    break;
                 }
+                if (gain <= 0) break;
+                best += gain;
+                S = bestS;
+            }
+        }
+        std::vector<char> taken(rest.size(), 0);
+        {
+            uint64_t T = S;
+            scan(T, false, &taken);
+        }
+        int nS = __builtin_popcountll(S);
+        std::vector<Op> deferred;
+        std::vector<OpSets> dsets;
+        for (size_t i = 0; i < rest.size(); ++i) {
+            if (taken[i]) {
+                ps.ops.push_back(rest[i]);
+            } else {
+                deferred.push_back(rest[i]);
+                dsets.push_back(rsets[i]);
             }
         }
         // A pass of Hadamards and diagonals runs in four-bit stages: when

@@ -405,6 +405,7 @@ int sv_queue_create(sv_ctx *ctx_, size_t hbm_budget_bytes, sv_queue **out) {
         q->ctx->cu_count = ctx->cu_count;
         for (int d = 0; d < 2; ++d) {
             q->ctx->tile_bits[d] = ctx->tile_bits[d];
+            q->ctx->tile_bits_layers[d] = ctx->tile_bits_layers[d];
             q->ctx->expect_bits[d] = ctx->expect_bits[d];
             q->ctx->perm_bits[d] = ctx->perm_bits[d];
         }

@@ -165,6 +165,8 @@ struct Pass {
 
 struct PlanOptions {
     int tile_bits = 13;    // m
+    int tile_bits_layers = 0;  // m of layered circuits (only uncontrolled one-qubit
+                               // gates and diagonals; 0: tile_bits)
     int low_bits = 4;      // l: 128 B (complex64) / 256 B (complex128) contiguous runs
     int perm_bits = 11;    // tile width of permutation passes
     bool fuse = true;      // false: one sweep op per gate
@@ -296,6 +298,7 @@ struct Ctx {
     // gate tile passes, expectation passes, permutation passes
     // (ranges: TILE_MAX / EXPECT_MAX / PERM_MAX below, minimum 6)
     int tile_bits[2] = {12, 12};
+    int tile_bits_layers[2] = {12, 12};  // layered circuits (see PlanOptions)
     int expect_bits[2] = {13, 12};
     int perm_bits[2] = {12, 11};
     bool dense4 = true;  // complex64 circuits: MFMA stages for dense four-qubit runs

@@ -68,6 +68,36 @@ Gates tuning_circuit(int n) {
     return G;
 }
 
+// The gate-based QFT alone (a layered circuit: Hadamards and controlled
+// phases, the swaps become a relabelling).
+Gates qft_circuit(int n) {
+    Gates G;
+    for (int j = 0; j < n; ++j) {
+        G.add(SV_H, j);
+        for (int k = j + 1; k < n; ++k) G.add(SV_CP, k, j, M_PI / std::ldexp(1.0, k - j));
+    }
+    for (int j = 0; j < n / 2; ++j) G.add(SV_SWAP, j, n - 1 - j);
+    return G;
+}
+
+// Layers of U3 on every qubit and CZ on a matching that changes per layer
+// (q paired with q + 2^(l mod 3) within blocks of 2^(l mod 3 + 1)): the
+// rotation-layer passes, whose tiles the planner searches; eight layers.
+Gates layers_circuit(int n) {
+    Gates G;
+    for (int l = 0; l < 8; ++l) {
+        for (int q = 0; q < n; ++q) {
+            G.add(SV_U3, q, -1, 0.3 + 0.05 * q + l);
+            G.g.back().angle[1] = 0.7 + 0.03 * q;
+            G.g.back().angle[2] = 1.1 + 0.02 * q;
+        }
+        const int d = 1 << (l % 3);
+        for (int q = 0; q + d < n; ++q)
+            if ((q / d) % 2 == 0) G.add(SV_CZ, q, q + d);
+    }
+    return G;
+}
+
 // Layers of fixed dense gates: U3 on every qubit, CZ on (q, q + 1) for even
 // q, then RXX and RYY on alternating neighbour pairs, twice (the rotation
 // runs are what the planner may fuse into dense four-qubit blocks).
@@ -146,12 +176,13 @@ void autotune(Ctx *ctx, sv_ctx *ctx_, int dtype, int n_qubits, const char *cache
         std::string line;
         while (std::getline(in, line)) {
             if (line.compare(0, key.size() + 1, key + " ") != 0) continue;
-            int tb = 0, eb = 0, pb = 0, dn = 0;
-            if (std::sscanf(line.c_str() + key.size(), " tile=%d expect=%d perm=%d dense=%d", &tb, &eb, &pb, &dn) ==
-                    4 &&
-                tb >= 6 && tb <= TILE_MAX[dtype] && eb >= 6 && eb <= EXPECT_MAX[dtype] && pb >= 6 &&
-                pb <= PERM_MAX[dtype] && (dn == 0 || dn == 1)) {
+            int tb = 0, lb = 0, eb = 0, pb = 0, dn = 0;
+            if (std::sscanf(line.c_str() + key.size(), " tile=%d layers=%d expect=%d perm=%d dense=%d", &tb, &lb, &eb,
+                            &pb, &dn) == 5 &&
+                tb >= 6 && tb <= TILE_MAX[dtype] && lb >= 6 && lb <= TILE_MAX[dtype] && eb >= 6 &&
+                eb <= EXPECT_MAX[dtype] && pb >= 6 && pb <= PERM_MAX[dtype] && (dn == 0 || dn == 1)) {
                 ctx->tile_bits[dtype] = tb;
+                ctx->tile_bits_layers[dtype] = lb;
                 ctx->expect_bits[dtype] = eb;
                 ctx->perm_bits[dtype] = pb;
                 if (dtype == SV_C64) ctx->dense4 = dn == 1;
@@ -162,6 +193,8 @@ void autotune(Ctx *ctx, sv_ctx *ctx_, int dtype, int n_qubits, const char *cache
     if (!hit) {
         Gates G = tuning_circuit(n);
         const sv_circuit circ = G.circuit(n);
+        Gates GL = layers_circuit(n), GQ = qft_circuit(n);
+        const sv_circuit lcirc = GL.circuit(n), qcirc = GQ.circuit(n);
         std::vector<double> coeffs;
         std::string paulis;
         tuning_hamiltonian(n, coeffs, paulis);
@@ -176,6 +209,12 @@ void autotune(Ctx *ctx, sv_ctx *ctx_, int dtype, int n_qubits, const char *cache
         const int reps = n >= 26 ? 2 : 3;
         auto apply = [&] {
             if (sv_reset(st) != SV_OK || sv_apply_circuit(st, &circ, nullptr, 0) != SV_OK)
+                fail(SV_EDEVICE, std::string("tuning run: ") + sv_last_error());
+        };
+        // layered circuits (their own tile width): the QFT and U3 + CZ layers
+        auto apply_layers = [&] {
+            if (sv_reset(st) != SV_OK || sv_apply_circuit(st, &qcirc, nullptr, 0) != SV_OK ||
+                sv_apply_circuit(st, &lcirc, nullptr, 0) != SV_OK)
                 fail(SV_EDEVICE, std::string("tuning run: ") + sv_last_error());
         };
         auto expect = [&] {
@@ -201,6 +240,7 @@ void autotune(Ctx *ctx, sv_ctx *ctx_, int dtype, int n_qubits, const char *cache
             return pick;
         };
         const int best_tb = sweep(&ctx->tile_bits[dtype], TILE_MAX[dtype] - 3, TILE_MAX[dtype], apply);
+        const int best_lb = sweep(&ctx->tile_bits_layers[dtype], TILE_MAX[dtype] - 3, TILE_MAX[dtype], apply_layers);
         const int best_pb = sweep(&ctx->perm_bits[dtype], PERM_MAX[dtype] - 2, PERM_MAX[dtype], apply);
         const int best_eb = sweep(&ctx->expect_bits[dtype], EXPECT_MAX[dtype] - 3, EXPECT_MAX[dtype], expect);
         // complex64: dense four-qubit blocks on MFMA or the register stages,
@@ -223,7 +263,7 @@ void autotune(Ctx *ctx, sv_ctx *ctx_, int dtype, int n_qubits, const char *cache
         }
         if (cache_path && *cache_path) {
             std::ofstream out(cache_path, std::ios::app);
-            out << key << " tile=" << best_tb << " expect=" << best_eb << " perm=" << best_pb
+            out << key << " tile=" << best_tb << " layers=" << best_lb << " expect=" << best_eb << " perm=" << best_pb
                 << " dense=" << best_dn << "\n";
         }
     }

@@ -50,7 +50,8 @@ class _Config(ctypes.Structure):
     _fields_ = [("tile_bits_c64", ctypes.c_int32), ("tile_bits_c128", ctypes.c_int32),
                 ("expect_bits_c64", ctypes.c_int32), ("expect_bits_c128", ctypes.c_int32),
                 ("perm_bits_c64", ctypes.c_int32), ("perm_bits_c128", ctypes.c_int32),
-                ("dense_fuse", ctypes.c_int32), ("graph_batch", ctypes.c_int32)]
+                ("dense_fuse", ctypes.c_int32), ("graph_batch", ctypes.c_int32),
+                ("tile_bits_layers_c64", ctypes.c_int32), ("tile_bits_layers_c128", ctypes.c_int32)]
 
 
 class _PlanStats(ctypes.Structure):
@@ -262,9 +263,10 @@ class Context:
     def __init__(self, device: int = 0, tile_bits_c64: int = 0, tile_bits_c128: int = 0,
                  expect_bits_c64: int = 0, expect_bits_c128: int = 0,
                  perm_bits_c64: int = 0, perm_bits_c128: int = 0, dense_fuse: int = 0,
-                 graph_batch: int = 0):
+                 graph_batch: int = 0, tile_bits_layers_c64: int = 0, tile_bits_layers_c128: int = 0):
         cfg = _Config(tile_bits_c64, tile_bits_c128, expect_bits_c64, expect_bits_c128,
-                      perm_bits_c64, perm_bits_c128, dense_fuse, graph_batch)
+                      perm_bits_c64, perm_bits_c128, dense_fuse, graph_batch,
+                      tile_bits_layers_c64, tile_bits_layers_c128)
         h = _vp()
         _check(lib().sv_init(ctypes.byref(h), device, ctypes.byref(cfg)))
         self.h = h

@@ -438,15 +438,16 @@ def test_autotune_picks_valid_widths_and_caches(sv, tmp_path):
     try:
         first = c.autotune(C64, 14, cache)
         assert 11 <= first["tile_bits_c64"] <= 14 and 11 <= first["expect_bits_c64"] <= 14
+        assert 11 <= first["tile_bits_layers_c64"] <= 14
         assert 10 <= first["perm_bits_c64"] <= 12
         assert first["dense_fuse"] in (1, -1)
         lines = open(cache).read().splitlines()
-        assert len(lines) == 1 and "dtype0 n14" in lines[0] and " dense=" in lines[0]
+        assert len(lines) == 1 and "dtype0 n14" in lines[0] and " dense=" in lines[0] and " layers=" in lines[0]
         second = c.autotune(C64, 14, cache)        # cache hit: same widths, no new line
         assert second == first
         assert len(open(cache).read().splitlines()) == 1
         tuned = c.autotune(C128, 13)
-        assert 9 <= tuned["tile_bits_c128"] <= 12
+        assert 9 <= tuned["tile_bits_c128"] <= 12 and 9 <= tuned["tile_bits_layers_c128"] <= 12
         # the tuned context still matches the oracle
         n = 14
         circ = I.random_circuit(n, 120, 31, n_params=4)

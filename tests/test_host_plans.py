@@ -36,13 +36,31 @@ def sv():
 
 
 def test_deep_circuit_plans_as_rotation_layers(sv):
+    # the planner searches the tile of each pass of a layered circuit
+    # (uncontrolled one-qubit gates and diagonals only): 35 passes at the
+    # default 12 bits where growing the tile in program order took 48
     c = I.deep_random_circuit(30, 40, 4)
     for dtype in (sv.C64, sv.C128):
         info = sv.plan_info(c, dtype=dtype)
-        assert info["tile_passes"] == 48 and info["perm_passes"] == 0
-        assert info["tile_passes_by_engine"] == [0, 0, 0, 0, 48]
+        assert info["tile_passes"] == 35 and info["perm_passes"] == 0
+        assert info["tile_passes_by_engine"] == [0, 0, 0, 0, 35]
         dump = sv.plan_dump(c, dtype=dtype)
         assert "acc=1" not in dump  # every diagonal folded into a table or a tile factor
+
+
+def test_layered_tile_width_and_search(sv):
+    # layered circuits take tile_bits_layers, others tile_bits; the search
+    # never takes fewer ops into a pass than growing the tile in program
+    # order, so a layered plan never has more passes at a wider tile
+    c = I.deep_random_circuit(24, 20, 9)
+    p12 = sv.plan_info(c, dtype=sv.C64, tile_bits_c64=10, tile_bits_layers_c64=12)["tile_passes"]
+    p10 = sv.plan_info(c, dtype=sv.C64, tile_bits_c64=12, tile_bits_layers_c64=10)["tile_passes"]
+    assert p12 < p10
+    hea = I.hea_circuit(20, 2)
+    prm = I.uniform_params(hea.n_params, 1)
+    a = sv.plan_info(hea, prm, dtype=sv.C64, tile_bits_c64=12, tile_bits_layers_c64=9)["tile_passes"]
+    b = sv.plan_info(hea, prm, dtype=sv.C64, tile_bits_c64=12, tile_bits_layers_c64=12)["tile_passes"]
+    assert a == b  # the ansatz (CNOTs, parameters) is not layered
 
 
 def test_forced_dense_block_widths(sv):
