@@ -171,9 +171,10 @@ typedef struct sv_config {
                                   launches and replay them as one hipGraph launch (the
                                   instantiated graph is reused while the batch keeps its
                                   shape); 0 = default (on), 1 = on, -1 = off */
-    int32_t tile_bits_layers_c64;  /* gate tile width of layered circuits (only uncontrolled
-                                      one-qubit gates and diagonals: rotation layers with CZ /
-                                      CP, the QFT), complex64: 6..14, 0 = default 12 */
+    int32_t tile_bits_layers_c64;  /* gate tile width of layered circuits (only fixed
+                                      uncontrolled one-qubit gates and diagonals, no merged CP
+                                      ladders: rotation layers with CZ / CP), complex64: 6..14,
+                                      0 = default 12 */
     int32_t tile_bits_layers_c128; /* same for complex128: 6..12, 0 = default 12 */
 } sv_config;
 

@@ -517,19 +517,20 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
     std::vector<Op> rest = ops;
     std::vector<OpSets> rsets(rest.size());
     for (size_t i = 0; i < rest.size(); ++i) rsets[i] = sets_of(rest[i]);
-    // Circuits of uncontrolled one-qubit gates and diagonals only (layers of
-    // rotations and CZ / CP: the deep random circuits, the QFT) take their
-    // own tile width and search each pass's tile.  Elsewhere the search is
-    // not used: in a batched gradient a shifted circuit runs the whole pass
-    // of its shifted gate, so larger passes repeat more work, and passes of
-    // two-qubit mixing gates (the Trotter rotations) measured slower when
-    // denser.
+    // Layered circuits -- fixed uncontrolled one-qubit gates and diagonals
+    // only, no CP ladders (layers of rotations with CZ / CP: the deep random
+    // circuits) -- take their own tile width and search each pass's tile.
+    // Elsewhere the search is not used: in a batched gradient a shifted
+    // circuit runs the whole pass of its shifted gate, so larger passes
+    // repeat more work; passes of two-qubit mixing gates (the Trotter
+    // rotations) measured slower when denser; the QFT's ladder passes gain
+    // nothing from it and prefer wider tiles than rotation layers.
     bool layered = true;
     for (const OpSets &st : rsets) {
         if (st.diag) continue;
         layered = layered && st.control == 0 && __builtin_popcountll(st.target) == 1;
     }
-    for (const Op &o : rest) layered = layered && !(o.kind != OP_DIAG && o.kind != OP_LADDER && o.param);
+    for (const Op &o : rest) layered = layered && o.kind != OP_LADDER && !(o.kind != OP_DIAG && o.param);
     const int m = std::min(layered && opt.tile_bits_layers > 0 ? opt.tile_bits_layers : opt.tile_bits, n);
     const int l = std::min(opt.low_bits, m);
     const uint64_t low = (l >= 64) ? ~0ull : (bit(l) - 1);

@@ -68,18 +68,6 @@ Gates tuning_circuit(int n) {
     return G;
 }
 
-// The gate-based QFT alone (a layered circuit: Hadamards and controlled
-// phases, the swaps become a relabelling).
-Gates qft_circuit(int n) {
-    Gates G;
-    for (int j = 0; j < n; ++j) {
-        G.add(SV_H, j);
-        for (int k = j + 1; k < n; ++k) G.add(SV_CP, k, j, M_PI / std::ldexp(1.0, k - j));
-    }
-    for (int j = 0; j < n / 2; ++j) G.add(SV_SWAP, j, n - 1 - j);
-    return G;
-}
-
 // Layers of U3 on every qubit and CZ on a matching that changes per layer
 // (q paired with q + 2^(l mod 3) within blocks of 2^(l mod 3 + 1)): the
 // rotation-layer passes, whose tiles the planner searches; eight layers.
@@ -193,8 +181,8 @@ void autotune(Ctx *ctx, sv_ctx *ctx_, int dtype, int n_qubits, const char *cache
     if (!hit) {
         Gates G = tuning_circuit(n);
         const sv_circuit circ = G.circuit(n);
-        Gates GL = layers_circuit(n), GQ = qft_circuit(n);
-        const sv_circuit lcirc = GL.circuit(n), qcirc = GQ.circuit(n);
+        Gates GL = layers_circuit(n);
+        const sv_circuit lcirc = GL.circuit(n);
         std::vector<double> coeffs;
         std::string paulis;
         tuning_hamiltonian(n, coeffs, paulis);
@@ -211,10 +199,9 @@ void autotune(Ctx *ctx, sv_ctx *ctx_, int dtype, int n_qubits, const char *cache
             if (sv_reset(st) != SV_OK || sv_apply_circuit(st, &circ, nullptr, 0) != SV_OK)
                 fail(SV_EDEVICE, std::string("tuning run: ") + sv_last_error());
         };
-        // layered circuits (their own tile width): the QFT and U3 + CZ layers
+        // layered circuits (their own tile width): U3 + CZ layers
         auto apply_layers = [&] {
-            if (sv_reset(st) != SV_OK || sv_apply_circuit(st, &qcirc, nullptr, 0) != SV_OK ||
-                sv_apply_circuit(st, &lcirc, nullptr, 0) != SV_OK)
+            if (sv_reset(st) != SV_OK || sv_apply_circuit(st, &lcirc, nullptr, 0) != SV_OK)
                 fail(SV_EDEVICE, std::string("tuning run: ") + sv_last_error());
         };
         auto expect = [&] {

@@ -61,6 +61,16 @@ def test_layered_tile_width_and_search(sv):
     a = sv.plan_info(hea, prm, dtype=sv.C64, tile_bits_c64=12, tile_bits_layers_c64=9)["tile_passes"]
     b = sv.plan_info(hea, prm, dtype=sv.C64, tile_bits_c64=12, tile_bits_layers_c64=12)["tile_passes"]
     assert a == b  # the ansatz (CNOTs, parameters) is not layered
+    qft = I.CircuitBuilder(24)
+    for j in range(24):
+        qft.add(I.H, [j])
+        for k in range(j + 1, 24):
+            qft.add(I.CP, [k, j], angles=[np.pi / 2 ** (k - j)])
+    q = qft.build(0)
+    a = sv.plan_info(q, dtype=sv.C64, tile_bits_c64=12, tile_bits_layers_c64=9)["tile_passes"]
+    b = sv.plan_info(q, dtype=sv.C64, tile_bits_c64=12, tile_bits_layers_c64=12)["tile_passes"]
+    c9 = sv.plan_info(q, dtype=sv.C64, tile_bits_c64=9, tile_bits_layers_c64=12)["tile_passes"]
+    assert a == b < c9  # the QFT's CP ladders follow the general width
 
 
 def test_forced_dense_block_widths(sv):
