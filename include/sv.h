@@ -419,16 +419,18 @@ int sv_profile_reset(sv_ctx *ctx);
 
 const char *sv_last_error(void);
 /*
- * Autotuner: times the gate tile width, then the permutation width, then the
- * expectation tile width of dtype on synthetic work of n_qubits qubits (a
- * gate-based QFT plus two RY/RZ + CNOT-ladder layers; a 2-local Pauli sum),
- * clamped to 8..28 qubits (27 for complex128), and keeps the fastest in ctx;
- * for complex64 it then times two layers of U3 + CZ with and without dense
- * four-qubit MFMA blocks (dense_fuse).
+ * Autotuner: times, for dtype on synthetic work of n_qubits qubits clamped
+ * to 8..30, the gate tile width (a gate-based QFT plus two RY/RZ +
+ * CNOT-ladder layers), the layered-circuit tile width (sixteen layers of U3
+ * on every qubit and CZ on a random matching), the permutation width and
+ * the expectation tile width (a 2-local Pauli sum), one at a time, and
+ * keeps the fastest in ctx; for complex64 it then times two layers of U3 +
+ * CZ + RXX / RYY with and without dense four-qubit MFMA blocks (dense_fuse).
  * cache_path (nullable): a text file with one line per device, dtype and
  * size; a valid line is used without timing, a new result is appended.
  * chosen (nullable) receives every width of ctx afterwards.  Needs a free
- * state of the clamped size in HBM; takes about a second at 28 qubits.
+ * state of the clamped size in HBM (16 GiB at 30 qubits complex128); takes
+ * about a second at 28 qubits complex64, a few at 30 complex128.
  */
 int sv_autotune(sv_ctx *ctx, int dtype, int n_qubits, const char *cache_path, sv_config *chosen);
 
