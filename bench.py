@@ -440,14 +440,18 @@ SERVE_N = (8, 24)
 SERVE_DEPTH = (2, 10)
 
 
-def bench_serving(ctx, sv, inputs, count, seed=5, serial_count=48, small_n=16, tick_budget=None):
+def bench_serving(ctx, sv, inputs, count, seed=5, serial_count=48, small_n=16, tick_budget=None, loads=None,
+                  progress=0):
     """Config 5's request mix (qubits 8..24, depth 2..10, 20-200 terms, half
     gradients, complex64) through the queue at 0.8x and 2x the serial rate
-    and in a burst.  The serial plain-GPU rate mu comes from the first
-    serial_count requests of the same list run one at a time; p50 / p99 are
-    reported over all requests and over those of at most small_n qubits."""
-    reqs = inputs.serving_requests(max(count, serial_count), seed, rate_per_s=0.0, n_range=SERVE_N,
-                                   depth_range=SERVE_DEPTH)
+    and in a burst (or the (load, count) pairs in loads).  The serial
+    plain-GPU rate mu comes from the first serial_count requests of the same
+    list run one at a time; p50 / p99 are reported over all requests and
+    over those of at most small_n qubits.  progress > 0 logs a line every
+    that many submissions and completions."""
+    # the generator is prefix-stable: the first serial_count requests of any
+    # longer list are these
+    reqs = inputs.serving_requests(serial_count, seed, rate_per_s=0.0, n_range=SERVE_N, depth_range=SERVE_DEPTH)
     t0 = time.perf_counter()
     for r in reqs[:serial_count]:
         if r.grad:
@@ -461,7 +465,10 @@ def bench_serving(ctx, sv, inputs, count, seed=5, serial_count=48, small_n=16, t
     mu = 1.0 / serial_dt
     out = {"serial_requests": serial_count, "serial_req_per_s": mu, "n_range": list(SERVE_N),
            "depth_range": list(SERVE_DEPTH), "small_n_max": small_n}
-    for load, cnt in ((0.8, min(count, 200)), (2.0, count), ("burst", count)):
+    if loads is None:
+        loads = ((0.8, min(count, 200)), (2.0, count), ("burst", count))
+    log(f"[bench] serving: serial rate {mu:.2f} requests/s over {serial_count} requests")
+    for load, cnt in loads:
         # burst: every request arrives at once (peak queue throughput)
         lam = 0.0 if load == "burst" else load * mu
         reqs = inputs.serving_requests(cnt, seed, rate_per_s=lam, n_range=SERVE_N, depth_range=SERVE_DEPTH)
@@ -475,10 +482,14 @@ def bench_serving(ctx, sv, inputs, count, seed=5, serial_count=48, small_n=16, t
             if r.arrival_s > now:
                 time.sleep(r.arrival_s - now)
             tickets.append(q.submit(r.circuit, r.params, r.hamiltonian, r.grad, sv.C64))
+            if progress and len(tickets) % progress == 0:
+                log(f"[bench] serving load {load}: {len(tickets)} submitted at {time.perf_counter() - t_start:.0f} s")
         lat = []
         for t in tickets:
             _, _, l = q.wait(t)
             lat.append(l)
+            if progress and len(lat) % progress == 0:
+                log(f"[bench] serving load {load}: {len(lat)} completed at {time.perf_counter() - t_start:.0f} s")
         total = time.perf_counter() - t_start
         st = q.stats()
         q.close()
@@ -621,11 +632,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--serving", type=int, default=1000, help="serving sample size at 2x and in a burst (0 = skip)")
+    ap.add_argument("--stream-requests", type=int, default=10000,
+                    help="requests of --only serving_stream (one stream at 2x the serial rate)")
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain streaming kernel used to scale HBM byte counters")
     ap.add_argument("--only", choices=["grad10", "grad20", "vqe10", "trotter", "deep30", "deep30_once",
-                                       "qft28_once", "deep30_dense4_once"],
+                                       "qft28_once", "deep30_dense4_once", "serving_stream"],
                     help="profiling aid: run only this extra (no headline) and print its record")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -660,6 +673,11 @@ def main():
             rec = bench_vqe(ctx, sv, inputs)
         elif args.only == "trotter":
             rec = bench_trotter(ctx, sv, inputs)
+        elif args.only == "serving_stream":
+            # config 5 at its stated length: 10k requests at twice the
+            # serial rate (about 12 minutes on one GPU)
+            rec = bench_serving(ctx, sv, inputs, args.stream_requests, loads=((2.0, args.stream_requests),),
+                                progress=1000)
         elif args.only == "deep30_once":
             # one fused application at complex128 (counter collection)
             c = inputs.deep_random_circuit(DEEP_N, DEEP_DEPTH, DEEP_SEED)

@@ -59,3 +59,16 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_serving_requests_are_prefix_stable():
+    # the serving bench takes the serial rate from a short list and runs the
+    # loads on longer ones: their first requests must be the same circuits
+    import numpy as np
+    from paper_2512_23183_amd import inputs as I
+    a = I.serving_requests(6, 5, rate_per_s=0.0, n_range=bench.SERVE_N, depth_range=bench.SERVE_DEPTH)
+    b = I.serving_requests(15, 5, rate_per_s=3.0, n_range=bench.SERVE_N, depth_range=bench.SERVE_DEPTH)
+    for x, y in zip(a, b):
+        assert x.circuit.n == y.circuit.n and x.grad == y.grad and x.circuit.n_gates == y.circuit.n_gates
+        assert np.array_equal(x.params, y.params)
+        assert np.array_equal(x.hamiltonian.coeffs, y.hamiltonian.coeffs)
