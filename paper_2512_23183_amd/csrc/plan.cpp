@@ -153,6 +153,84 @@ void finish_tile_pass(int n, Pass &ps, uint64_t S) {
     ps.l = run;
 }
 
+// Order the ops of a layered pass (uncontrolled one-qubit mixing ops and
+// diagonals) so that the four-bit stage builder, which closes a stage at a
+// fifth register bit, at a second mixing op on one bit, or at a mixing op
+// on a bit of a diagonal that follows a mixing op of the stage, forms few
+// stages.  Any topological order of the ops' conflict graph (two ops
+// conflict unless they act on disjoint bits or are both diagonal) is the
+// same product.  List scheduling: each stage first takes every diagonal
+// whose predecessors are placed, then up to four ready mixing ops (on
+// distinct bits by construction), those heading the longest chains of
+// mixing ops first, then program order.
+void order_layered_pass(std::vector<Op> &ops) {
+    const int N = (int)ops.size();
+    if (N < 3) return;
+    std::vector<OpSets> st(N);
+    for (int i = 0; i < N; ++i) st[i] = sets_of(ops[i]);
+    std::vector<std::vector<int>> succ(N);
+    std::vector<int> npred(N, 0);
+    std::vector<int> last_mix(64, -1);
+    std::vector<std::vector<int>> diags(64);
+    auto edge = [&](int a, int b) {
+        if (a < 0) return;
+        succ[a].push_back(b);
+        ++npred[b];
+    };
+    for (int j = 0; j < N; ++j) {
+        const uint64_t bits = st[j].touch;
+        if (st[j].diag) {
+            for (uint64_t m = bits; m; m &= m - 1) {
+                const int b = __builtin_ctzll(m);
+                edge(last_mix[b], j);
+                diags[b].push_back(j);
+            }
+        } else {
+            for (uint64_t m = bits; m; m &= m - 1) {
+                const int b = __builtin_ctzll(m);
+                edge(last_mix[b], j);
+                for (int d : diags[b]) edge(d, j);
+                diags[b].clear();
+                last_mix[b] = j;
+            }
+        }
+    }
+    // longest chain of mixing ops from each op (edges run forward)
+    std::vector<int> height(N, 0);
+    for (int j = N - 1; j >= 0; --j) {
+        int h = 0;
+        for (int k : succ[j]) h = std::max(h, height[k]);
+        height[j] = h + (st[j].diag ? 0 : 1);
+    }
+    std::vector<char> placed(N, 0);
+    std::vector<int> order;
+    order.reserve(N);
+    auto place = [&](int j) {
+        placed[j] = 1;
+        order.push_back(j);
+        for (int k : succ[j]) --npred[k];
+    };
+    while ((int)order.size() < N) {
+        for (int j = 0; j < N; ++j)
+            if (!placed[j] && st[j].diag && npred[j] == 0) place(j);
+        std::vector<int> ready;
+        for (int j = 0; j < N; ++j)
+            if (!placed[j] && !st[j].diag && npred[j] == 0) ready.push_back(j);
+        if (ready.empty()) {
+            if ((int)order.size() < N) return;  // cannot happen for a DAG; keep program order
+            break;
+        }
+        std::stable_sort(ready.begin(), ready.end(), [&](int a, int b) { return height[a] > height[b]; });
+        if (ready.size() > 4) ready.resize(4);
+        std::sort(ready.begin(), ready.end());
+        for (int j : ready) place(j);
+    }
+    std::vector<Op> out;
+    out.reserve(N);
+    for (int j : order) out.push_back(ops[j]);
+    ops.swap(out);
+}
+
 // ---------------------------------------------------------------------------
 // Dense four-bit blocks.  A run of consecutive fixed (parameter-free) ops
 // of a tile pass whose bits all lie in one set of at most four local bits
@@ -666,6 +744,7 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
         // pad the tile with the lowest unused bits (longer contiguous runs)
         for (int b = 0; b < n && nS < m; ++b)
             if (!(S & bit(b))) { S |= bit(b); ++nS; }
+        if (layered && opt.order_layers) order_layered_pass(ps.ops);
         finish_tile_pass(n, ps, S);
         if (ps.ops.empty()) fail(SV_EDEVICE, "internal: planner made no progress");
         if (opt.dense4 && ps.m >= 4) fuse_dense4(ps, plan, opt.dense_force);

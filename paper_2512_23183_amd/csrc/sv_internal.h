@@ -173,6 +173,7 @@ struct PlanOptions {
     bool dense4 = false;   // fuse runs of fixed gates on four bits into OP_DENSE4
     int dense_force = 0;   // 2..4: every run of >= 2 fixed gates on <= k bits becomes a
                            // block (padded to four bits), whatever its cost
+    bool order_layers = true;  // list-schedule the ops of layered passes into few stages
 };
 
 struct Plan {

@@ -43,6 +43,9 @@ def test_deep_circuit_plans_as_rotation_layers(sv):
     for dtype in (sv.C64, sv.C128):
         info = sv.plan_info(c, dtype=dtype)
         assert info["tile_passes"] == 35 and info["perm_passes"] == 0
+        # list-scheduled passes reach ceil(rotations / 4) stages in every
+        # pass (1200 rotations); program order took 336
+        assert info["stages"] == 313
         assert info["tile_passes_by_engine"] == [0, 0, 0, 0, 35]
         dump = sv.plan_dump(c, dtype=dtype)
         assert "acc=1" not in dump  # every diagonal folded into a table or a tile factor
