@@ -744,7 +744,9 @@ Plan make_plan(int n, const std::vector<Op> &ops_in, const PlanOptions &opt) {
         // pad the tile with the lowest unused bits (longer contiguous runs)
         for (int b = 0; b < n && nS < m; ++b)
             if (!(S & bit(b))) { S |= bit(b); ++nS; }
-        if (layered && opt.order_layers) order_layered_pass(ps.ops);
+        // (forced dense blocks take runs of consecutive ops: they keep the
+        // program order, whose runs stay on few bits)
+        if (layered && opt.order_layers && opt.dense_force == 0) order_layered_pass(ps.ops);
         finish_tile_pass(n, ps, S);
         if (ps.ops.empty()) fail(SV_EDEVICE, "internal: planner made no progress");
         if (opt.dense4 && ps.m >= 4) fuse_dense4(ps, plan, opt.dense_force);
