@@ -124,7 +124,7 @@ def roofline_block(S, prof, kernel, steps_passes=None):
 
 
 def bench_deep_headline(ctx, sv, inputs, args, tuned, dtype=None):
-    """Config 4 (30 qubits, depth 40) at complex128: reset + fused apply per
+    """The deep random circuit (30 qubits, depth 40) at complex128: reset + fused apply per
     step on a resident state."""
     dtype = sv.C128 if dtype is None else dtype
     n = DEEP_N
@@ -363,7 +363,7 @@ def bench_deep30_blocks(sv, c, n):
 
 
 def bench_vqe(ctx, sv, inputs):
-    """Config-1 VQE at the paper's optimiser settings (Adam, lr 1e-2, at most
+    """VQE of the 10-qubit XYZ chain at the paper's optimiser settings (Adam, lr 1e-2, at most
     350 iterations, tolerance 1e-7), one batched gradient per iteration."""
     c = inputs.hea_circuit(10, 4)
     ham = inputs.xyz_chain(10)
@@ -442,7 +442,7 @@ SERVE_DEPTH = (2, 10)
 
 def bench_serving(ctx, sv, inputs, count, seed=5, serial_count=48, small_n=16, tick_budget=None, loads=None,
                   progress=0):
-    """Config 5's request mix (qubits 8..24, depth 2..10, 20-200 terms, half
+    """The serving request mix (qubits 8..24, depth 2..10, 20-200 terms, half
     gradients, complex64) through the queue at 0.8x and 2x the serial rate
     and in a burst (or the (load, count) pairs in loads).  The serial
     plain-GPU rate mu comes from the first serial_count requests of the same
@@ -674,7 +674,7 @@ def main():
         elif args.only == "trotter":
             rec = bench_trotter(ctx, sv, inputs)
         elif args.only == "serving_stream":
-            # config 5 at its stated length: 10k requests at twice the
+            # the full-length stream: 10k requests at twice the
             # serial rate (about 12 minutes on one GPU)
             rec = bench_serving(ctx, sv, inputs, args.stream_requests, loads=((2.0, args.stream_requests),),
                                 progress=1000)

@@ -35,7 +35,7 @@ namespace sv {
 
 namespace {
 
-constexpr int EXPT_TPB = 512;  // 8 waves share a tile's groups (256: 16% slower at config 3)
+constexpr int EXPT_TPB = 512;  // 8 waves share a tile's groups (256: 16% slower on the 20-qubit 641-circuit gradient)
 constexpr int EXPT_WAVES = EXPT_TPB / 64;
 constexpr int EXPT_CHUNK = ESUM_CHUNK;  // terms per register block
 constexpr int EXPT_SLOT_CAP = 1024;  // terms per pass (LDS accumulators)

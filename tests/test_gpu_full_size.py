@@ -28,7 +28,7 @@ properties that hold at any size.
     vector (relative L2 <= 2 x the complex64 amplitude bound, each side
     being within it of the exact state), on 4096 sampled amplitudes, and on
     <Z_a Z_b> / <X_a X_b> expectations (<= 1e-5).
-  * The config-3 gradient (20 qubits, 8 layers, 641 circuits, 200 terms,
+  * The 20-qubit gradient (8 layers, 641 circuits, 200 terms,
     complex64): sampled components against the oracle's shifted energies
     (g_i = [E(theta + pi/2 e_i) - E(theta - pi/2 e_i)] / 2), <= 1e-5.
 """
@@ -214,7 +214,7 @@ def test_deep_random_30q_fused_vs_unfused(sv):
     assert np.max(np.abs(vf - vu)) <= 1e-5, (vf, vu)
 
 
-def test_config3_gradient_sampled_components(sv):
+def test_20q_641_circuit_gradient_sampled_components(sv):
     n = 20
     c = I.hea_circuit(n, 8)
     ham = I.random_2local(n, 200, 3)

@@ -306,7 +306,7 @@ def test_nonfinite_state_reports_enumeric(ctx, sv):
 # Parameter-shift gradients
 # ---------------------------------------------------------------------------
 
-def test_psr_config1_10q_c128(ctx):
+def test_psr_10q_xyz_chain_c128(ctx):
     n = 10
     c = I.hea_circuit(n, 4)
     ham = I.xyz_chain(n)
@@ -376,8 +376,8 @@ def test_psr_multipass_circuits(ctx, dtype):
     assert np.max(np.abs(g - g_ref)) <= tol
 
 
-def test_psr_config3_small_sample_c64(ctx):
-    # config-3 structure (RY/RZ + ladder, random 2-local) at a size the
+def test_psr_ansatz_random_2local_small_c64(ctx):
+    # the 20-qubit gradient's structure (RY/RZ + ladder, random 2-local) at a size the
     # oracle finishes quickly
     n = 12
     c = I.hea_circuit(n, 2)

@@ -23,7 +23,7 @@ def sv():
 
 
 @pytest.mark.parametrize("dtype,tol", [(C128, 1e-10), (C64, 1e-4)])
-def test_vqe_trajectory_matches_oracle_config1(sv, dtype, tol):
+def test_vqe_trajectory_matches_oracle_10q_xyz_chain(sv, dtype, tol):
     n = 10
     c = I.hea_circuit(n, 4)
     ham = I.xyz_chain(n)
@@ -40,7 +40,7 @@ def test_vqe_trajectory_matches_oracle_config1(sv, dtype, tol):
 
 
 def test_vqe_runs_to_the_cap_below_its_start_and_above_the_ground_energy(sv):
-    # config 1 at the paper's settings; exact ground energy of the chain
+    # the 10-qubit XYZ chain at the paper's settings; exact ground energy of the chain
     n = 10
     c = I.hea_circuit(n, 4)
     ham = I.xyz_chain(n)

@@ -184,7 +184,7 @@ def test_xyz_chain_exact_diagonalisation():
     # expectation of the exact ground vector reproduces the lowest eigenvalue
     e, mi = oracle.energy(v[:, 0], ham)
     assert abs(e - e0) <= 1e-11 and mi <= 1e-12
-    # variational bound on the config-1 ansatz energy
+    # variational bound on the 10-qubit, 4-layer ansatz energy
     c = I.hea_circuit(n, 4)
     params = I.uniform_params(c.n_params, 1)
     e_theta = oracle.circuit_energy(c, params, ham)
