@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cassert>
 #include <numeric>
+#include <set>
 
 #include "sv_internal.h"
 
@@ -202,28 +203,39 @@ void order_layered_pass(std::vector<Op> &ops) {
         for (int k : succ[j]) h = std::max(h, height[k]);
         height[j] = h + (st[j].diag ? 0 : 1);
     }
-    std::vector<char> placed(N, 0);
-    std::vector<int> order;
+    // ready sets kept up to date as ops are placed: O((N + edges) log N)
+    std::vector<int> order, ready_diag;
     order.reserve(N);
+    std::set<std::pair<int, int>> ready_mix;  // (-height, index): longest chains first
+    auto enqueue = [&](int j) {
+        if (st[j].diag) ready_diag.push_back(j);
+        else ready_mix.insert({-height[j], j});
+    };
+    for (int j = 0; j < N; ++j)
+        if (npred[j] == 0) enqueue(j);
     auto place = [&](int j) {
-        placed[j] = 1;
         order.push_back(j);
-        for (int k : succ[j]) --npred[k];
+        for (int k : succ[j])
+            if (--npred[k] == 0) enqueue(k);
     };
     while ((int)order.size() < N) {
-        for (int j = 0; j < N; ++j)
-            if (!placed[j] && st[j].diag && npred[j] == 0) place(j);
-        std::vector<int> ready;
-        for (int j = 0; j < N; ++j)
-            if (!placed[j] && !st[j].diag && npred[j] == 0) ready.push_back(j);
-        if (ready.empty()) {
+        // every ready diagonal (placing one readies only mixing ops)
+        std::vector<int> diag_now;
+        diag_now.swap(ready_diag);
+        std::sort(diag_now.begin(), diag_now.end());
+        for (int j : diag_now) place(j);
+        if (ready_mix.empty()) {
             if ((int)order.size() < N) return;  // cannot happen for a DAG; keep program order
             break;
         }
-        std::stable_sort(ready.begin(), ready.end(), [&](int a, int b) { return height[a] > height[b]; });
-        if (ready.size() > 4) ready.resize(4);
-        std::sort(ready.begin(), ready.end());
-        for (int j : ready) place(j);
+        // then up to four ready mixing ops, in program order
+        std::vector<int> take;
+        while (!ready_mix.empty() && take.size() < 4) {
+            take.push_back(ready_mix.begin()->second);
+            ready_mix.erase(ready_mix.begin());
+        }
+        std::sort(take.begin(), take.end());
+        for (int j : take) place(j);
     }
     std::vector<Op> out;
     out.reserve(N);

@@ -147,3 +147,15 @@ def test_host_driver_under_sanitizers():
     assert r.returncode == 0 and "ERROR: AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr, \
         r.stderr[-4000:]
     assert "host plans 60" in r.stdout
+
+
+def test_deep_small_circuit_plans_quickly(sv):
+    # one pass holds every op of a circuit no wider than its tile: the stage
+    # scheduler keeps its ready sets up to date instead of rescanning the
+    # pass per stage, so 12 qubits x 4000 layers (48000 rotations) plan fast
+    import time
+    c = I.deep_random_circuit(12, 4000, 3)
+    t0 = time.perf_counter()
+    info = sv.plan_info(c, dtype=sv.C128)
+    assert time.perf_counter() - t0 < 10.0
+    assert info["tile_passes"] == 1 and info["stages"] == 12 * 4000 // 4
