@@ -321,6 +321,47 @@ EPlanHost make_eplan(int n, int m_max, const DevTerms &dt) {
                 chosen.push_back(g);
                 break;
             }
+        } else {
+            // pad the greedy tile to m bits, then exchange one bit above the
+            // low ones for an outside bit while more of the remaining terms
+            // fit it (fewer passes over the states: each reads all of them)
+            for (int bit = 0; bit < n && __builtin_popcountll(S) < m; ++bit) S |= 1ull << bit;
+            auto fit = [&](uint64_t T) {
+                int c = 0;
+                for (int g : order)
+                    if (!done[g] && (gs[g].x & ~T) == 0) c += gs[g].e - gs[g].b;
+                return c;
+            };
+            int best = fit(S);
+            for (int round = 0; round < 32; ++round) {
+                int gain = 0;
+                uint64_t bestS = S;
+                for (int o = l0; o < n; ++o) {
+                    if (!((S >> o) & 1)) continue;
+                    for (int i = l0; i < n; ++i) {
+                        if ((S >> i) & 1) continue;
+                        const uint64_t T = (S & ~(1ull << o)) | (1ull << i);
+                        const int c = fit(T);
+                        if (c - best > gain) {
+                            gain = c - best;
+                            bestS = T;
+                        }
+                    }
+                }
+                if (gain <= 0) break;
+                best += gain;
+                S = bestS;
+            }
+            chosen.clear();
+            slots = 0;
+            for (int g : order) {
+                if (done[g]) continue;
+                const int cnt = gs[g].e - gs[g].b;
+                if ((gs[g].x & ~S) == 0 && slots + cnt <= EXPT_SLOT_CAP) {
+                    slots += cnt;
+                    chosen.push_back(g);
+                }
+            }
         }
         for (int bit = 0; bit < n && __builtin_popcountll(S) < m; ++bit) S |= 1ull << bit;
         std::vector<int> local, freeb;
