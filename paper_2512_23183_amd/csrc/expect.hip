@@ -333,7 +333,11 @@ EPlanHost make_eplan(int n, int m_max, const DevTerms &dt) {
                 return c;
             };
             int best = fit(S);
-            for (int round = 0; round < 32; ++round) {
+            // each round costs (remaining groups) x (tile bits) x (outside
+            // bits) containment tests: skipped for very large Pauli sums
+            const bool search = (uint64_t)remaining * (uint64_t)std::max(0, m - l0) * (uint64_t)std::max(0, n - m) <=
+                                (1u << 20);
+            for (int round = 0; search && round < 32; ++round) {
                 int gain = 0;
                 uint64_t bestS = S;
                 for (int o = l0; o < n; ++o) {
